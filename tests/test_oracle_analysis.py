@@ -1,0 +1,119 @@
+"""Pins of the spectral and correlation statistics (Sec. 5.3-5.4, Eqs. 5.5-5.13)
+against closed forms and brute force.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle import analysis
+
+
+def _grid(M, L):
+    dx = L / M
+    c = (np.arange(M) + 0.5) * dx
+    Y, X = np.meshgrid(c, c, indexing="ij")
+    return X, Y
+
+
+def test_parseval():
+    rng = np.random.default_rng(1)
+    u = rng.normal(0, 1, (32, 32, 2))
+    uh = analysis.fourier_coefficients(u)
+    lhs = 0.5 * (np.abs(uh) ** 2).sum()
+    rhs = 0.5 * (u * u).sum(axis=2).mean()
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_single_mode_energy():
+    # u = U sin(2 pi m y / L) e_x  ->  E(m) = U^2 / 4, zero elsewhere
+    M, L, U, m = 64, 100.0, 1.7, 5
+    X, Y = _grid(M, L)
+    u = np.zeros((M, M, 2))
+    u[..., 0] = U * np.sin(2 * math.pi * m * Y / L)
+    E = analysis.energy_spectrum(u)
+    assert E[m - 1] == pytest.approx(U * U / 4, rel=1e-12)
+    E[m - 1] = 0
+    assert np.abs(E).max() < 1e-20
+
+
+def test_fft_matches_direct_dft():
+    M = 8
+    rng = np.random.default_rng(2)
+    u = rng.normal(0, 1, (M, M, 2))
+    uh = analysis.fourier_coefficients(u)
+    j = np.arange(M)
+    for (ky, kx) in [(0, 0), (1, 3), (7, 2), (4, 4)]:
+        ph = np.exp(-2j * math.pi * (ky * j[:, None] + kx * j[None, :]) / M)
+        direct = (u * ph[..., None]).sum((0, 1)) / M ** 2
+        assert np.abs(uh[ky, kx] - direct).max() < 1e-12
+
+
+def test_slope_fit_recovers_power_law():
+    k = np.arange(1, 33, dtype=np.float64)
+    E = 3.5 * k ** 0.8
+    alpha, C = analysis.slope_fit(E)
+    assert alpha == pytest.approx(0.8, abs=1e-12)
+    assert C == pytest.approx(1.0, rel=1e-12)
+    E = 2.0 * k ** -0.5
+    assert analysis.slope_fit(E)[0] == pytest.approx(-0.5, abs=1e-12)
+
+
+def test_grid_autocorrelation_fft_equals_bruteforce():
+    rng = np.random.default_rng(3)
+    u = rng.normal(0, 1, (12, 12, 2))
+    a = analysis.grid_autocorrelation(u)
+    b = analysis.grid_autocorrelation_bruteforce(u)
+    assert np.abs(a - b).max() < 1e-12
+
+
+def test_vcf_single_mode_is_bessel_j0():
+    # an isotropic mixture is not needed: the angular average of cos(k . r)
+    # over directions is J0(|k| r); a plane wave along x with its rotated copy
+    # along y reproduces it up to the anisotropy of a two-direction average,
+    # so use many directions on a fine grid.
+    M, L = 256, 100.0
+    X, Y = _grid(M, L)
+    u = np.zeros((M, M, 2))
+    m = 3
+    k = 2 * math.pi * m / L
+    u[..., 0] = np.cos(k * X)
+    u[..., 1] = np.cos(k * Y)
+    r, g = analysis.vcf_grid(u, L, dr=L / M)
+    # two directions: g(r) = <cos(k r cos th) + cos(k r sin th)>_th / 2 = J0(k r)
+    sel = (r > 0) & (r < 0.25 * L)
+    assert np.nanmax(np.abs(g[sel] - special.j0(k * r[sel]))) < 0.05
+
+
+def test_vcf_iid_velocities_uncorrelated_and_bruteforce_agrees():
+    rng = np.random.default_rng(4)
+    L = 30.0
+    n = 900
+    pos = rng.uniform(0, L, (n, 2))
+    V = rng.normal(0, 1, (n, 2))
+    r, g, cnt = analysis.vcf_bruteforce(pos, V, L, dr=1.0)
+    assert g[0] == 1.0
+    assert np.abs(g[1:][cnt[1:] > 200]).max() < 0.2
+    # a velocity that is a smooth function of position is correlated at short range
+    V2 = np.stack([np.sin(2 * math.pi * pos[:, 0] / L), np.cos(2 * math.pi * pos[:, 1] / L)], 1)
+    r, g, cnt = analysis.vcf_bruteforce(pos, V2, L, dr=1.0)
+    assert g[1] > 0.9
+
+
+def test_integral_length_closed_form():
+    # g(r) = exp(-r / a) integrates to a (for L/2 >> a)
+    a = 2.0
+    r = np.linspace(0, 50, 5001)
+    g = np.exp(-r / a)
+    assert analysis.integral_length(r, g, L=100.0) == pytest.approx(a, rel=1e-4)
+    g = np.cos(math.pi * r / 10.0)   # first zero at r = 5: integral 10/pi
+    assert analysis.integral_length(r, g, L=100.0, to_first_zero=True) == pytest.approx(10 / math.pi, rel=1e-3)
+
+
+def test_agent_com_minimum_image():
+    L = 10.0
+    x = np.array([[9.9, 5.0], [0.3, 5.0]])
+    v = np.array([[1.0, 0.0], [3.0, 0.0]])
+    com, V = analysis.agent_com(x, v, L)
+    assert com[0] == pytest.approx([0.1, 5.0])
+    assert V[0] == pytest.approx([2.0, 0.0])

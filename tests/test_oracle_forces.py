@@ -1,0 +1,171 @@
+"""Pins of the oracle's force law against hand-evaluated closed forms, brute
+force and invariants (Sec. 2.1-2.3 of the paper).  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1310_0998_amd import inputs
+
+BASE = dict(n_agents=1, L=10.0, r_c=1.0, A=25.0, gamma=4.5, kT=1.0, kappa=1000.0,
+            bond_l=0.5, f_sp=1.0, gamma_s=0.5, mass=1.0, dt=0.005, seed=7)
+
+
+def test_conservative_force_hand_value(oracle_mod):
+    # r = r_c/2 along +x, A = 25: |f_C| = A (1 - r/r_c) = 12.5, pushing i away from j.
+    cfg = dict(BASE, gamma=0.0, kT=0.0)
+    f, parts, hit = oracle_mod.pair_force(cfg, [0.5, 0.0], [0.0, 0.0], 0.0)
+    assert hit
+    assert f == pytest.approx([12.5, 0.0], rel=1e-15, abs=1e-15)
+    # and along (3, 4)/5 at r = 0.25: w = 0.75, |f_C| = 18.75
+    f, _, _ = oracle_mod.pair_force(cfg, [0.15, 0.2], [0.0, 0.0], 0.0)
+    assert f == pytest.approx([18.75 * 0.6, 18.75 * 0.8], rel=1e-14)
+
+
+def test_dissipative_force_hand_value(oracle_mod):
+    # d = (0.3, 0.4): r = 0.5, e = (0.6, 0.8), w = 0.5; dv = (1, 2): g = 2.2
+    # f_D = -gamma w^2 g e = -4.5 * 0.25 * 2.2 * e = -2.475 e
+    cfg = dict(BASE, A=0.0, kT=0.0)
+    f, parts, hit = oracle_mod.pair_force(cfg, [0.3, 0.4], [1.0, 2.0], 0.0)
+    assert hit
+    assert parts[1] == pytest.approx([-1.485, -1.98], rel=1e-14)
+    assert f == pytest.approx([-1.485, -1.98], rel=1e-14)
+    # approaching particles (dv antiparallel to e) are pushed apart
+    f, _, _ = oracle_mod.pair_force(cfg, [0.3, 0.4], [-0.6, -0.8], 0.0)
+    assert f[0] > 0 and f[1] > 0
+
+
+def test_random_force_hand_value(oracle_mod):
+    # sigma = sqrt(2 gamma kT) = 3; |f_R| = sigma w alpha / sqrt(dt)
+    # = 3 * 0.5 * 0.7 / sqrt(0.005) = 14.849242404917499
+    cfg = dict(BASE, A=0.0)
+    f, parts, _ = oracle_mod.pair_force(cfg, [0.3, 0.4], [0.0, 0.0], 0.7)
+    assert parts[2] == pytest.approx([8.909545442950499, 11.879393923933999], rel=1e-14)
+
+
+def test_cutoff_is_strict_and_weight_vanishes(oracle_mod):
+    cfg = dict(BASE)
+    f, _, hit = oracle_mod.pair_force(cfg, [1.0, 0.0], [3.0, 0.0], 2.0)
+    assert not hit and f.tolist() == [0.0, 0.0]
+    f, _, hit = oracle_mod.pair_force(cfg, [0.0, 0.0], [1.0, 0.0], 2.0)
+    assert not hit and f.tolist() == [0.0, 0.0]
+    r = 1.0 - 1e-9
+    f, parts, hit = oracle_mod.pair_force(cfg, [r, 0.0], [0.0, 0.0], 0.0)
+    assert hit and abs(f[0]) < 25 * 1.1e-9
+
+
+def test_pair_force_antisymmetric_bitwise(oracle_mod):
+    rng = np.random.default_rng(3)
+    cfg = dict(BASE)
+    for _ in range(200):
+        d = rng.uniform(-0.7, 0.7, 2)
+        dv = rng.normal(0, 2, 2)
+        a = rng.normal()
+        f1, _, _ = oracle_mod.pair_force(cfg, d, dv, a)
+        f2, _, _ = oracle_mod.pair_force(cfg, -d, -dv, a)
+        assert (f1 == -f2).all()
+
+
+def _pairs_numpy(x, L, rc):
+    """Independent brute force: full distance matrix with minimum image."""
+    n = len(x)
+    d = x[:, None, :] - x[None, :, :]
+    d -= L * np.round(d / L)
+    r2 = (d * d).sum(-1)
+    i, j = np.nonzero((r2 > 0) & (r2 < rc * rc))
+    keep = (i < j) & (j != (i ^ 1))
+    return np.stack([i[keep], j[keep]], 1)
+
+
+@pytest.mark.parametrize("L,rc,n_agents,kind", [
+    (3.0, 1.0, 6, "random"), (4.0, 1.0, 20, "random"), (5.5, 1.0, 30, "random"),
+    (7.3, 1.1, 60, "edge"), (8.0, 1.0, 64, "edge"), (3.2, 1.0, 40, "clustered"),
+    (40.0, 1.0, 800, "random"), (40.0, 1.0, 800, "edge"),
+])
+def test_cell_list_equals_bruteforce(oracle_mod, L, rc, n_agents, kind):
+    cfg = dict(BASE, L=L, r_c=rc, n_agents=n_agents, seed=11)
+    x, _ = inputs.initial_state(cfg, kind=kind)
+    x64 = x.astype(np.float64)
+    pb = oracle_mod.pairs(cfg, x64, "brute")
+    pc = oracle_mod.pairs(cfg, x64, "cells")
+    pn = _pairs_numpy(x64, L, rc)
+    pn = pn[np.lexsort((pn[:, 1], pn[:, 0]))]
+    assert pb.shape == pn.shape and (pb == pn).all()
+    assert pc.shape == pb.shape and (pc == pb).all()
+    # forces by both routes are bit-identical (same sorted partner order)
+    v = np.random.default_rng(5).normal(0, 1, x.shape)
+    Fb = oracle_mod.forces(cfg, x64, v, 3, "brute")
+    Fc = oracle_mod.forces(cfg, x64, v, 3, "cells")
+    assert (Fb == Fc).all()
+
+
+def test_pairs_at_cutoff_plus_minus_ulp(oracle_mod):
+    # two agents whose heads sit at r_c -/+ 1 ulp (in FP64) apart
+    L, rc = 6.0, 1.0
+    cfg = dict(BASE, L=L, r_c=rc, n_agents=2)
+    lo = np.nextafter(1.0, 0.0)
+    hi = np.nextafter(1.0, 2.0)
+    for sep, expect in ((lo, 1), (1.0, 0), (hi, 0)):
+        x = np.array([[0.0, 3.0], [0.0, 2.0], [sep, 3.0], [sep, 4.0]])
+        p = oracle_mod.pairs(cfg, x, "brute")
+        heads = [tuple(q) for q in p.tolist()]
+        assert ((0, 2) in heads) == bool(expect)
+        assert (oracle_mod.pairs(cfg, x, "cells") == p).all()
+
+
+def test_total_pair_force_cancels(oracle_mod):
+    # with f_sp = gamma_s = 0 the forces sum to zero (pairs and bonds antisymmetric)
+    cfg = dict(inputs.physics(inputs.WORKLOADS["dimers_1600"]), f_sp=0.0, gamma_s=0.0)
+    x, _ = inputs.initial_state(cfg)
+    v = inputs.thermal_velocities(3, len(x), 1.0, 1.0)
+    F = oracle_mod.forces(cfg, x, v, 17)
+    assert np.abs(F.sum(0)).max() < 1e-10 * np.abs(F).sum()
+
+
+def test_propulsion_and_stokes_sum(oracle_mod):
+    # sum_i F_i = f_sp sum_k n_k - gamma_s sum_i v_i  (pair and bond forces cancel)
+    cfg = dict(inputs.physics(inputs.WORKLOADS["dimers_1600"]), f_sp=1.3, gamma_s=0.7)
+    x, _ = inputs.initial_state(cfg)
+    v = inputs.thermal_velocities(4, len(x), 1.0, 1.0).astype(np.float64)
+    F = oracle_mod.forces(cfg, x, v, 2)
+    x64 = x.astype(np.float64)
+    d = x64[0::2] - x64[1::2]
+    d -= cfg["L"] * np.round(d / cfg["L"])
+    n = d / np.sqrt((d * d).sum(1))[:, None]
+    expect = cfg["f_sp"] * n.sum(0) - cfg["gamma_s"] * v.sum(0)
+    assert F.sum(0) == pytest.approx(expect, abs=1e-9)
+    # head-only split gives the same total
+    F2 = oracle_mod.forces(dict(cfg, sp_split=1), x, v, 2)
+    assert F2.sum(0) == pytest.approx(expect, abs=1e-9)
+
+
+def test_galilean_invariance(oracle_mod):
+    cfg = dict(inputs.physics(inputs.WORKLOADS["dimers_1600"]), gamma_s=0.0)
+    x, _ = inputs.initial_state(cfg)
+    v = inputs.thermal_velocities(5, len(x), 1.0, 1.0).astype(np.float64)
+    F1 = oracle_mod.forces(cfg, x, v, 9)
+    F2 = oracle_mod.forces(cfg, x, v + np.array([3.25, -1.5]), 9)
+    scale = np.abs(F1).max()
+    assert np.abs(F1 - F2).max() < 1e-12 * scale
+
+
+def test_bond_excluded_from_pair_forces(oracle_mod):
+    # an isolated dimer at rest, bond at rest length: no force at all
+    cfg = dict(BASE, n_agents=1, f_sp=0.0, L=10.0)
+    x = np.array([[5.0, 5.0], [5.5, 5.0]])
+    F = oracle_mod.forces(cfg, x, np.zeros((2, 2)), 0, "brute")
+    assert np.abs(F).max() < 1e-12
+    # stretched by 0.01: bond force kappa * 0.01 = 10 pulling the pair together
+    x = np.array([[5.0, 5.0], [5.51, 5.0]])
+    F = oracle_mod.forces(cfg, x, np.zeros((2, 2)), 0, "brute")
+    assert F[0] == pytest.approx([10.0, 0.0], rel=1e-9)
+    assert F[1] == pytest.approx([-10.0, 0.0], rel=1e-9)
+
+
+def test_force_parts_scale(oracle_mod):
+    cfg = inputs.physics(inputs.WORKLOADS["dimers_1600"])
+    x, v = inputs.initial_state(cfg, thermal=True)
+    parts, scale = oracle_mod.force_parts(cfg, x, v, 4)
+    F = oracle_mod.forces(cfg, x, v, 4)
+    assert (scale > 0).all()
+    assert (np.sqrt((F * F).sum(1)) <= scale * (1 + 1e-12)).all()
