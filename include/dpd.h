@@ -1,0 +1,185 @@
+/*
+ * dpd.h -- C ABI of the MI355X DPD engine for self-propelled soft-core
+ * dumbbells (Hinz, Panchenko, Kim & Fried, arXiv:1310.0998).
+ *
+ * The model (Sec. 2 of the paper): particle 2k is the head and 2k+1 the tail of
+ * agent k.  Each particle feels
+ *   - the DPD pair force f_C + f_D + f_R from every non-bonded particle within
+ *     r_c (Eqs. 2.2-2.4), with e = (r_i - r_j)/r, w = 1 - r/r_c and the random
+ *     number alpha^{ij} drawn from a counter-based generator keyed on
+ *     (min id, max id, step, seed), so that f_ij = -f_ji exactly;
+ *   - the harmonic bond V = kappa (r - l)^2 / 2 to its partner (Eq. 2.5), whose
+ *     other pair forces are switched off (Sec. 2.2);
+ *   - the self-propulsion f_sp n^k of its agent, n^k = (r_head - r_tail)/|...|
+ *     (Eqs. 2.6-2.7), split f_sp/2 per particle or all on the head;
+ *   - Stokes friction -gamma_s v (Eq. 2.6);
+ * in a 2-D periodic square box of side L, advanced by velocity-Verlet (Sec. 5):
+ *   u = v + dt/(2m) F;  x <- wrap(x + dt u);  F <- F(x, u, step + 1);
+ *   v = u + dt/(2m) F.
+ *
+ * Conventions for every entry point:
+ *   - Vector arrays are N x 2 FP32 (x0, y0, x1, y1, ...) in particle-id order,
+ *     N = 2 n_agents, contiguous, in device memory of the current HIP device.
+ *   - The caller owns every buffer and the workspace; the library allocates no
+ *     device memory and frees nothing it was given.
+ *   - All device work is enqueued on the stream given to dpd_create and is
+ *     asynchronous unless stated otherwise; outputs are valid once the stream
+ *     has been synchronised.  One handle per stream; a handle is not
+ *     thread-safe.
+ *   - Return value: DPD_OK (0) or a negative DPD_E* code; dpd_last_error gives
+ *     the message.  No exception crosses the ABI and the library never aborts.
+ *   - Device-side failures (non-finite state, a bonded partner beyond the
+ *     neighbour stencil, a velocity too large for the binned field) set a flag
+ *     that the next synchronising call (dpd_sync, dpd_get_state, dpd_forces,
+ *     dpd_get_cells, dpd_bin_velocity) reports.
+ */
+#ifndef DPD_H
+#define DPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPD_OK          0
+#define DPD_EINVAL     -1  /* bad argument or parameter                          */
+#define DPD_EWORKSPACE -2  /* workspace missing, misaligned or too small          */
+#define DPD_EHIP       -3  /* a HIP runtime call failed                           */
+#define DPD_ENONFINITE -4  /* a non-finite position, velocity or force appeared   */
+#define DPD_ESTATE     -5  /* call needs a state set by dpd_set_state first       */
+#define DPD_EBOND      -6  /* a bond grew longer than one cell width              */
+#define DPD_ERANGE     -7  /* a velocity exceeded the binned-field range          */
+
+/* Model and engine parameters; physics constants in the units of the caller
+ * (e.g. the nondimensional units of Sec. 3).  All fields are read once, by
+ * dpd_workspace_bytes / dpd_create / dpd_rng_words. */
+typedef struct dpd_params {
+    int64_t  n_agents;   /* agents, >= 1; particles N = 2 n_agents <= 2^30           */
+    double   L;          /* box side, exactly representable in FP32, >= 3 r_c         */
+    double   r_c;        /* pair cutoff (Eq. 2.2), > 0; cells per side n_c = floor(L/r_c) */
+    double   A;          /* conservative amplitude (Eq. 2.3), >= 0                    */
+    double   gamma;      /* pair friction (Eq. 2.3), >= 0                             */
+    double   kT;         /* thermal energy (Eq. 2.3), >= 0; sigma = sqrt(2 gamma kT)  */
+    double   kappa;      /* bond stiffness (Eq. 2.5), >= 0                            */
+    double   bond_l;     /* bond rest length (Eq. 2.5), >= 0                          */
+    double   f_sp;       /* total self-propulsion per agent (Eq. 2.6)                 */
+    double   gamma_s;    /* Stokes friction per particle (Eq. 2.6), >= 0              */
+    double   mass;       /* particle mass (Eq. 2.1), > 0                              */
+    double   dt;         /* time step, > 0                                            */
+    uint64_t seed;       /* key of the noise generator                                */
+    int32_t  noise_kind; /* 0: Gaussian alpha (Box-Muller); 1: uniform sqrt(3)(2u-1)  */
+    int32_t  rng_kind;   /* 0: Philox4x32-10 on (min id, max id, step, 0), key = seed;
+                            1: Philox2x32-10 on (min id, max id), key folds seed and step */
+    int32_t  sp_split;   /* 0: f_sp/2 on head and tail; 1: f_sp on the head only      */
+    int32_t  bin_M_max;  /* largest grid side dpd_bin_velocity will be asked for (0: 256) */
+    int32_t  tile;       /* pair-kernel tile side in cells (0: automatic)             */
+    int32_t  reserved[3];
+} dpd_params;
+
+typedef struct dpd_handle dpd_handle;
+
+/* Bytes of device workspace that dpd_create needs for these parameters.
+ * Returns DPD_EINVAL for invalid parameters (message via dpd_last_error(NULL)). */
+int dpd_workspace_bytes(const dpd_params* p, size_t* bytes);
+
+/* Validate p, carve `workspace` (device memory, 256-byte aligned, at least
+ * dpd_workspace_bytes bytes, owned by the caller and kept alive until
+ * dpd_destroy) and bind the handle to `stream` (a hipStream_t; NULL = the null
+ * stream).  Enqueues the clearing of internal counters on the stream.
+ * Errors: DPD_EINVAL, DPD_EWORKSPACE, DPD_EHIP. */
+int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
+               dpd_handle** out);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+void dpd_destroy(dpd_handle* h);
+
+/* Message of the last failure on h, or of the last failed call without a
+ * handle when h is NULL.  Never NULL. */
+const char* dpd_last_error(const dpd_handle* h);
+
+/* Set the state at `step` from x (positions in [0, L)^2; values outside are
+ * wrapped) and v, both device N x 2 FP32 in id order.  If F is NULL the force
+ * F(x, v, step) is evaluated (Eqs. 2.1-2.7 with the velocity v); otherwise F
+ * (device N x 2, id order) is taken as the force of that state, which makes a
+ * checkpoint taken with dpd_get_state resume bit-exactly.
+ * Errors: DPD_EINVAL (NULL pointers), DPD_EHIP; non-finite inputs are reported
+ * by the next synchronising call as DPD_ENONFINITE. */
+int dpd_set_state(dpd_handle* h, const float* x, const float* v, int64_t step,
+                  const float* F);
+
+/* Copy the state out in id order: x, v, F device N x 2 FP32 (any may be NULL),
+ * *step (host, may be NULL).  Synchronises the stream.
+ * Errors: DPD_ESTATE, DPD_EHIP, device flags. */
+int dpd_get_state(dpd_handle* h, float* x, float* v, float* F, int64_t* step);
+
+/* Force F(x, v, step) of the current state (pair + bond + propulsion + Stokes,
+ * velocity-dependent terms with the stored v), device N x 2 FP32, id order.
+ * Does not change the state.  Synchronises the stream.
+ * Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP, device flags. */
+int dpd_forces(dpd_handle* h, float* F_out);
+
+/* Advance n_steps >= 0 velocity-Verlet steps (Sec. 5), rebinning the cell list
+ * every step.  If reduce_every > 0 and pk_out != NULL, after every
+ * reduce_every-th step the FP64 totals (P_x, P_y, KE) = (sum m v_x, sum m v_y,
+ * sum m |v|^2 / 2) are written to device pk_out[3 r .. 3 r + 2], r = 0, 1, ...
+ * (pk_out holds 3 * floor(n_steps / reduce_every) doubles).  Asynchronous.
+ * Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP. */
+int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_out);
+
+/* Filtered and projected velocity field u_M (Sec. 5.4, Eqs. 5.8-5.10) of the
+ * current state on an M x M grid (1 <= M <= bin_M_max), grid points
+ * x_M = ((i + 1/2) L/M, (j + 1/2) L/M).  A contributor at x belongs to grid
+ * point (i, j) iff the minimum-image d = x - x_M has both components in
+ * [-eps/2, eps/2); eps <= 0 means non-overlapping bins of side L/M, each grid
+ * point owning [i L/M, (i+1) L/M) x [j L/M, (j+1) L/M).  mode 0: particles and
+ * their velocities; mode 1: agent centres of mass (minimum-image midpoints)
+ * and (v_head + v_tail)/2.  u_out: device M*M*2 FP32, element (j*M + i)*2 + c,
+ * the mean velocity (0 where nothing contributes); n_out: device M*M int32
+ * contributor counts.  Sums are exact in 64-bit fixed point, so the result is
+ * independent of the order of contributions.  Synchronises the stream.
+ * Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP, DPD_ERANGE, device flags. */
+int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode,
+                     float* u_out, int32_t* n_out);
+
+/* Wait for the stream and return the first device-side failure since the last
+ * synchronising call (clearing it), or DPD_OK. */
+int dpd_sync(dpd_handle* h);
+
+/* ---- diagnostics used by tests and the benchmark --------------------------- */
+
+/* The cell list of the current state: cell_start_out device int32[n_c^2 + 1]
+ * (first slot of each cell, row-major cells cy * n_c + cx with
+ * c = min(n_c - 1, floor(x * n_c / L)) per axis in FP64), ids_out device
+ * int32[N] (particle ids ordered by (cell, id)).  Synchronises the stream. */
+int dpd_get_cells(dpd_handle* h, int32_t* cell_start_out, int32_t* ids_out);
+
+/* Cells per side of the cell list for p (n_c = floor(L / r_c)), or a negative
+ * error code. */
+int64_t dpd_cells_per_side(const dpd_params* p);
+
+/* The generator output for n pairs (i[k], j[k]) at `step` with p's seed,
+ * rng_kind and noise_kind: words_out device uint32[4 n] (unused words zero),
+ * alpha_out device float[n] (may be NULL).  i, j device int32[n].  Enqueued on
+ * `stream`; synchronises it. */
+int dpd_rng_words(const dpd_params* p, const int32_t* i, const int32_t* j, int64_t step,
+                  int32_t n, uint32_t* words_out, float* alpha_out, void* stream);
+
+/* Bracket every launch of the fused pair kernel with HIP events on the
+ * handle's stream (on != 0) or stop doing so (on == 0). */
+int dpd_set_profiling(dpd_handle* h, int32_t on);
+
+/* Total device time (ms) and number of launches of the fused pair kernel
+ * recorded since profiling was switched on.  Synchronises the stream. */
+int dpd_pair_kernel_time(dpd_handle* h, double* ms_total, int64_t* launches);
+
+/* Plain device-to-device copy of `bytes` (multiple of 16) by a simple
+ * streaming kernel, for calibrating hardware byte counters.  Enqueued on
+ * `stream`. */
+int dpd_copy_kernel(const void* src, void* dst, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPD_H */

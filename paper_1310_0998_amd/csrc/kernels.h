@@ -1,0 +1,712 @@
+// kernels.h -- HIP kernels of the DPD engine (gfx950).
+//
+// One step of the hot path runs four kinds of kernel on the caller's stream:
+//   k_pair<STEP>  fused: stage a tile of cells plus a one-cell halo in LDS,
+//                 DPD pair forces (Eqs. 2.2-2.4, bonded partner excluded),
+//                 bond + propulsion + Stokes (Eqs. 2.5-2.7), second half kick,
+//                 next step's half kick + drift + FP64 wrap, new cell key and
+//                 its atomic rank in the new cell;
+//   k_scan_*      exclusive scan of the per-cell counts -> cell_start;
+//   k_scatter     slot = cell_start[key] + rank;
+//   k_cell_sort   order every cell's members by particle id,
+// so that the particle order is always (cell, id), bit-identical to a plain
+// counting sort, and every sum below runs in a fixed order.
+#pragma once
+
+#include "device.h"
+
+namespace dpd {
+
+constexpr int kBlock = 256;                              // threads per block
+constexpr int kTileMax = 16;                             // tile side (cells)
+constexpr int kLocMax = (kTileMax + 2) * (kTileMax + 2); // tile + halo cells
+constexpr int kCap = 1024;                               // LDS particle slots
+
+enum PairMode { MODE_STEP = 0, MODE_FINAL = 1, MODE_FORCES = 2 };
+
+struct PairArgs {
+    const int* cs;      // cell_start of the current (cell, id) order
+    const int* src;     // sorted slot -> index in the input buffers
+    const float2* xin;
+    const float2* uin;  // velocity the forces use
+    const int* idin;
+    float2* xout;       // STEP: next position; FINAL/FORCES: position
+    float2* uout;       // STEP: next half-step velocity; FINAL: v; FORCES: input velocity
+    int* idout;
+    int* keyout;        // STEP: new cell key
+    int* rankout;       // STEP: rank of the particle within its new cell
+    int* count;         // STEP: per-cell counters (atomically incremented)
+    float2* Fout;       // FINAL/FORCES: total force
+    double* red;        // 3 doubles per tile (sum v_x, sum v_y, sum |v|^2) or null
+    unsigned* status;
+    uint32_t step;      // step number of the force evaluation (mod 2^32)
+};
+
+// ---- small helpers ----------------------------------------------------------
+
+__device__ __forceinline__ int wrap_cell(int c, int nc) {
+    c += (c < 0) ? nc : 0;
+    return c - ((c >= nc) ? nc : 0);
+}
+
+// Exclusive scan of vals[0..n) in LDS by a 256-thread block (n <= 512);
+// vals[n] receives the total, which is also returned.
+__device__ int block_scan_excl_512(int* vals, int n, int* s_wave) {
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    const int a = (2 * t < n) ? vals[2 * t] : 0;
+    const int b = (2 * t + 1 < n) ? vals[2 * t + 1] : 0;
+    const int s = a + b;
+    int incl = s;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) s_wave[w] = incl;
+    __syncthreads();
+    int wofs = 0;
+    for (int k = 0; k < w; ++k) wofs += s_wave[k];
+    const int total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    const int excl = wofs + incl - s;
+    if (2 * t < n) vals[2 * t] = excl;
+    if (2 * t + 1 < n) vals[2 * t + 1] = excl + a;
+    if (t == 0) vals[n] = total;
+    __syncthreads();
+    return total;
+}
+
+// Sum of three doubles over a 256-thread block in a fixed order; result valid
+// in thread 0.
+__device__ void block_sum3(double v[3], double (*s_red)[3]) {
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v[k] += __shfl_down(v[k], o, kWave);
+    }
+    if (lane == 0) {
+        s_red[w][0] = v[0]; s_red[w][1] = v[1]; s_red[w][2] = v[2];
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int k = 0; k < 3; ++k)
+            v[k] = ((s_red[0][k] + s_red[1][k]) + s_red[2][k]) + s_red[3][k];
+    }
+}
+
+// DPD pair force on i from j (Eqs. 2.2-2.4) added to (fx, fy); d = x_i - x_j
+// with 0 < |d|^2 < r_c^2 already established.  Every operation is symmetric
+// under (i, j, d) -> (j, i, -d), so the force on j is bitwise the negation.
+__device__ __forceinline__ void add_pair_force(const DevParams& P, float dx, float dy,
+                                               float r2, float2 ui, float2 uj, int idi,
+                                               int idj, uint32_t step, float& fx,
+                                               float& fy) {
+    const float rinv = rsqrtf(r2);
+    const float r = r2 * rinv;
+    const float w = 1.0f - r * P.inv_rc;
+    const float ex = dx * rinv, ey = dy * rinv;
+    const float g = (ui.x - uj.x) * ex + (ui.y - uj.y) * ey;
+    const uint32_t a = (uint32_t)min(idi, idj), b = (uint32_t)max(idi, idj);
+    const float alpha = alpha_from_words(P.noise_kind, pair_words2(P, a, b, step));
+    const float s = P.A * w - P.gamma * w * w * g + P.sigma_rdt * w * alpha;
+    fx += s * ex;
+    fy += s * ey;
+}
+
+// Bond to the partner (Eq. 2.5), propulsion along n = (r_head - r_tail)/|.|
+// (Eqs. 2.6-2.7) and Stokes friction (Eq. 2.6); d = x_i - x_partner.
+__device__ __forceinline__ void add_agent_force(const DevParams& P, float dx, float dy,
+                                                float2 ui, int idi, float& fx, float& fy) {
+    const float r = sqrtf(dx * dx + dy * dy);
+    const float rinv = 1.0f / r;
+    const float cb = -P.kappa * (r - P.bond_l) * rinv;
+    const float csp = ((idi & 1) ? -P.sp_tail : P.sp_head) * rinv;
+    fx += (cb + csp) * dx - P.gamma_s * ui.x;
+    fy += (cb + csp) * dy - P.gamma_s * ui.y;
+}
+
+// Finish one particle: kicks, drift, key and outputs at sorted slot g.
+template <int MODE>
+__device__ __forceinline__ void finish_particle(const DevParams& P, const PairArgs& a, int g,
+                                                float2 xi, float2 ui, int idi, float fx,
+                                                float fy, double rv[3], bool reduce) {
+    const float2 F = make_float2(fx, fy);
+    if (MODE == MODE_FORCES) {
+        a.xout[g] = xi;
+        a.uout[g] = ui;
+        a.idout[g] = idi;
+        a.Fout[g] = F;
+        if (!finite2(F)) atomicOr(a.status, kStatusNonFinite);
+        return;
+    }
+    const float2 v = make_float2(ui.x + P.h * fx, ui.y + P.h * fy);
+    if (reduce) {
+        rv[0] += (double)v.x;
+        rv[1] += (double)v.y;
+        rv[2] += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    }
+    if (MODE == MODE_FINAL) {
+        a.xout[g] = xi;
+        a.uout[g] = v;
+        a.idout[g] = idi;
+        a.Fout[g] = F;
+        if (!finite2(v) || !finite2(F)) atomicOr(a.status, kStatusNonFinite);
+        return;
+    }
+    const float2 un = make_float2(v.x + P.h * fx, v.y + P.h * fy);
+    const float2 xn = make_float2(drift_wrap(xi.x, un.x, P), drift_wrap(xi.y, un.y, P));
+    const int key = cell_key(xn, P);
+    const int rank = atomicAdd(&a.count[key], 1);
+    a.xout[g] = xn;
+    a.uout[g] = un;
+    a.idout[g] = idi;
+    a.keyout[g] = key;
+    a.rankout[g] = rank;
+    if (!finite2(xn) || !finite2(un)) atomicOr(a.status, kStatusNonFinite);
+}
+
+// Slow path for a tile whose cells hold more than kCap particles (dense
+// clusters): every particle reads its neighbours straight from global memory,
+// still in (cell, id) order.
+template <int MODE>
+__device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int cy0, int tw,
+                            int th, double rv[3], bool reduce) {
+    const int nc = P.nc;
+    for (int ic = threadIdx.x; ic < tw * th; ic += kBlock) {
+        const int gx = cx0 + ic % tw, gy = cy0 + ic / tw;
+        const int c = gy * nc + gx;
+        const int b = a.cs[c], e = a.cs[c + 1];
+        for (int g = b; g < e; ++g) {
+            const int p = a.src[g];
+            const float2 xi = a.xin[p], ui = a.uin[p];
+            const int idi = a.idin[p], pid = idi ^ 1;
+            float fx = 0.f, fy = 0.f;
+            bool found = false;
+            float pdx = 0.f, pdy = 0.f;
+            for (int oy = -1; oy <= 1; ++oy) {
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const int c2 = wrap_cell(gy + oy, nc) * nc + wrap_cell(gx + ox, nc);
+                    const int b2 = a.cs[c2], e2 = a.cs[c2 + 1];
+                    for (int g2 = b2; g2 < e2; ++g2) {
+                        if (g2 == g) continue;
+                        const int q = a.src[g2];
+                        const int idj = a.idin[q];
+                        const float2 xj = a.xin[q];
+                        const float dx = minimg_sub(xi.x, xj.x, P);
+                        const float dy = minimg_sub(xi.y, xj.y, P);
+                        if (idj == pid) {
+                            found = true;
+                            pdx = dx;
+                            pdy = dy;
+                            continue;
+                        }
+                        const float r2 = dx * dx + dy * dy;
+                        if (r2 < P.rc2 && r2 > 0.f)
+                            add_pair_force(P, dx, dy, r2, ui, a.uin[q], idi, idj, a.step, fx, fy);
+                    }
+                }
+            }
+            if (found) {
+                add_agent_force(P, pdx, pdy, ui, idi, fx, fy);
+            } else {
+                atomicOr(a.status, kStatusBond);
+                fx -= P.gamma_s * ui.x;
+                fy -= P.gamma_s * ui.y;
+            }
+            finish_particle<MODE>(P, a, g, xi, ui, idi, fx, fy, rv, reduce);
+        }
+    }
+}
+
+// The fused pair / agent / integrator kernel.  One 256-thread block per tile of
+// up to kTileMax x kTileMax cells; the tile and a one-cell halo are staged in
+// LDS in (cell, id) order, each thread then owns particles of the tile.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_pair(DevParams P, PairArgs a, int reduce) {
+    __shared__ int s_ofs[kLocMax + 1];
+    __shared__ int s_gbeg[kLocMax];
+    __shared__ int s_wave[kBlock / kWave];
+    __shared__ unsigned short s_lcell[kCap];
+    __shared__ float2 s_x[kCap];
+    __shared__ float2 s_u[kCap];
+    __shared__ int s_id[kCap];
+    __shared__ double s_red[kBlock / kWave][3];
+
+    // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs, so give
+    // each XCD a contiguous band of tiles (neighbouring halos share its L2).
+    const int nt = P.ntx * P.nty;
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7, kk = bid >> 3;
+    const int per = nt >> 3, rem = nt & 7;
+    const int t = xcd * per + min(xcd, rem) + kk;
+    const int tx = t % P.ntx, ty = t / P.ntx;
+    const int cx0 = tx * P.tile, cy0 = ty * P.tile;
+    const int tw = min(P.tile, P.nc - cx0), th = min(P.tile, P.nc - cy0);
+    const int W = tw + 2, H = th + 2, nloc = W * H;
+    const bool edge = (cx0 == 0) || (cx0 + tw >= P.nc) || (cy0 == 0) || (cy0 + th >= P.nc);
+
+    for (int lc = threadIdx.x; lc < nloc; lc += kBlock) {
+        const int gx = wrap_cell(cx0 - 1 + lc % W, P.nc);
+        const int gy = wrap_cell(cy0 - 1 + lc / W, P.nc);
+        const int c = gy * P.nc + gx;
+        const int b = a.cs[c], e = a.cs[c + 1];
+        s_ofs[lc] = e - b;
+        s_gbeg[lc] = b;
+    }
+    __syncthreads();
+    const int total = block_scan_excl_512(s_ofs, nloc, s_wave);
+
+    double rv[3] = {0.0, 0.0, 0.0};
+    if (total > kCap) {
+        tile_global<MODE>(P, a, cx0, cy0, tw, th, rv, reduce != 0);
+    } else {
+        for (int lc = threadIdx.x; lc < nloc; lc += kBlock)
+            for (int s = s_ofs[lc]; s < s_ofs[lc + 1]; ++s) s_lcell[s] = (unsigned short)lc;
+        __syncthreads();
+        for (int s = threadIdx.x; s < total; s += kBlock) {
+            const int lc = s_lcell[s];
+            const int p = a.src[s_gbeg[lc] + (s - s_ofs[lc])];
+            s_x[s] = a.xin[p];
+            s_u[s] = a.uin[p];
+            s_id[s] = a.idin[p];
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < total; s += kBlock) {
+            const int lc = s_lcell[s];
+            const int lx = lc % W, ly = lc / W;
+            if (lx < 1 || lx > tw || ly < 1 || ly > th) continue;  // halo
+            const float2 xi = s_x[s], ui = s_u[s];
+            const int idi = s_id[s], pid = idi ^ 1;
+            float fx = 0.f, fy = 0.f;
+            int jp = -1;
+            for (int r = 0; r < 3; ++r) {
+                const int row = (ly - 1 + r) * W;
+                const int j0 = s_ofs[row + lx - 1], j1 = s_ofs[row + lx + 2];
+                for (int j = j0; j < j1; ++j) {
+                    if (j == s) continue;
+                    const int idj = s_id[j];
+                    if (idj == pid) {
+                        jp = j;
+                        continue;
+                    }
+                    const float2 xj = s_x[j];
+                    float dx, dy;
+                    if (edge) {
+                        dx = minimg_sub(xi.x, xj.x, P);
+                        dy = minimg_sub(xi.y, xj.y, P);
+                    } else {
+                        dx = xi.x - xj.x;
+                        dy = xi.y - xj.y;
+                    }
+                    const float r2 = dx * dx + dy * dy;
+                    if (r2 < P.rc2 && r2 > 0.f)
+                        add_pair_force(P, dx, dy, r2, ui, s_u[j], idi, idj, a.step, fx, fy);
+                }
+            }
+            if (jp >= 0) {
+                const float2 xp = s_x[jp];
+                const float dx = edge ? minimg_sub(xi.x, xp.x, P) : xi.x - xp.x;
+                const float dy = edge ? minimg_sub(xi.y, xp.y, P) : xi.y - xp.y;
+                add_agent_force(P, dx, dy, ui, idi, fx, fy);
+            } else {
+                atomicOr(a.status, kStatusBond);
+                fx -= P.gamma_s * ui.x;
+                fy -= P.gamma_s * ui.y;
+            }
+            const int g = s_gbeg[lc] + (s - s_ofs[lc]);
+            finish_particle<MODE>(P, a, g, xi, ui, idi, fx, fy, rv, reduce != 0);
+        }
+    }
+    if (reduce) {
+        __syncthreads();
+        block_sum3(rv, s_red);
+        if (threadIdx.x == 0) {
+            a.red[3 * t + 0] = rv[0];
+            a.red[3 * t + 1] = rv[1];
+            a.red[3 * t + 2] = rv[2];
+        }
+    }
+}
+
+// ---- binning ------------------------------------------------------------------
+
+// Input state in id order -> buffer (x wrapped into the box, v, id) plus cell
+// key and atomic rank.
+__global__ void k_load_input(DevParams P, const float2* __restrict__ x, const float2* __restrict__ v,
+                             float2* xo, float2* uo, int* ido, int* key, int* rank, int* count,
+                             unsigned* status) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.N) return;
+    const float2 xi = x[i], vi = v[i];
+    if (!finite2(xi) || !finite2(vi)) atomicOr(status, kStatusNonFinite);
+    const float2 xw = make_float2(drift_wrap(xi.x, 0.f, P), drift_wrap(xi.y, 0.f, P));
+    const int k = cell_key(xw, P);
+    xo[i] = xw;
+    uo[i] = vi;
+    ido[i] = i;
+    key[i] = k;
+    rank[i] = atomicAdd(&count[k], 1);
+}
+
+// Positions (any order) -> cell key and atomic rank.
+__global__ void k_key_rank(DevParams P, const float2* __restrict__ x, int* key, int* rank,
+                           int* count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.N) return;
+    const int k = cell_key(x[i], P);
+    key[i] = k;
+    rank[i] = atomicAdd(&count[k], 1);
+}
+
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kBlock * kScanPer;  // cells per scan block
+
+// Pass 1: per-block sums of the counts; the last block to finish scans the
+// block sums (exclusive) and writes the grand total to cell_start[n].
+__global__ __launch_bounds__(kBlock) void k_scan_partial(const int* __restrict__ count, int n,
+                                                         int* partial, unsigned* done,
+                                                         int* total_out) {
+    __shared__ int s_wave[kBlock / kWave];
+    __shared__ int s_vals[2 * kBlock + 1];
+    __shared__ int s_last;
+    const int base = blockIdx.x * kScanTile;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int idx = base + k * kBlock + threadIdx.x;
+        if (idx < n) s += count[idx];
+    }
+    // fixed-order block sum
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kWave);
+    if (lane == 0) s_wave[w] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = ((s_wave[0] + s_wave[1]) + s_wave[2]) + s_wave[3];
+        __threadfence();
+        const unsigned prev = atomicAdd(done, 1u);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    // exclusive scan of partial[0..G) by this block, in chunks of 512
+    const int G = gridDim.x;
+    int carry = 0;
+    for (int c0 = 0; c0 < G; c0 += 2 * kBlock) {
+        const int m = min(2 * kBlock, G - c0);
+        for (int k = threadIdx.x; k < m; k += kBlock) s_vals[k] = partial[c0 + k];
+        __syncthreads();
+        const int tot = block_scan_excl_512(s_vals, m, s_wave);
+        for (int k = threadIdx.x; k < m; k += kBlock) partial[c0 + k] = s_vals[k] + carry;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *total_out = carry;
+        *done = 0u;
+    }
+}
+
+// Pass 2: exclusive scan within each block + block offset -> cell_start; the
+// counts are cleared for the next use.
+__global__ __launch_bounds__(kBlock) void k_scan_final(int* count, int n, const int* partial,
+                                                       int* cs) {
+    __shared__ int s_v[kScanTile + kScanTile / 32];
+    __shared__ int s_tsum[2 * kBlock + 1];
+    __shared__ int s_wave[kBlock / kWave];
+    const int base = blockIdx.x * kScanTile;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int li = k * kBlock + threadIdx.x;
+        const int idx = base + li;
+        s_v[li + (li >> 5)] = (idx < n) ? count[idx] : 0;
+    }
+    __syncthreads();
+    int loc[kScanPer];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int li = threadIdx.x * kScanPer + k;
+        loc[k] = sum;
+        sum += s_v[li + (li >> 5)];
+    }
+    // thread sums -> exclusive offsets (one value per thread)
+    s_tsum[threadIdx.x] = sum;
+    __syncthreads();
+    // scan 256 values with the 512-wide helper (upper half zero)
+    if (threadIdx.x < kBlock) s_tsum[kBlock + threadIdx.x] = 0;
+    __syncthreads();
+    block_scan_excl_512(s_tsum, kBlock, s_wave);
+    const int off = partial[blockIdx.x] + s_tsum[threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int li = threadIdx.x * kScanPer + k;
+        s_v[li + (li >> 5)] = off + loc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int li = k * kBlock + threadIdx.x;
+        const int idx = base + li;
+        if (idx < n) {
+            cs[idx] = s_v[li + (li >> 5)];
+            count[idx] = 0;
+        }
+    }
+}
+
+// slot = cell_start[key] + rank
+__global__ void k_scatter(int N, const int* __restrict__ key, const int* __restrict__ rank,
+                          const int* __restrict__ cs, int* src) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    src[cs[key[i]] + rank[i]] = i;
+}
+
+// Order each cell's slots by particle id (insertion sort; cells are small).
+__global__ void k_cell_sort(int n_cells, const int* __restrict__ cs, int* src,
+                            const int* __restrict__ id) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const int b = cs[c], e = cs[c + 1];
+    if (e - b < 2) return;
+    if (e - b <= 8) {
+        int sv[8], iv[8];
+        const int n = e - b;
+        for (int k = 0; k < n; ++k) {
+            sv[k] = src[b + k];
+            iv[k] = id[sv[k]];
+        }
+        for (int k = 1; k < n; ++k) {
+            const int s0 = sv[k], i0 = iv[k];
+            int m = k - 1;
+            while (m >= 0 && iv[m] > i0) {
+                sv[m + 1] = sv[m];
+                iv[m + 1] = iv[m];
+                --m;
+            }
+            sv[m + 1] = s0;
+            iv[m + 1] = i0;
+        }
+        for (int k = 0; k < n; ++k) src[b + k] = sv[k];
+        return;
+    }
+    for (int k = b + 1; k < e; ++k) {
+        const int s0 = src[k], i0 = id[s0];
+        int m = k - 1;
+        while (m >= b && id[src[m]] > i0) {
+            src[m + 1] = src[m];
+            --m;
+        }
+        src[m + 1] = s0;
+    }
+}
+
+// Resume: state in sorted order from the binned input plus a given force (id order).
+__global__ void k_gather_state(int N, const int* __restrict__ src, const float2* __restrict__ xi,
+                               const float2* __restrict__ ui, const int* __restrict__ idi,
+                               const float2* __restrict__ Fin, float2* xo, float2* vo, int* ido,
+                               float2* Fo, unsigned* status) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    const int p = src[g];
+    const int id = idi[p];
+    const float2 F = Fin[id];
+    if (!finite2(F)) atomicOr(status, kStatusNonFinite);
+    xo[g] = xi[p];
+    vo[g] = ui[p];
+    ido[g] = id;
+    Fo[g] = F;
+}
+
+// First half kick and drift of a dpd_step call, from the stored state.
+__global__ void k_kick_drift(DevParams P, const float2* __restrict__ x, const float2* __restrict__ v,
+                             const float2* __restrict__ F, const int* __restrict__ id, float2* xo,
+                             float2* uo, int* ido, int* key, int* rank, int* count,
+                             unsigned* status) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= P.N) return;
+    const float2 f = F[g], vv = v[g], xx = x[g];
+    const float2 u = make_float2(vv.x + P.h * f.x, vv.y + P.h * f.y);
+    const float2 xn = make_float2(drift_wrap(xx.x, u.x, P), drift_wrap(xx.y, u.y, P));
+    const int k = cell_key(xn, P);
+    xo[g] = xn;
+    uo[g] = u;
+    ido[g] = id[g];
+    key[g] = k;
+    rank[g] = atomicAdd(&count[k], 1);
+    if (!finite2(xn) || !finite2(u)) atomicOr(status, kStatusNonFinite);
+}
+
+// Fixed-order sum of the per-tile partials -> (P_x, P_y, KE).
+__global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restrict__ red,
+                                                         int n_tiles, double mass, double* out) {
+    __shared__ double s_red[kBlock / kWave][3];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < n_tiles; t += kBlock) {
+        v[0] += red[3 * t + 0];
+        v[1] += red[3 * t + 1];
+        v[2] += red[3 * t + 2];
+    }
+    block_sum3(v, s_red);
+    if (threadIdx.x == 0) {
+        out[0] = mass * v[0];
+        out[1] = mass * v[1];
+        out[2] = 0.5 * mass * v[2];
+    }
+}
+
+// Sorted order -> id order.
+__global__ void k_unpermute(int N, const int* __restrict__ id, const float2* __restrict__ a,
+                            float2* out) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    out[id[g]] = a[g];
+}
+
+// ---- filtered and projected velocity field (Sec. 5.4) -------------------------
+
+struct BinArgs {
+    const float2* x;   // id order
+    const float2* v;   // id order
+    long long* acc;    // M*M*3: sum q_x, sum q_y, count
+    unsigned* status;
+    int n_src;         // particles (mode 0) or agents (mode 1)
+    int mode;
+    int M;
+    double L;
+    double inv_dx;     // M / L
+    double dx;         // L / M
+    double eps;        // window width, <= 0 for plain bins
+    double qscale;     // fixed-point scale 2^S
+    double vmax;       // velocities beyond this cannot be summed exactly
+};
+
+__device__ __forceinline__ int clamp_floor(double y, int n) {
+    double f = floor(y);
+    f = fmin(fmax(f, 0.0), (double)(n - 1));
+    return (int)f;
+}
+
+__global__ void k_bin_accum(BinArgs b) {
+#pragma clang fp contract(off)
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= b.n_src) return;
+    double px, py, vx, vy;
+    const double L = b.L;
+    if (b.mode == 0) {
+        px = (double)b.x[s].x;
+        py = (double)b.x[s].y;
+        vx = (double)b.v[s].x;
+        vy = (double)b.v[s].y;
+    } else {
+        const float2 xh = b.x[2 * s], xt = b.x[2 * s + 1];
+        const float2 vh = b.v[2 * s], vt = b.v[2 * s + 1];
+        double dx = (double)xh.x - (double)xt.x;
+        double dy = (double)xh.y - (double)xt.y;
+        if (dx >= 0.5 * L) dx -= L; else if (dx < -0.5 * L) dx += L;
+        if (dy >= 0.5 * L) dy -= L; else if (dy < -0.5 * L) dy += L;
+        px = (double)xt.x + 0.5 * dx;
+        py = (double)xt.y + 0.5 * dy;
+        if (px < 0.0) px += L; else if (px >= L) px -= L;
+        if (py < 0.0) py += L; else if (py >= L) py -= L;
+        vx = 0.5 * ((double)vh.x + (double)vt.x);
+        vy = 0.5 * ((double)vh.y + (double)vt.y);
+    }
+    if (!(px >= 0.0 && px < L) || !(py >= 0.0 && py < L)) {
+        atomicOr(b.status, kStatusNonFinite);
+        return;
+    }
+    if (!(fabs(vx) <= b.vmax) || !(fabs(vy) <= b.vmax)) {
+        atomicOr(b.status, kStatusRange);
+        return;
+    }
+    const long long qx = llrint(vx * b.qscale), qy = llrint(vy * b.qscale);
+    const int M = b.M;
+    if (b.eps <= 0.0) {
+        const int bx = clamp_floor(px * b.inv_dx, M), by = clamp_floor(py * b.inv_dx, M);
+        const int k = by * M + bx;
+        atomicAdd((unsigned long long*)&b.acc[3 * k + 0], (unsigned long long)qx);
+        atomicAdd((unsigned long long*)&b.acc[3 * k + 1], (unsigned long long)qy);
+        atomicAdd((unsigned long long*)&b.acc[3 * k + 2], 1ull);
+        return;
+    }
+    const double half = 0.5 * b.eps;
+    long long lo[2], hi[2];
+    const double pos[2] = {px, py};
+    for (int ax = 0; ax < 2; ++ax) {
+        lo[ax] = (long long)floor((pos[ax] - half) / b.dx) - 1;
+        hi[ax] = (long long)floor((pos[ax] + half) / b.dx) + 1;
+        if (hi[ax] - lo[ax] + 1 > M) {
+            lo[ax] = 0;
+            hi[ax] = M - 1;
+        }
+    }
+    for (long long jy = lo[1]; jy <= hi[1]; ++jy) {
+        const int gy = (int)(((jy % M) + M) % M);
+        const double ym = ((double)gy + 0.5) * b.dx;
+        double ddy = py - ym;
+        if (ddy >= 0.5 * L) ddy -= L; else if (ddy < -0.5 * L) ddy += L;
+        if (!(ddy >= -half && ddy < half)) continue;
+        for (long long jx = lo[0]; jx <= hi[0]; ++jx) {
+            const int gx = (int)(((jx % M) + M) % M);
+            const double xm = ((double)gx + 0.5) * b.dx;
+            double ddx = px - xm;
+            if (ddx >= 0.5 * L) ddx -= L; else if (ddx < -0.5 * L) ddx += L;
+            if (!(ddx >= -half && ddx < half)) continue;
+            const int k = gy * M + gx;
+            atomicAdd((unsigned long long*)&b.acc[3 * k + 0], (unsigned long long)qx);
+            atomicAdd((unsigned long long*)&b.acc[3 * k + 1], (unsigned long long)qy);
+            atomicAdd((unsigned long long*)&b.acc[3 * k + 2], 1ull);
+        }
+    }
+}
+
+__global__ void k_bin_finalize(int nbin, const long long* __restrict__ acc, double qscale,
+                               float2* u, int* n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nbin) return;
+    const long long c = acc[3 * k + 2];
+    n[k] = (int)c;
+    if (c > 0) {
+        const double inv = 1.0 / (qscale * (double)c);
+        u[k] = make_float2((float)((double)acc[3 * k + 0] * inv), (float)((double)acc[3 * k + 1] * inv));
+    } else {
+        u[k] = make_float2(0.f, 0.f);
+    }
+}
+
+// ---- diagnostics -------------------------------------------------------------
+
+__global__ void k_rng_words(DevParams P, const int* __restrict__ i, const int* __restrict__ j,
+                            uint32_t step, int n, uint4* words, float* alpha) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t a = (uint32_t)min(i[k], j[k]), b = (uint32_t)max(i[k], j[k]);
+    uint4 w;
+    uint2 w2;
+    if (P.rng_kind == 0) {
+        w = philox4x32_10(make_uint4(a, b, step, 0u), P.seed_lo, P.seed_hi);
+        w2 = make_uint2(w.x, w.y);
+    } else {
+        w2 = pair_words2(P, a, b, step);
+        w = make_uint4(w2.x, w2.y, 0u, 0u);
+    }
+    words[k] = w;
+    if (alpha) alpha[k] = alpha_from_words(P.noise_kind, w2);
+}
+
+__global__ void k_fill_i32(int* p, int v, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_copy16(const uint4* __restrict__ a, uint4* __restrict__ b, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+}  // namespace dpd

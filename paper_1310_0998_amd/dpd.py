@@ -1,0 +1,252 @@
+"""Python binding of the HIP DPD engine (libdpd.so, C ABI in include/dpd.h).
+
+Argument marshalling only: every step of the hot path runs in the engine's
+kernels.  PyTorch provides device memory (the workspace and the state
+tensors) and the stream.  If libdpd.so is missing the import of the engine
+fails loudly; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Mapping, Optional
+
+import torch  # loaded first so that the engine binds to torch's HIP runtime
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpd.so")
+
+DPD_OK = 0
+ERRORS = {
+    -1: "DPD_EINVAL", -2: "DPD_EWORKSPACE", -3: "DPD_EHIP", -4: "DPD_ENONFINITE",
+    -5: "DPD_ESTATE", -6: "DPD_EBOND", -7: "DPD_ERANGE",
+}
+
+
+class DPDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n_agents", ctypes.c_int64),
+        ("L", ctypes.c_double),
+        ("r_c", ctypes.c_double),
+        ("A", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("kT", ctypes.c_double),
+        ("kappa", ctypes.c_double),
+        ("bond_l", ctypes.c_double),
+        ("f_sp", ctypes.c_double),
+        ("gamma_s", ctypes.c_double),
+        ("mass", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("noise_kind", ctypes.c_int32),
+        ("rng_kind", ctypes.c_int32),
+        ("sp_split", ctypes.c_int32),
+        ("bin_M_max", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+_INT_FIELDS = {"n_agents", "seed", "noise_kind", "rng_kind", "sp_split", "bin_M_max", "tile"}
+_DEFAULTS = dict(mass=1.0, seed=0, noise_kind=0, rng_kind=0, sp_split=0, bin_M_max=0, tile=0)
+
+
+def make_params(cfg: Mapping) -> Params:
+    vals = dict(_DEFAULTS)
+    vals.update(cfg)
+    p = Params()
+    for name, _ in Params._fields_:
+        if name == "reserved":
+            continue
+        v = vals[name]
+        setattr(p, name, int(v) if name in _INT_FIELDS else float(v))
+    return p
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, P = ctypes.c_void_p, ctypes.POINTER(Params)
+        i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "dpd_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
+            "dpd_create": (ctypes.c_int, [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+            "dpd_destroy": (None, [vp]),
+            "dpd_last_error": (ctypes.c_char_p, [vp]),
+            "dpd_set_state": (ctypes.c_int, [vp, vp, vp, i64, vp]),
+            "dpd_get_state": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(i64)]),
+            "dpd_forces": (ctypes.c_int, [vp, vp]),
+            "dpd_step": (ctypes.c_int, [vp, i32, i32, vp]),
+            "dpd_bin_velocity": (ctypes.c_int, [vp, i32, f64, i32, vp, vp]),
+            "dpd_sync": (ctypes.c_int, [vp]),
+            "dpd_get_cells": (ctypes.c_int, [vp, vp, vp]),
+            "dpd_cells_per_side": (i64, [P]),
+            "dpd_rng_words": (ctypes.c_int, [P, vp, vp, i64, i32, vp, vp, vp]),
+            "dpd_set_profiling": (ctypes.c_int, [vp, i32]),
+            "dpd_pair_kernel_time": (ctypes.c_int, [vp, ctypes.POINTER(f64), ctypes.POINTER(i64)]),
+            "dpd_copy_kernel": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, handle=None):
+    if rc != DPD_OK:
+        msg = lib().dpd_last_error(handle).decode()
+        raise DPDError(rc, msg)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == 2 * n):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of {n} x 2 values")
+    return t
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def cells_per_side(cfg: Mapping) -> int:
+    r = lib().dpd_cells_per_side(ctypes.byref(make_params(cfg)))
+    if r < 0:
+        _check(int(r))
+    return int(r)
+
+
+def workspace_bytes(cfg: Mapping) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().dpd_workspace_bytes(ctypes.byref(make_params(cfg)), ctypes.byref(n)))
+    return int(n.value)
+
+
+class Sim:
+    """One simulation bound to the current torch stream of `device`."""
+
+    def __init__(self, cfg: Mapping, device="cuda"):
+        self.cfg = dict(cfg)
+        self.device = torch.device(device)
+        self.params = make_params(cfg)
+        self.N = 2 * int(cfg["n_agents"])
+        nbytes = workspace_bytes(cfg)
+        # the allocator returns 512-byte aligned blocks; keep 256 spare anyway
+        self._ws_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws_raw.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self._stream = _stream_handle(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().dpd_create(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr),
+                                ctypes.c_size_t(nbytes), self._stream, ctypes.byref(h)))
+        self._h = h
+        self.n_c = cells_per_side(cfg)
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            lib().dpd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _c(self, rc):
+        _check(rc, self._h)
+
+    # -- state
+    def set_state(self, x: torch.Tensor, v: torch.Tensor, step: int = 0,
+                  F: Optional[torch.Tensor] = None):
+        _vec(x, self.N, "x")
+        _vec(v, self.N, "v")
+        if F is not None:
+            _vec(F, self.N, "F")
+        self._c(lib().dpd_set_state(self._h, _ptr(x), _ptr(v), int(step), _ptr(F)))
+
+    def get_state(self):
+        x = torch.empty((self.N, 2), dtype=torch.float32, device=self.device)
+        v = torch.empty_like(x)
+        F = torch.empty_like(x)
+        s = ctypes.c_int64(0)
+        self._c(lib().dpd_get_state(self._h, _ptr(x), _ptr(v), _ptr(F), ctypes.byref(s)))
+        return x, v, F, int(s.value)
+
+    def forces(self) -> torch.Tensor:
+        F = torch.empty((self.N, 2), dtype=torch.float32, device=self.device)
+        self._c(lib().dpd_forces(self._h, _ptr(F)))
+        return F
+
+    def step(self, n: int, reduce_every: int = 0, pk: Optional[torch.Tensor] = None):
+        """Advance n steps.  With reduce_every > 0 returns a (n // reduce_every, 3)
+        float64 device tensor of (P_x, P_y, KE) records."""
+        if reduce_every > 0 and pk is None:
+            nrec = n // reduce_every
+            pk = torch.zeros((max(nrec, 1), 3), dtype=torch.float64, device=self.device)
+        self._c(lib().dpd_step(self._h, int(n), int(reduce_every), _ptr(pk)))
+        if reduce_every > 0:
+            return pk[: n // reduce_every]
+        return None
+
+    def sync(self):
+        self._c(lib().dpd_sync(self._h))
+
+    def bin_velocity(self, M: int, eps: float = 0.0, mode: int = 0):
+        u = torch.empty((M, M, 2), dtype=torch.float32, device=self.device)
+        n = torch.empty((M, M), dtype=torch.int32, device=self.device)
+        self._c(lib().dpd_bin_velocity(self._h, int(M), float(eps), int(mode), _ptr(u), _ptr(n)))
+        return u, n
+
+    def cells(self):
+        cs = torch.empty(self.n_c * self.n_c + 1, dtype=torch.int32, device=self.device)
+        ids = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        self._c(lib().dpd_get_cells(self._h, _ptr(cs), _ptr(ids)))
+        return cs, ids
+
+    # -- profiling
+    def set_profiling(self, on: bool):
+        self._c(lib().dpd_set_profiling(self._h, 1 if on else 0))
+
+    def pair_kernel_time(self):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        self._c(lib().dpd_pair_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+
+def rng_words(cfg: Mapping, i: torch.Tensor, j: torch.Tensor, step: int):
+    """Generator words (n, 4) as int32 (bit pattern of uint32) and alpha (n,)."""
+    n = i.numel()
+    ii = i.int().contiguous()
+    jj = j.int().contiguous()
+    words = torch.empty((n, 4), dtype=torch.int32, device=i.device)
+    alpha = torch.empty(n, dtype=torch.float32, device=i.device)
+    _check(lib().dpd_rng_words(ctypes.byref(make_params(cfg)), _ptr(ii), _ptr(jj), int(step),
+                               int(n), _ptr(words), _ptr(alpha), _stream_handle(i.device)))
+    return words, alpha
+
+
+def copy_kernel(src: torch.Tensor, dst: torch.Tensor):
+    nbytes = src.numel() * src.element_size()
+    _check(lib().dpd_copy_kernel(_ptr(src), _ptr(dst), ctypes.c_size_t(nbytes),
+                                 _stream_handle(src.device)))

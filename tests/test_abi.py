@@ -1,0 +1,96 @@
+"""The C-ABI library loads, exports every entry point include/dpd.h declares,
+and its host-only paths (parameter validation, workspace sizing) behave.
+CPU only: no call here launches a kernel."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1310_0998_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dpd.h")
+
+
+@pytest.fixture(scope="module")
+def dpd():
+    from paper_1310_0998_amd import build as b
+    if not os.path.exists(b.LIB):
+        b.build(force=True)
+    from paper_1310_0998_amd import dpd as d
+    d.lib()
+    return d
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+\**\s*(dpd_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("dpd_create", "dpd_set_state", "dpd_forces", "dpd_step", "dpd_bin_velocity",
+                     "dpd_get_state", "dpd_destroy", "dpd_last_error", "dpd_workspace_bytes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(dpd):
+    lib = ctypes.CDLL(dpd.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_params_struct_layout_matches_header(dpd):
+    # 1 int64 + 11 doubles + 1 uint64 + 5 int32 + 3 reserved int32 = 128 bytes
+    assert ctypes.sizeof(dpd.Params) == 8 + 11 * 8 + 8 + 8 * 4
+
+
+def test_workspace_and_cells(dpd):
+    cfg = inputs.physics(inputs.WORKLOADS["dimers_1600"])
+    assert dpd.cells_per_side(cfg) == 40
+    n = dpd.workspace_bytes(cfg)
+    assert n > 1600 * 100
+    big = inputs.physics(inputs.WORKLOADS["dimers_4M"])
+    assert dpd.cells_per_side(big) == 2000
+    assert dpd.workspace_bytes(big) < 2 * 1024 ** 3
+    assert dpd.cells_per_side(dict(cfg, L=7.25, r_c=1.1)) == 6
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_agents=0), dict(L=2.5), dict(L=40.1), dict(r_c=0.0), dict(dt=0.0), dict(mass=-1.0),
+    dict(gamma=-1.0), dict(kT=float("nan")), dict(noise_kind=2), dict(rng_kind=5), dict(sp_split=3),
+    dict(tile=99), dict(bin_M_max=-1),
+])
+def test_invalid_parameters_rejected(dpd, bad):
+    cfg = dict(inputs.physics(inputs.WORKLOADS["dimers_1600"]), **bad)
+    with pytest.raises(dpd.DPDError) as ei:
+        dpd.workspace_bytes(cfg)
+    assert ei.value.code == -1
+    assert len(dpd.lib().dpd_last_error(None)) > 0
+
+
+def test_create_rejects_bad_workspace(dpd):
+    cfg = inputs.physics(inputs.WORKLOADS["dimers_1600"])
+    p = dpd.make_params(cfg)
+    h = ctypes.c_void_p()
+    lib = dpd.lib()
+    assert lib.dpd_create(ctypes.byref(p), None, 0, None, ctypes.byref(h)) == -2
+    assert lib.dpd_create(ctypes.byref(p), ctypes.c_void_p(256 * 1000 + 8), 10 ** 9, None,
+                          ctypes.byref(h)) == -2          # misaligned
+    need = dpd.workspace_bytes(cfg)
+    assert lib.dpd_create(ctypes.byref(p), ctypes.c_void_p(256 * 1000), need - 1, None,
+                          ctypes.byref(h)) == -2          # too small
+    assert b"needs" in lib.dpd_last_error(None)
+    assert h.value is None
+
+
+def test_null_handle_calls_fail_cleanly(dpd):
+    lib = dpd.lib()
+    assert lib.dpd_step(None, 1, 0, None) == -1
+    assert lib.dpd_forces(None, None) == -1
+    assert lib.dpd_set_state(None, None, None, 0, None) == -1
+    assert lib.dpd_sync(None) == -1
+    lib.dpd_destroy(None)

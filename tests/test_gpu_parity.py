@@ -1,0 +1,383 @@
+"""GPU engine against the FP64 oracle, element by element on the same seeded
+inputs, through the C ABI.  Needs an MI355X."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1310_0998_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+C1 = inputs.physics(inputs.WORKLOADS["dimers_1600"])
+C2 = inputs.physics(inputs.WORKLOADS["dimers_200k"])
+C3 = inputs.physics(inputs.WORKLOADS["dimers_4M"])
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def dpd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1310_0998_amd import dpd as d
+    d.lib()
+    return d
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make_sim(dpd, cfg, x, v, step=0, F=None):
+    sim = dpd.Sim(cfg, device=DEV)
+    sim.set_state(dev(x), dev(v), step, None if F is None else dev(F))
+    return sim
+
+
+def force_errors(cfg, x, v, step, F_gpu):
+    """Per-particle error relative to the scale S_i, and the global relative L2 error."""
+    Fo = oracle.forces(cfg, x, v, step)
+    _, scale = oracle.force_parts(cfg, x, v, step)
+    F = F_gpu.astype(np.float64)
+    per = np.sqrt(((F - Fo) ** 2).sum(1)) / scale
+    glob = np.sqrt(((F - Fo) ** 2).sum()) / np.sqrt((Fo ** 2).sum())
+    return per, glob
+
+
+# ---------------------------------------------------------------- noise words
+
+@pytest.mark.parametrize("rng_kind,noise_kind", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_rng_words_bit_identical(dpd, rng_kind, noise_kind):
+    cfg = dict(C1, rng_kind=rng_kind, noise_kind=noise_kind, seed=0xDEADBEEF12345)
+    rng = np.random.default_rng(1)
+    n = 3000
+    i = rng.integers(0, 2 ** 30, n).astype(np.int32)
+    j = rng.integers(0, 2 ** 30, n).astype(np.int32)
+    i[:10] = np.arange(10)
+    j[:10] = np.arange(10)[::-1]
+    for step in (0, 1, 12345, 2 ** 32 + 7):
+        w, a = dpd.rng_words(cfg, dev(i), dev(j), step)
+        w = host(w).view(np.uint32)
+        a = host(a)
+        for k in range(0, n, 97):
+            wo = oracle.pair_words(cfg, int(i[k]), int(j[k]), step)
+            assert (w[k] == wo).all(), (k, w[k], wo)
+            ao = oracle.pair_alpha(cfg, int(i[k]), int(j[k]), step)
+            assert abs(a[k] - ao) <= 2e-6 * max(1.0, abs(ao)), (k, a[k], ao)
+
+
+# ------------------------------------------------------------------- binning
+
+BIN_CASES = [
+    ("C1", dict(C1), "random"),
+    ("C1-edge", dict(C1), "edge"),
+    ("ragged-47", dict(C1, L=47.0, n_agents=1100, seed=5), "random"),
+    ("w>rc", dict(C1, L=29.25, r_c=1.1, n_agents=420, seed=6), "edge"),
+    ("nc3", dict(C1, L=3.0, n_agents=4, seed=7), "random"),
+    ("nc4", dict(C1, L=4.5, r_c=1.125, n_agents=8, seed=8), "edge"),
+    ("nc5", dict(C1, L=5.0, n_agents=12, seed=9), "random"),
+    ("clustered", dict(C1, L=40.0, n_agents=1200, seed=10), "clustered"),
+    ("one-agent", dict(C1, L=10.0, n_agents=1, seed=11), "random"),
+]
+
+
+@pytest.mark.parametrize("name,cfg,kind", BIN_CASES, ids=[c[0] for c in BIN_CASES])
+def test_binning_bit_exact(dpd, name, cfg, kind):
+    x, v = inputs.initial_state(cfg, kind=kind, thermal=True)
+    sim = make_sim(dpd, cfg, x, v)
+    cs, ids = sim.cells()
+    cso, idso = oracle.bin_cells(cfg, x)
+    assert (host(cs) == cso).all()
+    assert (host(ids) == idso).all()
+    # and again after the particles moved (state positions are FP32)
+    sim.step(7)
+    xs = host(sim.get_state()[0])
+    cs, ids = sim.cells()
+    cso, idso = oracle.bin_cells(cfg, xs)
+    assert (host(cs) == cso).all()
+    assert (host(ids) == idso).all()
+    sim.close()
+
+
+# -------------------------------------------------------------------- forces
+
+FORCE_CASES = [
+    ("C1", dict(C1), "random", True),
+    ("C1-edge", dict(C1), "edge", True),
+    ("ragged-47", dict(C1, L=47.0, n_agents=1100, seed=5), "random", True),
+    ("w>rc", dict(C1, L=29.25, r_c=1.1, n_agents=420, seed=6), "edge", True),
+    ("nc3", dict(C1, L=3.0, n_agents=4, seed=7), "random", True),
+    ("nc4", dict(C1, L=4.5, r_c=1.125, n_agents=8, seed=8), "edge", True),
+    ("nc5", dict(C1, L=5.0, n_agents=12, seed=9), "random", True),
+    ("clustered", dict(C1, L=40.0, n_agents=1200, seed=10), "clustered", True),
+    ("uniform-noise", dict(C1, noise_kind=1, seed=12), "random", True),
+    ("philox2x32", dict(C1, rng_kind=1, seed=13), "random", True),
+    ("head-only", dict(C1, sp_split=1, seed=14), "random", True),
+    ("tile8", dict(C1, tile=8, seed=15), "random", True),
+    ("tile1", dict(C1, L=12.0, n_agents=70, tile=1, seed=16), "random", True),
+    ("gamma0", dict(C1, gamma=0.0, seed=17), "random", True),
+    ("at-rest", dict(C1, seed=18), "random", False),
+]
+
+
+@pytest.mark.parametrize("name,cfg,kind,thermal", FORCE_CASES, ids=[c[0] for c in FORCE_CASES])
+def test_forces_match_oracle(dpd, name, cfg, kind, thermal):
+    x, v = inputs.initial_state(cfg, kind=kind, thermal=thermal)
+    step = 31
+    sim = make_sim(dpd, cfg, x, v, step=step)
+    F = host(sim.forces())
+    per, glob = force_errors(cfg, x, v, step, F)
+    assert per.max() <= 1e-5, (name, per.max(), int(per.argmax()))
+    assert glob <= 1e-5, (name, glob)
+    # the stored force of set_state is the same evaluation
+    _, _, Fs, s = sim.get_state()
+    assert s == step
+    assert (host(Fs) == F).all()
+    sim.close()
+
+
+def test_forces_full_size_sampled(dpd):
+    # 4M particles in the benchmark's launch configuration: every force is
+    # computed on the GPU, a sample is checked against the oracle one by one
+    cfg = C3
+    x, v = inputs.initial_state(cfg, thermal=True)
+    sim = make_sim(dpd, cfg, x, v, step=3)
+    F = host(sim.forces())
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([rng.choice(len(x), 3000, replace=False), [0, 1, len(x) - 2, len(x) - 1]])
+    Fo = oracle.forces_subset(cfg, x, v, 3, idx)
+    err = np.sqrt(((F[idx].astype(np.float64) - Fo) ** 2).sum(1))
+    scale = np.sqrt((Fo ** 2).sum(1)) + 25.0
+    assert (err / scale).max() <= 1e-5
+    # cell list of the full system is bit-exact
+    cs, ids = sim.cells()
+    cso, idso = oracle.bin_cells(cfg, x)
+    assert (host(cs) == cso).all() and (host(ids) == idso).all()
+    # after stepping in the benchmark's configuration the state stays sane
+    sim.step(20)
+    sim.sync()
+    xs = host(sim.get_state()[0])
+    assert np.isfinite(xs).all() and (xs >= 0).all() and (xs < cfg["L"]).all()
+    sim.close()
+
+
+def test_forces_200k_sampled(dpd):
+    cfg = dict(C2, gamma=20.0, gamma_s=5.0)
+    x, v = inputs.initial_state(cfg, thermal=True)
+    sim = make_sim(dpd, cfg, x, v, step=11)
+    F = host(sim.forces())
+    idx = np.random.default_rng(1).choice(len(x), 4000, replace=False)
+    Fo = oracle.forces_subset(cfg, x, v, 11, idx)
+    err = np.sqrt(((F[idx].astype(np.float64) - Fo) ** 2).sum(1))
+    scale = np.sqrt((Fo ** 2).sum(1)) + 25.0
+    assert (err / scale).max() <= 1e-5
+    sim.close()
+
+
+# --------------------------------------------------------------- trajectories
+
+def _traj_errors(cfg, xa, va, xb, vb):
+    d = xa.astype(np.float64) - xb
+    d -= cfg["L"] * np.round(d / cfg["L"])
+    dx = np.sqrt((d * d).sum(1)).max() / cfg["r_c"]
+    vrms = math.sqrt((vb * vb).sum(1).mean())
+    dv = np.sqrt(((va - vb) ** 2).sum(1)).max() / vrms
+    return dx, dv
+
+
+@pytest.mark.parametrize("gamma", [4.5, 0.0])
+def test_trajectory_100_steps(dpd, gamma):
+    cfg = dict(C1, gamma=gamma)
+    x, v = inputs.initial_state(cfg)
+    Fo = oracle.forces(cfg, x, v, 0)
+    xo, vo, _, so, _ = oracle.step(cfg, x, v, Fo, 0, 100)
+    # yardstick: the oracle against itself with every position moved by one FP32 ulp
+    xp = np.nextafter(x, np.float32(np.inf)).astype(np.float32)
+    xp[xp >= np.float32(cfg["L"])] = 0
+    Fp = oracle.forces(cfg, xp, v, 0)
+    xq, vq, _, _, _ = oracle.step(cfg, xp, v, Fp, 0, 100)
+    chaos_x, chaos_v = _traj_errors(cfg, xq, vq, xo, vo)
+    sim = make_sim(dpd, cfg, x, v)
+    sim.step(100)
+    xs, vs, _, s = sim.get_state()
+    assert s == so == 100
+    ex, ev = _traj_errors(cfg, host(xs), host(vs), xo, vo)
+    tol_x = max(1e-4, 10 * chaos_x)
+    tol_v = max(1e-4, 10 * chaos_v)
+    print(f"gamma={gamma}: gpu-oracle dx={ex:.2e} dv={ev:.2e}; oracle 1-ulp self-divergence "
+          f"dx={chaos_x:.2e} dv={chaos_v:.2e}")
+    assert ex <= tol_x and ev <= tol_v
+    sim.close()
+
+
+def test_run_to_run_bitwise_and_resume(dpd):
+    cfg = C1
+    x, v = inputs.initial_state(cfg, thermal=True)
+    a = make_sim(dpd, cfg, x, v)
+    a.step(60)
+    xa, va, Fa, sa = [t if isinstance(t, int) else host(t) for t in a.get_state()]
+    b = make_sim(dpd, cfg, x, v)
+    b.step(60)
+    xb, vb, Fb, sb = [t if isinstance(t, int) else host(t) for t in b.get_state()]
+    assert (xa == xb).all() and (va == vb).all() and (Fa == Fb).all() and sa == sb == 60
+    # 30 + 30 from a checkpoint equals 60 in one go
+    c = make_sim(dpd, cfg, x, v)
+    c.step(30)
+    xc, vc, Fc, sc = c.get_state()
+    d = make_sim(dpd, cfg, host(xc), host(vc), step=sc, F=host(Fc))
+    d.step(30)
+    xd, vd, Fd, sd = [t if isinstance(t, int) else host(t) for t in d.get_state()]
+    assert sd == 60
+    assert (xd == xa).all() and (vd == va).all() and (Fd == Fa).all()
+    # and 1 + 59 split inside one handle
+    e = make_sim(dpd, cfg, x, v)
+    e.step(1)
+    e.step(59)
+    xe = host(e.get_state()[0])
+    assert (xe == xa).all()
+    for s in (a, b, c, d, e):
+        s.close()
+
+
+def test_momentum_conserved_on_gpu(dpd):
+    cfg = dict(C1, f_sp=0.0, gamma_s=0.0)
+    x, v = inputs.initial_state(cfg, thermal=True)
+    sim = make_sim(dpd, cfg, x, v)
+    pk = host(sim.step(1000, reduce_every=10))
+    P0 = oracle.momentum_ke(cfg, v.astype(np.float64))
+    scale = np.abs(v).sum()
+    assert np.abs(pk[:, :2] - P0[:2]).max() <= 1e-5 * scale
+    sim.close()
+
+
+def test_stokes_momentum_decay_on_gpu(dpd):
+    cfg = dict(C1, f_sp=0.0, gamma_s=0.8)
+    x, v = inputs.initial_state(cfg, thermal=True)
+    v = (v + np.float32(0.75)).astype(np.float32)
+    sim = make_sim(dpd, cfg, x, v)
+    pk = host(sim.step(400, reduce_every=1))
+    P0 = oracle.momentum_ke(cfg, v.astype(np.float64))[:2]
+    c = cfg["gamma_s"] * cfg["dt"] / 2
+    n = np.arange(1, 401)
+    expect = P0[None, :] * ((1 - c) ** 2 * (1 - 2 * c) ** (n - 1))[:, None]
+    assert np.abs(pk[:, :2] - expect).max() <= 1e-5 * np.abs(v).sum()
+    sim.close()
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_isolated_dimer_terminal_velocity_on_gpu(dpd, split):
+    cfg = dict(C1, n_agents=1, L=20.0, gamma_s=5.0, sp_split=split)
+    th = 0.7
+    x = np.array([[10 + 0.25 * math.cos(th), 10 + 0.25 * math.sin(th)],
+                  [10 - 0.25 * math.cos(th), 10 - 0.25 * math.sin(th)]], np.float32)
+    sim = make_sim(dpd, cfg, x, np.zeros_like(x))
+    sim.step(3000)
+    _, vs, _, _ = sim.get_state()
+    vs = host(vs).astype(np.float64)
+    vt = cfg["f_sp"] / (2 * cfg["gamma_s"])
+    com = 0.5 * (vs[0] + vs[1])
+    assert com == pytest.approx(vt * np.array([math.cos(th), math.sin(th)]), abs=1e-6)
+    sim.close()
+
+
+def test_reductions_are_exact_sums(dpd):
+    cfg = C1
+    x, v = inputs.initial_state(cfg, thermal=True)
+    sim = make_sim(dpd, cfg, x, v)
+    pk = host(sim.step(25, reduce_every=25))
+    _, vs, _, _ = sim.get_state()
+    vs = host(vs).astype(np.float64)
+    ref = [math.fsum(vs[:, 0]), math.fsum(vs[:, 1]), 0.5 * math.fsum((vs * vs).sum(1))]
+    assert pk[0] == pytest.approx(ref, rel=1e-12, abs=1e-12)
+    sim.close()
+
+
+def test_fluctuation_dissipation_on_gpu(dpd):
+    cfg = dict(C1, f_sp=0.0, gamma_s=0.0, seed=102)
+    x, v = inputs.initial_state(cfg, thermal=True)
+    sim = make_sim(dpd, cfg, x, v)
+    sim.step(10000)
+    pk = host(sim.step(10000, reduce_every=10))
+    n = 2 * cfg["n_agents"]
+    T = 2 * pk[:, 2].mean() / (2 * n - 2)
+    assert T == pytest.approx(cfg["kT"], rel=0.01)
+    sim.close()
+
+
+# ----------------------------------------------------------- velocity field
+
+@pytest.mark.parametrize("M,eps,mode", [(40, 0.0, 0), (64, 0.0, 1), (16, 7.5, 0), (10, 12.0, 1),
+                                        (1, 0.0, 0)])
+def test_bin_velocity_matches_oracle(dpd, M, eps, mode):
+    cfg = C1
+    x, v = inputs.initial_state(cfg, thermal=True)
+    sim = make_sim(dpd, cfg, x, v)
+    sim.step(5)
+    xs, vs, _, _ = sim.get_state()
+    xs, vs = host(xs), host(vs)
+    u, n = sim.bin_velocity(M, eps, mode)
+    uo, no = oracle.bin_velocity(cfg, xs, vs, M, eps, mode)
+    assert (host(n) == no).all()
+    q = 2.0 ** -min(32, 46 - math.ceil(math.log2(len(x) // (1 + mode) + 1)))
+    err = np.abs(host(u).astype(np.float64) - uo)
+    assert (err <= q + 2.0 ** -23 * np.abs(uo)).all()
+    sim.close()
+
+
+def test_bin_velocity_full_size(dpd):
+    cfg = C3
+    x, v = inputs.initial_state(cfg, thermal=True)
+    sim = make_sim(dpd, cfg, x, v)
+    u, n = sim.bin_velocity(256, 0.0, 0)
+    uo, no = oracle.bin_velocity(cfg, x, v, 256, 0.0, 0)
+    assert (host(n) == no).all()
+    assert np.abs(host(u) - uo).max() <= 1e-6
+    sim.close()
+
+
+# ------------------------------------------------------------- error paths
+
+def test_error_paths(dpd):
+    cfg = C1
+    x, v = inputs.initial_state(cfg)
+    sim = dpd.Sim(cfg, device=DEV)
+    with pytest.raises(dpd.DPDError) as e:
+        sim.step(1)
+    assert e.value.code == -5
+    with pytest.raises(dpd.DPDError) as e:
+        sim.forces()
+    assert e.value.code == -5
+    bad = x.copy()
+    bad[17, 0] = np.nan
+    sim.set_state(dev(bad), dev(v))
+    with pytest.raises(dpd.DPDError) as e:
+        sim.sync()
+    assert e.value.code == -4
+    # a bond stretched across more than one cell width is reported
+    far = x.copy()
+    far[1] = far[0] + np.float32(2.5)
+    far[1] = np.mod(far[1], np.float32(cfg["L"]))
+    sim.set_state(dev(far), dev(v))
+    with pytest.raises(dpd.DPDError) as e:
+        sim.sync()
+    assert e.value.code == -6
+    # recovery: a good state works again
+    sim.set_state(dev(x), dev(v))
+    sim.step(3)
+    sim.sync()
+    # a blow-up (huge time step) is reported as non-finite
+    cfg2 = dict(C1, dt=5.0)
+    s2 = make_sim(dpd, cfg2, x, v)
+    s2.step(30)
+    with pytest.raises(dpd.DPDError) as e:
+        s2.sync()
+    assert e.value.code in (-4, -6)
+    sim.close()
+    s2.close()
