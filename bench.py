@@ -1,0 +1,218 @@
+"""Throughput of the DPD hot path on one MI355X.
+
+One step = one velocity-Verlet step of the whole hot path (cell binning, fused
+pair / agent / integrator kernel), with the FP64 momentum and kinetic-energy
+reduction every 100 steps and the binned 256 x 256 velocity field every 20
+steps, on the 4M-particle system (2M dimers in a 2000 x 2000 periodic box,
+synthetic random initial state).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-steps S]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (FP32 pair kernel, % HBM roofline); closure speedup at ≤5% E(k) err"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pair_kernel_bytes(n_particles: int, n_cells: int) -> int:
+    """Algorithmic HBM bytes of one launch of the fused pair kernel (step mode):
+    reads slot->index (4), x (8), u (8), id (4) per particle and cell_start
+    (4 per cell + 1); writes x (8), u (8), id (4), key (4), rank (4) per
+    particle; one 4-byte atomic read-modify-write of a cell counter (8)."""
+    return n_particles * (4 + 8 + 8 + 4 + 8 + 8 + 4 + 4 + 4 + 8) + 4 * (n_cells + 1)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("device.h", "kernels.h", "engine.hip"):
+        with open(os.path.join(ROOT, "paper_1310_0998_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_launch_particles: int):
+    """HBM bytes per launch of the pair kernel from the committed rocprofv3
+    counter summary, if it was taken with the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pair_kernel_dimers_4M_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cfg, x, v, steps: int):
+    import numpy as np
+
+    import oracle
+    t0 = time.perf_counter()
+    F = oracle.forces(cfg, x, v, 0)
+    t1 = time.perf_counter()
+    oracle.step(cfg, x, v, F, 0, steps)
+    t2 = time.perf_counter()
+    n = len(x)
+    return {
+        "value": n * steps / (t2 - t1),
+        "unit": "particle-steps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{steps} velocity-Verlet steps of the full {n}-particle system from the "
+                  f"benchmark's initial state (FP64 oracle, OpenMP; initial force "
+                  f"evaluation {t1 - t0:.2f} s not counted)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="dimers_4M")
+    ap.add_argument("--rng-kind", type=int, default=0)
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="first run a plain copy kernel of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the engine has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1310_0998_amd import dpd, inputs
+
+    wl = inputs.WORKLOADS[args.workload]
+    cfg = dict(inputs.physics(wl), rng_kind=args.rng_kind)
+    bin_M = wl.get("bin_M", 256)
+    bin_every = wl.get("bin_every", 20)
+    reduce_every = wl.get("reduce_every", 100)
+    steps = max(bin_every, (args.steps // bin_every) * bin_every)
+    warm = max(0, args.warmup)
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy_mb > 0:
+        nb = args.calibrate_copy_mb << 20
+        a = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            dpd.copy_kernel(a, b)
+        torch.cuda.synchronize()
+        log(f"copy kernel calibration: 3 x {nb} bytes")
+        del a, b
+    x, v = inputs.initial_state(cfg)
+    N = len(x)
+    log(f"workload {args.workload}: N={N} L={cfg['L']} steps={steps} warmup={warm}")
+
+    sim = dpd.Sim(dict(cfg, bin_M_max=bin_M), device=dev)
+    sim.set_state(torch.from_numpy(x).to(dev), torch.from_numpy(v).to(dev), 0)
+    out = (torch.empty((bin_M, bin_M, 2), dtype=torch.float32, device=dev),
+           torch.empty((bin_M, bin_M), dtype=torch.int32, device=dev))
+    n_chunks_red = max(1, reduce_every // bin_every)
+    pk = torch.zeros((steps // reduce_every + 1, 3), dtype=torch.float64, device=dev)
+
+    def run(nsteps, record_pk):
+        rec = 0
+        for c in range(nsteps // bin_every):
+            do_red = record_pk and ((c + 1) % n_chunks_red == 0)
+            if do_red:
+                sim.step(bin_every, reduce_every=bin_every, pk=pk[rec:rec + 1])
+                rec += 1
+            else:
+                sim.step(bin_every)
+            sim.bin_velocity(bin_M, 0.0, 0, out=out)
+        rem = nsteps % bin_every
+        if rem:
+            sim.step(rem)
+
+    run(warm, False)
+    sim.sync()
+    torch.cuda.synchronize()
+    sim.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.sync()
+    pair_ms, launches = sim.pair_kernel_time()
+    sim.set_profiling(False)
+    elapsed = t1 - t0
+    value = N * steps / elapsed
+    ms_per_step = 1e3 * elapsed / steps
+    avg_us = 1e3 * pair_ms / max(launches, 1)
+    alg = pair_kernel_bytes(N, sim.n_c * sim.n_c)
+    achieved = alg / (avg_us * 1e-6) / 1e9
+    traffic = measured_traffic(N)
+    pkh = pk.cpu().numpy()
+    log(f"elapsed {elapsed:.3f} s, {ms_per_step:.4f} ms/step, pair kernel {avg_us:.1f} us avg over "
+        f"{launches} launches, {achieved:.0f} GB/s algorithmic; last KE {pkh[max(0, steps // reduce_every - 1), 2]:.1f}")
+
+    cpu = None
+    if not args.no_cpu and args.cpu_steps > 0:
+        log(f"cpu baseline: oracle, {args.cpu_steps} steps ...")
+        cpu = cpu_baseline(cfg, x, v, args.cpu_steps)
+        log(f"cpu baseline {cpu['value']:.3e} particle-steps/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: 2-D periodic box L={cfg['L']:g} r_c, "
+                        f"{cfg['n_agents']} dimers ({N} particles, density 1), a=25, "
+                        f"gamma={cfg['gamma']}, kT=1, zeta={cfg['gamma_s']}, F_p=1, "
+                        f"dt={cfg['dt']}; 256x256 velocity field every {bin_every} steps, "
+                        f"FP64 momentum/KE every {reduce_every} steps",
+            "n_particles": N,
+            "cells": sim.n_c * sim.n_c,
+            "rng": ["philox4x32-10", "philox2x32-10"][cfg["rng_kind"]],
+            "noise": "gaussian",
+            "state": "fp32 (fp64 wrap and reductions)",
+            "parallelism": "single-gpu",
+        },
+        "roofline": {
+            "kernel": "k_pair (fused pair + agent + Verlet)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg,
+            "avg_launch_us": avg_us,
+        },
+        "cpu_baseline": cpu,
+    }
+    sim.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

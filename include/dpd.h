@@ -31,7 +31,7 @@
  *   - Device-side failures (non-finite state, a bonded partner beyond the
  *     neighbour stencil, a velocity too large for the binned field) set a flag
  *     that the next synchronising call (dpd_sync, dpd_get_state, dpd_forces,
- *     dpd_get_cells, dpd_bin_velocity) reports.
+ *     dpd_get_cells) reports.
  */
 #ifndef DPD_H
 #define DPD_H
@@ -137,9 +137,11 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
  * their velocities; mode 1: agent centres of mass (minimum-image midpoints)
  * and (v_head + v_tail)/2.  u_out: device M*M*2 FP32, element (j*M + i)*2 + c,
  * the mean velocity (0 where nothing contributes); n_out: device M*M int32
- * contributor counts.  Sums are exact in 64-bit fixed point, so the result is
- * independent of the order of contributions.  Synchronises the stream.
- * Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP, DPD_ERANGE, device flags. */
+ * contributor counts.  Sums are exact in 64-bit fixed point (scale 2^S with
+ * S = min(32, 46 - ceil(log2(contributors + 1))), |v| <= 2^16), so the result
+ * is independent of the order of contributions.  Asynchronous; a velocity
+ * beyond 2^16 is reported by the next synchronising call as DPD_ERANGE.
+ * Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP. */
 int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode,
                      float* u_out, int32_t* n_out);
 

@@ -33,6 +33,8 @@ struct DevParams {
     float sigma_rdt;  // sqrt(2 gamma kT) / sqrt(dt)
     float kappa;
     float bond_l;
+    float bond_l2_hi; // l^2 as a sum of two floats (hi + lo)
+    float bond_l2_lo;
     float sp_head;    // share of f_sp on the head, times f_sp
     float sp_tail;    // share of f_sp on the tail, times f_sp
     float gamma_s;

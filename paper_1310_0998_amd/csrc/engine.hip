@@ -102,6 +102,11 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     P.sigma_rdt = (float)(std::sqrt(2.0 * p->gamma * p->kT) / std::sqrt(p->dt));
     P.kappa = (float)p->kappa;
     P.bond_l = (float)p->bond_l;
+    {
+        const double l2 = (double)P.bond_l * (double)P.bond_l;
+        P.bond_l2_hi = (float)l2;
+        P.bond_l2_lo = (float)(l2 - (double)P.bond_l2_hi);
+    }
     P.sp_head = (float)(p->sp_split == 0 ? 0.5 * p->f_sp : p->f_sp);
     P.sp_tail = (float)(p->sp_split == 0 ? 0.5 * p->f_sp : 0.0);
     P.gamma_s = (float)p->gamma_s;
@@ -579,7 +584,7 @@ int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode, float* 
                            (int)nbin, (const long long*)h->binacc, b.qscale, (float2*)u_out,
                            (int*)n_out);
         LAUNCHCHK(h);
-        return read_status(h);
+        return DPD_OK;
     } catch (...) {
         return fail(h, DPD_EINVAL, "internal error");
     }

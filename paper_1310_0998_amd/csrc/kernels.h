@@ -113,13 +113,31 @@ __device__ __forceinline__ void add_pair_force(const DevParams& P, float dx, flo
     fy += s * ey;
 }
 
+// Bond stretch r - l for the separation d.  r^2 is formed without rounding
+// error (two-product and two-sum), and r - l = (r^2 - l^2) / (r + l), so the
+// stiff bond force kappa (r - l) keeps FP32 relative accuracy even though r
+// itself is only known to one FP32 ulp.
+__device__ __forceinline__ float bond_stretch(const DevParams& P, float dx, float dy, float& r) {
+#pragma clang fp contract(off)
+    const float px = dx * dx, ex = fmaf(dx, dx, -px);
+    const float py = dy * dy, ey = fmaf(dy, dy, -py);
+    const float s = px + py;
+    const float bp = s - px;
+    const float es = (px - (s - bp)) + (py - bp);
+    const float lo = (es + ex) + ey;
+    const float num = (s - P.bond_l2_hi) + (lo - P.bond_l2_lo);
+    r = sqrtf(s);
+    return num / (r + P.bond_l);
+}
+
 // Bond to the partner (Eq. 2.5), propulsion along n = (r_head - r_tail)/|.|
 // (Eqs. 2.6-2.7) and Stokes friction (Eq. 2.6); d = x_i - x_partner.
 __device__ __forceinline__ void add_agent_force(const DevParams& P, float dx, float dy,
                                                 float2 ui, int idi, float& fx, float& fy) {
-    const float r = sqrtf(dx * dx + dy * dy);
+    float r;
+    const float stretch = bond_stretch(P, dx, dy, r);
     const float rinv = 1.0f / r;
-    const float cb = -P.kappa * (r - P.bond_l) * rinv;
+    const float cb = -P.kappa * stretch * rinv;
     const float csp = ((idi & 1) ? -P.sp_tail : P.sp_head) * rinv;
     fx += (cb + csp) * dx - P.gamma_s * ui.x;
     fy += (cb + csp) * dy - P.gamma_s * ui.y;

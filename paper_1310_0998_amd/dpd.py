@@ -211,9 +211,14 @@ class Sim:
     def sync(self):
         self._c(lib().dpd_sync(self._h))
 
-    def bin_velocity(self, M: int, eps: float = 0.0, mode: int = 0):
-        u = torch.empty((M, M, 2), dtype=torch.float32, device=self.device)
-        n = torch.empty((M, M), dtype=torch.int32, device=self.device)
+    def bin_velocity(self, M: int, eps: float = 0.0, mode: int = 0, out=None):
+        """Mean velocity (M, M, 2) [row j, column i] and counts (M, M) per grid
+        window; asynchronous on the stream (reading the tensors waits for it)."""
+        if out is None:
+            u = torch.empty((M, M, 2), dtype=torch.float32, device=self.device)
+            n = torch.empty((M, M), dtype=torch.int32, device=self.device)
+        else:
+            u, n = out
         self._c(lib().dpd_bin_velocity(self._h, int(M), float(eps), int(mode), _ptr(u), _ptr(n)))
         return u, n
 
