@@ -26,6 +26,7 @@ struct DevParams {
     int rng_kind;     // 0 Philox4x32-10, 1 Philox2x32-10
     float L;          // box side (FP32)
     float halfL;
+    float rc;         // r_c
     float rc2;        // r_c^2
     float inv_rc;     // 1 / r_c
     float A;
@@ -132,6 +133,21 @@ __device__ __forceinline__ float minimg_sub(float xi, float xj, const DevParams&
     if (d > P.halfL) d = (xi - P.L) - xj;
     else if (d < -P.halfL) d = xi - (xj - P.L);
     return d;
+}
+
+// Minimum-image separation as an unevaluated sum hi + lo of two floats (the
+// rounding error of the final subtraction by Knuth's two-sum), for the stiff
+// bond whose force needs |d| beyond FP32 resolution.
+__device__ __forceinline__ float minimg_sub2(float xi, float xj, const DevParams& P, float& lo) {
+#pragma clang fp contract(off)
+    float a = xi, b = xj;
+    const float d0 = xi - xj;
+    if (d0 > P.halfL) a = xi - P.L;        // exact: xi >= L/2
+    else if (d0 < -P.halfL) b = xj - P.L;  // exact: xj >= L/2
+    const float s = a - b;
+    const float bb = s - a;
+    lo = (a - (s - bb)) + (-b - bb);
+    return s;
 }
 
 __device__ __forceinline__ bool finite2(float2 a) {

@@ -95,6 +95,7 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     P.rng_kind = p->rng_kind;
     P.L = (float)p->L;
     P.halfL = (float)(0.5 * p->L);
+    P.rc = (float)p->r_c;
     P.rc2 = (float)(p->r_c * p->r_c);
     P.inv_rc = (float)(1.0 / p->r_c);
     P.A = (float)p->A;

@@ -94,16 +94,28 @@ __device__ void block_sum3(double v[3], double (*s_red)[3]) {
     }
 }
 
-// DPD pair force on i from j (Eqs. 2.2-2.4) added to (fx, fy); d = x_i - x_j
-// with 0 < |d|^2 < r_c^2 already established.  Every operation is symmetric
-// under (i, j, d) -> (j, i, -d), so the force on j is bitwise the negation.
+// r_c^2 - |d|^2 by two fused multiply-adds: accurate to ~1e-8 absolute near the
+// cutoff, where 1 - r/r_c would lose most of its digits.
+__device__ __forceinline__ float cutoff_gap(const DevParams& P, float dx, float dy) {
+    return fmaf(-dy, dy, fmaf(-dx, dx, P.rc2));
+}
+
+// The pair interacts iff 0 < |d| < r_c: q = r_c^2 - |d|^2 > 0 and r2 = |d|^2 > 0
+// (q alone cannot tell a coincident pair from one a few ulps apart).
+__device__ __forceinline__ bool interacts(float q, float r2) { return q > 0.f && r2 > 0.f; }
+
+// DPD pair force on i from j (Eqs. 2.2-2.4) added to (fx, fy); d = x_i - x_j,
+// r2 = |d|^2 and q = r_c^2 - |d|^2 with interacts(q, r2).  The weight
+// w = 1 - r/r_c (Eq. 2.4) is evaluated as q / (r_c (r_c + r)).  Every
+// operation is symmetric under (i, j, d) -> (j, i, -d), so the force on j is
+// bitwise the negation.
 __device__ __forceinline__ void add_pair_force(const DevParams& P, float dx, float dy,
-                                               float r2, float2 ui, float2 uj, int idi,
+                                               float q, float r2, float2 ui, float2 uj, int idi,
                                                int idj, uint32_t step, float& fx,
                                                float& fy) {
     const float rinv = rsqrtf(r2);
     const float r = r2 * rinv;
-    const float w = 1.0f - r * P.inv_rc;
+    const float w = q * __builtin_amdgcn_rcpf(fmaf(r, P.rc, P.rc2));
     const float ex = dx * rinv, ey = dy * rinv;
     const float g = (ui.x - uj.x) * ex + (ui.y - uj.y) * ey;
     const uint32_t a = (uint32_t)min(idi, idj), b = (uint32_t)max(idi, idj);
@@ -113,14 +125,16 @@ __device__ __forceinline__ void add_pair_force(const DevParams& P, float dx, flo
     fy += s * ey;
 }
 
-// Bond stretch r - l for the separation d.  r^2 is formed without rounding
-// error (two-product and two-sum), and r - l = (r^2 - l^2) / (r + l), so the
-// stiff bond force kappa (r - l) keeps FP32 relative accuracy even though r
-// itself is only known to one FP32 ulp.
-__device__ __forceinline__ float bond_stretch(const DevParams& P, float dx, float dy, float& r) {
+// Bond stretch r - l for the separation d = (dx + dx_lo, dy + dy_lo).  r^2 is
+// formed without rounding error (two-product and two-sum, the lo parts to
+// first order), and r - l = (r^2 - l^2) / (r + l), so the stiff bond force
+// kappa (r - l) keeps FP32 relative accuracy even though r itself is only
+// known to one FP32 ulp.
+__device__ __forceinline__ float bond_stretch(const DevParams& P, float dx, float dx_lo, float dy,
+                                              float dy_lo, float& r) {
 #pragma clang fp contract(off)
-    const float px = dx * dx, ex = fmaf(dx, dx, -px);
-    const float py = dy * dy, ey = fmaf(dy, dy, -py);
+    const float px = dx * dx, ex = fmaf(2.0f * dx, dx_lo, fmaf(dx, dx, -px));
+    const float py = dy * dy, ey = fmaf(2.0f * dy, dy_lo, fmaf(dy, dy, -py));
     const float s = px + py;
     const float bp = s - px;
     const float es = (px - (s - bp)) + (py - bp);
@@ -131,11 +145,14 @@ __device__ __forceinline__ float bond_stretch(const DevParams& P, float dx, floa
 }
 
 // Bond to the partner (Eq. 2.5), propulsion along n = (r_head - r_tail)/|.|
-// (Eqs. 2.6-2.7) and Stokes friction (Eq. 2.6); d = x_i - x_partner.
-__device__ __forceinline__ void add_agent_force(const DevParams& P, float dx, float dy,
+// (Eqs. 2.6-2.7) and Stokes friction (Eq. 2.6) on particle i at xi.
+__device__ __forceinline__ void add_agent_force(const DevParams& P, float2 xi, float2 xp,
                                                 float2 ui, int idi, float& fx, float& fy) {
+    float lx, ly;
+    const float dx = minimg_sub2(xi.x, xp.x, P, lx);
+    const float dy = minimg_sub2(xi.y, xp.y, P, ly);
     float r;
-    const float stretch = bond_stretch(P, dx, dy, r);
+    const float stretch = bond_stretch(P, dx, lx, dy, ly, r);
     const float rinv = 1.0f / r;
     const float cb = -P.kappa * stretch * rinv;
     const float csp = ((idi & 1) ? -P.sp_tail : P.sp_head) * rinv;
@@ -200,7 +217,7 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
             const int idi = a.idin[p], pid = idi ^ 1;
             float fx = 0.f, fy = 0.f;
             bool found = false;
-            float pdx = 0.f, pdy = 0.f;
+            float2 xpart = xi;
             for (int oy = -1; oy <= 1; ++oy) {
                 for (int ox = -1; ox <= 1; ++ox) {
                     const int c2 = wrap_cell(gy + oy, nc) * nc + wrap_cell(gx + ox, nc);
@@ -214,18 +231,18 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
                         const float dy = minimg_sub(xi.y, xj.y, P);
                         if (idj == pid) {
                             found = true;
-                            pdx = dx;
-                            pdy = dy;
+                            xpart = xj;
                             continue;
                         }
-                        const float r2 = dx * dx + dy * dy;
-                        if (r2 < P.rc2 && r2 > 0.f)
-                            add_pair_force(P, dx, dy, r2, ui, a.uin[q], idi, idj, a.step, fx, fy);
+                        const float gap = cutoff_gap(P, dx, dy);
+                        const float r2 = fmaf(dx, dx, dy * dy);
+                        if (interacts(gap, r2))
+                            add_pair_force(P, dx, dy, gap, r2, ui, a.uin[q], idi, idj, a.step, fx, fy);
                     }
                 }
             }
             if (found) {
-                add_agent_force(P, pdx, pdy, ui, idi, fx, fy);
+                add_agent_force(P, xi, xpart, ui, idi, fx, fy);
             } else {
                 atomicOr(a.status, kStatusBond);
                 fx -= P.gamma_s * ui.x;
@@ -316,16 +333,14 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevParams P, PairArgs a, int re
                         dx = xi.x - xj.x;
                         dy = xi.y - xj.y;
                     }
-                    const float r2 = dx * dx + dy * dy;
-                    if (r2 < P.rc2 && r2 > 0.f)
-                        add_pair_force(P, dx, dy, r2, ui, s_u[j], idi, idj, a.step, fx, fy);
+                    const float gap = cutoff_gap(P, dx, dy);
+                    const float r2 = fmaf(dx, dx, dy * dy);
+                    if (interacts(gap, r2))
+                        add_pair_force(P, dx, dy, gap, r2, ui, s_u[j], idi, idj, a.step, fx, fy);
                 }
             }
             if (jp >= 0) {
-                const float2 xp = s_x[jp];
-                const float dx = edge ? minimg_sub(xi.x, xp.x, P) : xi.x - xp.x;
-                const float dy = edge ? minimg_sub(xi.y, xp.y, P) : xi.y - xp.y;
-                add_agent_force(P, dx, dy, ui, idi, fx, fy);
+                add_agent_force(P, xi, s_x[jp], ui, idi, fx, fy);
             } else {
                 atomicOr(a.status, kStatusBond);
                 fx -= P.gamma_s * ui.x;
