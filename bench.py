@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="dimers_4M")
     ap.add_argument("--rng-kind", type=int, default=0)
+    ap.add_argument("--noise-kind", type=int, default=0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run a plain copy kernel of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -101,7 +102,7 @@ def main():
     from paper_1310_0998_amd import dpd, inputs
 
     wl = inputs.WORKLOADS[args.workload]
-    cfg = dict(inputs.physics(wl), rng_kind=args.rng_kind)
+    cfg = dict(inputs.physics(wl), rng_kind=args.rng_kind, noise_kind=args.noise_kind)
     bin_M = wl.get("bin_M", 256)
     bin_every = wl.get("bin_every", 20)
     reduce_every = wl.get("reduce_every", 100)
@@ -193,7 +194,7 @@ def main():
             "n_particles": N,
             "cells": sim.n_c * sim.n_c,
             "rng": ["philox4x32-10", "philox2x32-10"][cfg["rng_kind"]],
-            "noise": "gaussian",
+            "noise": ["gaussian", "uniform"][cfg["noise_kind"]],
             "state": "fp32 (fp64 wrap and reductions)",
             "parallelism": "single-gpu",
         },

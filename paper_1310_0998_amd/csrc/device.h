@@ -14,13 +14,15 @@ constexpr int kWave = 64;
 constexpr unsigned kStatusNonFinite = 1u;
 constexpr unsigned kStatusBond = 2u;
 constexpr unsigned kStatusRange = 4u;
+constexpr unsigned kStatusBinning = 8u;  // cell counts inconsistent with N (internal error)
 
 // Everything a kernel needs to know about the model, by value.
 struct DevParams {
     int N;            // particles
     int nc;           // cells per side
     int n_cells;      // nc * nc
-    int tile;         // tile side in cells
+    int tile_x;       // pair-kernel tile width (cells)
+    int tile_y;       // pair-kernel tile height (cells)
     int ntx, nty;     // tiles per side
     int noise_kind;   // 0 Gaussian, 1 uniform
     int rng_kind;     // 0 Philox4x32-10, 1 Philox2x32-10

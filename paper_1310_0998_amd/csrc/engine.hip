@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -23,7 +24,7 @@ struct Layout {
     size_t off_Sx, off_Sv, off_SF, off_Sid;
     size_t off_Ax, off_Au, off_Aid, off_Bx, off_Bu, off_Bid;
     size_t off_key, off_rank, off_src, off_count, off_cs;
-    size_t off_scan_part, off_scan_done, off_red, off_Fs, off_binacc, off_status;
+    size_t off_scan_part, off_red, off_Fs, off_binacc, off_status;
     size_t total;
 };
 
@@ -86,11 +87,11 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     P.N = (int)(2 * p->n_agents);
     P.nc = (int)ncd;
     P.n_cells = P.nc * P.nc;
-    int tile = p->tile ? p->tile : kTileMax;
-    if (tile > P.nc - 2) tile = P.nc - 2;  // tile + halo must not wrap onto itself
-    P.tile = tile;
-    P.ntx = (P.nc + tile - 1) / tile;
-    P.nty = P.ntx;
+    // tile + halo must not wrap onto itself: tile side <= n_c - 2
+    P.tile_x = std::min(p->tile ? p->tile : kTileX, P.nc - 2);
+    P.tile_y = std::min(p->tile ? p->tile : kTileY, P.nc - 2);
+    P.ntx = (P.nc + P.tile_x - 1) / P.tile_x;
+    P.nty = (P.nc + P.tile_y - 1) / P.tile_y;
     P.noise_kind = p->noise_kind;
     P.rng_kind = p->rng_kind;
     P.L = (float)p->L;
@@ -142,7 +143,6 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     L.off_count = take((size_t)P.n_cells * 4);
     L.off_cs = take(((size_t)P.n_cells + 1) * 4);
     L.off_scan_part = take((size_t)d->n_scan_blocks * 4);
-    L.off_scan_done = take(16);
     L.off_red = take((size_t)d->n_tiles * 3 * 8);
     L.off_Fs = take(N * 8);
     L.off_binacc = take((size_t)d->bin_M_max * d->bin_M_max * 3 * 8);
@@ -162,7 +162,7 @@ struct dpd_handle {
     char* ws;
     float2 *Sx, *Sv, *SF, *Ax, *Au, *Bx, *Bu, *Fs;
     int *Sid, *Aid, *Bid, *key, *rank, *src, *count, *cs, *scan_part;
-    unsigned *scan_done, *status;
+    unsigned* status;
     double* red;
     long long* binacc;
     int64_t step;
@@ -201,8 +201,10 @@ int fail(dpd_handle* h, int code, const std::string& msg) {
 int bin_from_counts(dpd_handle* h, const int* id_of_input) {
     const DevParams& P = h->d.P;
     const int G = h->d.n_scan_blocks;
-    hipLaunchKernelGGL(k_scan_partial, dim3(G), dim3(kBlock), 0, h->stream, h->count, P.n_cells,
-                       h->scan_part, h->scan_done, h->cs + P.n_cells);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(G), dim3(kBlock), 0, h->stream, (const int*)h->count,
+                       P.n_cells, h->scan_part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, h->stream, h->scan_part, G,
+                       h->cs + P.n_cells);
     hipLaunchKernelGGL(k_scan_final, dim3(G), dim3(kBlock), 0, h->stream, h->count, P.n_cells,
                        (const int*)h->scan_part, h->cs);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
@@ -229,11 +231,11 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
         HIPCHK(h, hipEventRecord(h->ev_start[ev], h->stream));
     }
     if (mode == MODE_STEP)
-        hipLaunchKernelGGL(k_pair<MODE_STEP>, dim3(G), dim3(kBlock), 0, h->stream, P, a, (int)reduce);
+        hipLaunchKernelGGL(k_pair<MODE_STEP>, dim3(G), dim3(kWave), 0, h->stream, P, a, (int)reduce);
     else if (mode == MODE_FINAL)
-        hipLaunchKernelGGL(k_pair<MODE_FINAL>, dim3(G), dim3(kBlock), 0, h->stream, P, a, (int)reduce);
+        hipLaunchKernelGGL(k_pair<MODE_FINAL>, dim3(G), dim3(kWave), 0, h->stream, P, a, (int)reduce);
     else
-        hipLaunchKernelGGL(k_pair<MODE_FORCES>, dim3(G), dim3(kBlock), 0, h->stream, P, a, 0);
+        hipLaunchKernelGGL(k_pair<MODE_FORCES>, dim3(G), dim3(kWave), 0, h->stream, P, a, 0);
     LAUNCHCHK(h);
     if (h->profiling) {
         HIPCHK(h, hipEventRecord(h->ev_stop[ev], h->stream));
@@ -265,6 +267,8 @@ int read_status(dpd_handle* h) {
         return fail(h, DPD_EBOND, "a bonded partner was farther than one cell width");
     if (st[0] & kStatusRange)
         return fail(h, DPD_ERANGE, "a velocity exceeded the range of the binned field");
+    if (st[0] & kStatusBinning)
+        return fail(h, DPD_EHIP, "internal error: cell counts inconsistent with the particle count");
     return DPD_OK;
 }
 
@@ -332,7 +336,6 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
         h->count = (int*)(w + L.off_count);
         h->cs = (int*)(w + L.off_cs);
         h->scan_part = (int*)(w + L.off_scan_part);
-        h->scan_done = (unsigned*)(w + L.off_scan_done);
         h->red = (double*)(w + L.off_red);
         h->Fs = (float2*)(w + L.off_Fs);
         h->binacc = (long long*)(w + L.off_binacc);
@@ -347,8 +350,6 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
         // clear the counters the kernels rely on
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(d.P.n_cells)), dim3(kBlock), 0, h->stream,
                            h->count, 0, (long long)d.P.n_cells);
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, (int*)h->scan_done, 0,
-                           4LL);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, (int*)h->status, 0, 4LL);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
@@ -424,6 +425,7 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
     try {
         const DevParams& P = h->d.P;
         const bool want_pk = reduce_every > 0 && pk_out != nullptr;
+        // first half kick + drift from the stored state
         hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
                            (const float2*)h->Sx, (const float2*)h->Sv, (const float2*)h->SF,
                            (const int*)h->Sid, h->Ax, h->Au, h->Aid, h->key, h->rank, h->count,

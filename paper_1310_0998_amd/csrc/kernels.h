@@ -17,10 +17,16 @@
 
 namespace dpd {
 
-constexpr int kBlock = 256;                              // threads per block
-constexpr int kTileMax = 16;                             // tile side (cells)
-constexpr int kLocMax = (kTileMax + 2) * (kTileMax + 2); // tile + halo cells
-constexpr int kCap = 1024;                               // LDS particle slots
+constexpr int kBlock = 256;  // threads per block of the streaming kernels
+
+// Pair kernel: one wavefront per tile of up to kTileX x kTileY cells.
+constexpr int kTileX = 8, kTileY = 7;                // default tile (cells)
+constexpr int kTileMax = 8;                          // largest tile side
+constexpr int kLocMax = (kTileMax + 2) * (kTileMax + 2);  // tile + halo cells
+constexpr int kCap = 192;   // staged particles (tile + halo)
+constexpr int kTP = 128;    // tile particles
+constexpr int kEcap = 224;  // kept pairs per tile
+constexpr int kCand = 640;  // half-stencil candidates per tile
 
 enum PairMode { MODE_STEP = 0, MODE_FINAL = 1, MODE_FORCES = 2 };
 
@@ -140,8 +146,8 @@ __device__ __forceinline__ float bond_stretch(const DevParams& P, float dx, floa
     const float es = (px - (s - bp)) + (py - bp);
     const float lo = (es + ex) + ey;
     const float num = (s - P.bond_l2_hi) + (lo - P.bond_l2_lo);
-    r = sqrtf(s);
-    return num / (r + P.bond_l);
+    r = __builtin_amdgcn_sqrtf(s);
+    return num * __builtin_amdgcn_rcpf(r + P.bond_l);
 }
 
 // Bond to the partner (Eq. 2.5), propulsion along n = (r_head - r_tail)/|.|
@@ -153,7 +159,7 @@ __device__ __forceinline__ void add_agent_force(const DevParams& P, float2 xi, f
     const float dy = minimg_sub2(xi.y, xp.y, P, ly);
     float r;
     const float stretch = bond_stretch(P, dx, lx, dy, ly, r);
-    const float rinv = 1.0f / r;
+    const float rinv = __builtin_amdgcn_rcpf(r);
     const float cb = -P.kappa * stretch * rinv;
     const float csp = ((idi & 1) ? -P.sp_tail : P.sp_head) * rinv;
     fx += (cb + csp) * dx - P.gamma_s * ui.x;
@@ -207,12 +213,16 @@ template <int MODE>
 __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int cy0, int tw,
                             int th, double rv[3], bool reduce) {
     const int nc = P.nc;
-    for (int ic = threadIdx.x; ic < tw * th; ic += kBlock) {
+    for (int ic = threadIdx.x; ic < tw * th; ic += blockDim.x) {
         const int gx = cx0 + ic % tw, gy = cy0 + ic / tw;
         const int c = gy * nc + gx;
         const int b = a.cs[c], e = a.cs[c + 1];
         for (int g = b; g < e; ++g) {
-            const int p = a.src[g];
+            int p = a.src[g];
+            if ((unsigned)p >= (unsigned)P.N) {
+                atomicOr(a.status, kStatusBinning);
+                p = 0;
+            }
             const float2 xi = a.xin[p], ui = a.uin[p];
             const int idi = a.idin[p], pid = idi ^ 1;
             float fx = 0.f, fy = 0.f;
@@ -224,7 +234,8 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
                     const int b2 = a.cs[c2], e2 = a.cs[c2 + 1];
                     for (int g2 = b2; g2 < e2; ++g2) {
                         if (g2 == g) continue;
-                        const int q = a.src[g2];
+                        int q = a.src[g2];
+                        if ((unsigned)q >= (unsigned)P.N) q = 0;
                         const int idj = a.idin[q];
                         const float2 xj = a.xin[q];
                         const float dx = minimg_sub(xi.x, xj.x, P);
@@ -253,19 +264,65 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
     }
 }
 
-// The fused pair / agent / integrator kernel.  One 256-thread block per tile of
-// up to kTileMax x kTileMax cells; the tile and a one-cell halo are staged in
-// LDS in (cell, id) order, each thread then owns particles of the tile.
+// ---- wavefront helpers ----------------------------------------------------------
+
+__device__ __forceinline__ int wave_scan_excl(int v, int& total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+    }
+    total = __shfl(incl, kWave - 1, kWave);
+    return incl - v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// lanes below this one whose bit is set in mask
+__device__ __forceinline__ int lanes_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// The fused pair / agent / integrator kernel: one 64-lane wavefront per tile of
+// up to kTileX x kTileY cells, the tile and a one-cell halo staged in LDS in
+// (cell, id) order.  Phases, each in a fixed order:
+//   A1 every tile particle lists its half-stencil candidates: the rest of its
+//      own cell and the cell to its right, the row above, and any halo cells of
+//      its 3x3 stencil - so each interior pair is listed once (by its earlier
+//      slot) and each halo pair once; the lists are concatenated in particle
+//      order;
+//   A2 the wavefront tests the candidates 64 at a time and keeps the pairs
+//      within r_c in list order (so each particle's kept pairs are contiguous),
+//      recording bonded partners both ways;
+//   B  one force evaluation per kept pair (Eqs. 2.2-2.4);
+//   C  each particle adds its kept pairs in order, subtracts the pairs kept by
+//      interior partners in pair order (Newton's third law), adds the agent
+//      forces and finishes the step.
+// A tile that overflows an LDS capacity is processed by tile_global instead.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_pair(DevParams P, PairArgs a, int reduce) {
+__global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int reduce) {
     __shared__ int s_ofs[kLocMax + 1];
     __shared__ int s_gbeg[kLocMax];
-    __shared__ int s_wave[kBlock / kWave];
-    __shared__ unsigned short s_lcell[kCap];
-    __shared__ float2 s_x[kCap];
+    __shared__ int s_tofs[kLocMax];
+    __shared__ unsigned char s_lcell[kCap];
+    __shared__ float4 s_rec[kCap];          // x, y, id, tile index (0xFF: halo)
     __shared__ float2 s_u[kCap];
-    __shared__ int s_id[kCap];
-    __shared__ double s_red[kBlock / kWave][3];
+    __shared__ unsigned char s_tslot[kTP];
+    __shared__ unsigned char s_partner[kTP];
+    __shared__ int s_fcnt[kTP + 1];         // kept pairs per owner -> offsets
+    __shared__ int s_bcnt[kTP + 1];         // pairs as interior partner -> offsets
+    __shared__ int s_bfill[kTP];
+    __shared__ unsigned short s_cand[kCand];
+    __shared__ unsigned short s_pair[kEcap];
+    __shared__ unsigned char s_bkt[kEcap];
+    __shared__ float2 s_f[kEcap];
 
     // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs, so give
     // each XCD a contiguous band of tiles (neighbouring halos share its L2).
@@ -273,90 +330,253 @@ __global__ __launch_bounds__(kBlock) void k_pair(DevParams P, PairArgs a, int re
     const int bid = blockIdx.x;
     const int xcd = bid & 7, kk = bid >> 3;
     const int per = nt >> 3, rem = nt & 7;
-    const int t = xcd * per + min(xcd, rem) + kk;
-    const int tx = t % P.ntx, ty = t / P.ntx;
-    const int cx0 = tx * P.tile, cy0 = ty * P.tile;
-    const int tw = min(P.tile, P.nc - cx0), th = min(P.tile, P.nc - cy0);
-    const int W = tw + 2, H = th + 2, nloc = W * H;
+    const int tile = xcd * per + min(xcd, rem) + kk;
+    const int ty = tile / P.ntx, tx = tile - ty * P.ntx;
+    const int cx0 = tx * P.tile_x, cy0 = ty * P.tile_y;
+    const int tw = min(P.tile_x, P.nc - cx0), th = min(P.tile_y, P.nc - cy0);
+    const int W = tw + 2, nloc = W * (th + 2);
+    // local cell -> (lx, ly) by multiply-shift: exact for lc < 128 and W <= 10
+    const int wmul = (65536 + W - 1) / W;
     const bool edge = (cx0 == 0) || (cx0 + tw >= P.nc) || (cy0 == 0) || (cy0 + th >= P.nc);
+    const int lane = threadIdx.x;
 
-    for (int lc = threadIdx.x; lc < nloc; lc += kBlock) {
-        const int gx = wrap_cell(cx0 - 1 + lc % W, P.nc);
-        const int gy = wrap_cell(cy0 - 1 + lc / W, P.nc);
-        const int c = gy * P.nc + gx;
-        const int b = a.cs[c], e = a.cs[c + 1];
-        s_ofs[lc] = e - b;
-        s_gbeg[lc] = b;
+    // cell counts of the tile + halo, two local cells per lane
+    int cnt[2], tcnt[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int lc = lane + h * kWave;
+        cnt[h] = 0;
+        tcnt[h] = 0;
+        if (lc < nloc) {
+            const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
+            const int c = wrap_cell(cy0 - 1 + ly, P.nc) * P.nc + wrap_cell(cx0 - 1 + lx, P.nc);
+            const int b = a.cs[c];
+            cnt[h] = a.cs[c + 1] - b;
+            s_gbeg[lc] = b;
+            if (lx >= 1 && lx <= tw && ly >= 1 && ly <= th) tcnt[h] = cnt[h];
+        }
     }
+    int t0, t1, u0, u1;
+    const int e0 = wave_scan_excl(cnt[0], t0), e1 = wave_scan_excl(cnt[1], t1);
+    const int f0 = wave_scan_excl(tcnt[0], u0), f1 = wave_scan_excl(tcnt[1], u1);
+    const int total = t0 + t1, ntile = u0 + u1;
+    if (lane < nloc) { s_ofs[lane] = e0; s_tofs[lane] = f0; }
+    if (lane + kWave < nloc) { s_ofs[lane + kWave] = t0 + e1; s_tofs[lane + kWave] = u0 + f1; }
+    if (lane == 0) s_ofs[nloc] = total;
     __syncthreads();
-    const int total = block_scan_excl_512(s_ofs, nloc, s_wave);
 
     double rv[3] = {0.0, 0.0, 0.0};
-    if (total > kCap) {
-        tile_global<MODE>(P, a, cx0, cy0, tw, th, rv, reduce != 0);
-    } else {
-        for (int lc = threadIdx.x; lc < nloc; lc += kBlock)
-            for (int s = s_ofs[lc]; s < s_ofs[lc + 1]; ++s) s_lcell[s] = (unsigned short)lc;
-        __syncthreads();
-        for (int s = threadIdx.x; s < total; s += kBlock) {
-            const int lc = s_lcell[s];
-            const int p = a.src[s_gbeg[lc] + (s - s_ofs[lc])];
-            s_x[s] = a.xin[p];
-            s_u[s] = a.uin[p];
-            s_id[s] = a.idin[p];
+    bool done = false;
+    if (total <= kCap && ntile <= kTP) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int lc = lane + h * kWave;
+            if (lc < nloc)
+                for (int q = s_ofs[lc]; q < s_ofs[lc] + cnt[h]; ++q) s_lcell[q] = (unsigned char)lc;
         }
         __syncthreads();
-        for (int s = threadIdx.x; s < total; s += kBlock) {
-            const int lc = s_lcell[s];
-            const int lx = lc % W, ly = lc / W;
-            if (lx < 1 || lx > tw || ly < 1 || ly > th) continue;  // halo
-            const float2 xi = s_x[s], ui = s_u[s];
-            const int idi = s_id[s], pid = idi ^ 1;
-            float fx = 0.f, fy = 0.f;
-            int jp = -1;
-            for (int r = 0; r < 3; ++r) {
-                const int row = (ly - 1 + r) * W;
-                const int j0 = s_ofs[row + lx - 1], j1 = s_ofs[row + lx + 2];
-                for (int j = j0; j < j1; ++j) {
-                    if (j == s) continue;
-                    const int idj = s_id[j];
-                    if (idj == pid) {
-                        jp = j;
-                        continue;
+        for (int q = lane; q < total; q += kWave) {
+            const int lc = s_lcell[q];
+            int p = a.src[s_gbeg[lc] + (q - s_ofs[lc])];
+            if ((unsigned)p >= (unsigned)P.N) {
+                atomicOr(a.status, kStatusBinning);
+                p = 0;
+            }
+            const float2 xq = a.xin[p];
+            s_u[q] = a.uin[p];
+            const int idq = a.idin[p];
+            const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
+            int ti = 0xFF;
+            if (lx >= 1 && lx <= tw && ly >= 1 && ly <= th) {
+                ti = s_tofs[lc] + (q - s_ofs[lc]);
+                s_tslot[ti] = (unsigned char)q;
+                s_partner[ti] = 0xFF;
+            }
+            s_rec[q] = make_float4(xq.x, xq.y, __int_as_float(idq), __int_as_float(ti));
+        }
+        for (int k = lane; k <= ntile; k += kWave) {
+            s_fcnt[k] = 0;
+            s_bcnt[k] = 0;
+            if (k < ntile) s_bfill[k] = 0;
+        }
+        __syncthreads();
+
+        // ---- phase A1: half-stencil candidate lists, concatenated in particle order
+        const int rounds = (ntile + kWave - 1) / kWave;
+        int C = 0;
+        for (int r = 0; r < rounds; ++r) {
+            const int k = r * kWave + lane;
+            int b0 = 0, n0 = 0, b1 = 0, n1 = 0, b2 = 0, n2 = 0, b3 = 0, n3 = 0, b4 = 0, n4 = 0;
+            if (k < ntile) {
+                const int si = s_tslot[k];
+                const int lc = s_lcell[si];
+                const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
+                const int up = (ly + 1) * W, me = ly * W, dn = (ly - 1) * W;
+                b0 = s_ofs[up + lx - 1];                 // row above, three cells
+                n0 = s_ofs[up + lx + 2] - b0;
+                b1 = si + 1;                             // rest of own cell + right cell
+                n1 = s_ofs[me + lx + 2] - b1;
+                if (lx == 1) {                           // left halo cell of own row
+                    b2 = s_ofs[me];
+                    n2 = s_ofs[me + 1] - b2;
+                }
+                if (ly == 1) {                           // row below is halo: three cells
+                    b3 = s_ofs[dn + lx - 1];
+                    n3 = s_ofs[dn + lx + 2] - b3;
+                } else {
+                    if (lx == 1) {                       // left halo cell of row below
+                        b3 = s_ofs[dn];
+                        n3 = s_ofs[dn + 1] - b3;
                     }
-                    const float2 xj = s_x[j];
-                    float dx, dy;
-                    if (edge) {
-                        dx = minimg_sub(xi.x, xj.x, P);
-                        dy = minimg_sub(xi.y, xj.y, P);
-                    } else {
-                        dx = xi.x - xj.x;
-                        dy = xi.y - xj.y;
+                    if (lx == tw) {                      // right halo cell of row below
+                        b4 = s_ofs[dn + tw + 1];
+                        n4 = s_ofs[dn + tw + 2] - b4;
                     }
-                    const float gap = cutoff_gap(P, dx, dy);
-                    const float r2 = fmaf(dx, dx, dy * dy);
-                    if (interacts(gap, r2))
-                        add_pair_force(P, dx, dy, gap, r2, ui, s_u[j], idi, idj, a.step, fx, fy);
                 }
             }
-            if (jp >= 0) {
-                add_agent_force(P, xi, s_x[jp], ui, idi, fx, fy);
-            } else {
-                atomicOr(a.status, kStatusBond);
-                fx -= P.gamma_s * ui.x;
-                fy -= P.gamma_s * ui.y;
+            int ctot;
+            const int off = C + wave_scan_excl(n0 + n1 + n2 + n3 + n4, ctot);
+            if (C + ctot <= kCand && k < ntile) {
+                const unsigned short kw = (unsigned short)(k << 8);
+                int o = off;
+                for (int t = 0; t < n0; ++t) s_cand[o++] = kw | (unsigned short)(b0 + t);
+                for (int t = 0; t < n1; ++t) s_cand[o++] = kw | (unsigned short)(b1 + t);
+                for (int t = 0; t < n2; ++t) s_cand[o++] = kw | (unsigned short)(b2 + t);
+                for (int t = 0; t < n3; ++t) s_cand[o++] = kw | (unsigned short)(b3 + t);
+                for (int t = 0; t < n4; ++t) s_cand[o++] = kw | (unsigned short)(b4 + t);
             }
-            const int g = s_gbeg[lc] + (s - s_ofs[lc]);
-            finish_particle<MODE>(P, a, g, xi, ui, idi, fx, fy, rv, reduce != 0);
+            C += ctot;
+        }
+        __syncthreads();
+
+        // ---- phase A2: test the candidates 64 at a time, keep pairs in list order
+        int E = 0;
+        if (C <= kCand) {
+            for (int c0 = 0; c0 < C; c0 += kWave) {
+                const int c = c0 + lane;
+                bool keep = false;
+                int w = 0, own = 0, tj = 0xFF;
+                if (c < C) {
+                    w = s_cand[c];
+                    own = w >> 8;
+                    const int j = w & 0xFF, si = s_tslot[own];
+                    const float4 ri = s_rec[si], rj = s_rec[j];
+                    tj = __float_as_int(rj.w);
+                    if ((__float_as_int(ri.z) ^ 1) == __float_as_int(rj.z)) {
+                        s_partner[own] = (unsigned char)j;
+                        if (tj != 0xFF) s_partner[tj] = (unsigned char)si;
+                    } else {
+                        const float dx = edge ? minimg_sub(ri.x, rj.x, P) : ri.x - rj.x;
+                        const float dy = edge ? minimg_sub(ri.y, rj.y, P) : ri.y - rj.y;
+                        keep = interacts(cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy));
+                    }
+                }
+                const unsigned long long m = __ballot(keep);
+                if (keep) {
+                    const int pos = E + lanes_below(m);
+                    if (pos < kEcap) {
+                        s_pair[pos] = (unsigned short)(((tj != 0xFF) << 15) | w);
+                        atomicAdd(&s_fcnt[own], 1);
+                        if (tj != 0xFF) atomicAdd(&s_bcnt[tj], 1);
+                    }
+                }
+                E += __popcll(m);
+            }
+        }
+        __syncthreads();
+
+        if (C <= kCand && E <= kEcap) {
+            // ---- phase B: one force per kept pair
+            for (int e = lane; e < E; e += kWave) {
+                const int w = s_pair[e];
+                const int own = (w >> 8) & 0x7F, j = w & 0xFF;
+                const int so = s_tslot[own];
+                const float4 ro = s_rec[so], rj = s_rec[j];
+                const float dx = edge ? minimg_sub(ro.x, rj.x, P) : ro.x - rj.x;
+                const float dy = edge ? minimg_sub(ro.y, rj.y, P) : ro.y - rj.y;
+                float fx = 0.f, fy = 0.f;
+                add_pair_force(P, dx, dy, cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy), s_u[so],
+                               s_u[j], __float_as_int(ro.z), __float_as_int(rj.z), a.step, fx, fy);
+                s_f[e] = make_float2(fx, fy);
+            }
+            {
+                // owner-run offsets and partner-bucket offsets (two per lane)
+                const int a0 = lane < ntile ? s_fcnt[lane] : 0;
+                const int a1 = lane + kWave < ntile ? s_fcnt[lane + kWave] : 0;
+                const int c0 = lane < ntile ? s_bcnt[lane] : 0;
+                const int c1 = lane + kWave < ntile ? s_bcnt[lane + kWave] : 0;
+                int sa0, sa1, s0, s1;
+                const int y0 = wave_scan_excl(a0, sa0), y1 = wave_scan_excl(a1, sa1);
+                const int x0 = wave_scan_excl(c0, s0), x1 = wave_scan_excl(c1, s1);
+                __syncthreads();
+                if (lane < ntile) { s_fcnt[lane] = y0; s_bcnt[lane] = x0; }
+                if (lane + kWave < ntile) { s_fcnt[lane + kWave] = sa0 + y1; s_bcnt[lane + kWave] = s0 + x1; }
+                if (lane == 0) { s_fcnt[ntile] = sa0 + sa1; s_bcnt[ntile] = s0 + s1; }
+            }
+            __syncthreads();
+            for (int e = lane; e < E; e += kWave) {
+                const int w = s_pair[e];
+                if (w & 0x8000) {
+                    const int tj = __float_as_int(s_rec[w & 0xFF].w);
+                    s_bkt[s_bcnt[tj] + atomicAdd(&s_bfill[tj], 1)] = (unsigned char)e;
+                }
+            }
+            __syncthreads();
+
+            // ---- phase C: fixed-order sums, agent forces, integration
+            for (int r = 0; r < rounds; ++r) {
+                const int k = r * kWave + lane;
+                if (k >= ntile) continue;
+                const int si = s_tslot[k];
+                const int lc = s_lcell[si];
+                const float4 ri = s_rec[si];
+                const float2 xi = make_float2(ri.x, ri.y), ui = s_u[si];
+                const int idi = __float_as_int(ri.z);
+                float fx = 0.f, fy = 0.f;
+                for (int e = s_fcnt[k]; e < s_fcnt[k + 1]; ++e) {  // own pairs, list order
+                    const float2 f = s_f[e];
+                    fx += f.x;
+                    fy += f.y;
+                }
+                const int b = s_bcnt[k], en = s_bcnt[k + 1];
+                int last = -1;
+                for (int q0 = b; q0 < en; ++q0) {        // partners' pairs by pair index
+                    int best = 0x7FFFFFFF;
+                    for (int q = b; q < en; ++q) {
+                        const int e = s_bkt[q];
+                        if (e > last && e < best) best = e;
+                    }
+                    const float2 f = s_f[best];
+                    fx -= f.x;
+                    fy -= f.y;
+                    last = best;
+                }
+                const int jpk = s_partner[k];
+                if (jpk != 0xFF) {
+                    const float4 rp = s_rec[jpk];
+                    add_agent_force(P, xi, make_float2(rp.x, rp.y), ui, idi, fx, fy);
+                } else {
+                    atomicOr(a.status, kStatusBond);
+                    fx -= P.gamma_s * ui.x;
+                    fy -= P.gamma_s * ui.y;
+                }
+                const int g = s_gbeg[lc] + (si - s_ofs[lc]);
+                finish_particle<MODE>(P, a, g, xi, ui, idi, fx, fy, rv, reduce != 0);
+            }
+            done = true;
         }
     }
+    if (!done) tile_global<MODE>(P, a, cx0, cy0, tw, th, rv, reduce != 0);
     if (reduce) {
-        __syncthreads();
-        block_sum3(rv, s_red);
-        if (threadIdx.x == 0) {
-            a.red[3 * t + 0] = rv[0];
-            a.red[3 * t + 1] = rv[1];
-            a.red[3 * t + 2] = rv[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) rv[k] += __shfl_down(rv[k], o, kWave);
+        }
+        if (lane == 0) {
+            a.red[3 * tile + 0] = rv[0];
+            a.red[3 * tile + 1] = rv[1];
+            a.red[3 * tile + 2] = rv[2];
         }
     }
 }
@@ -394,14 +614,10 @@ __global__ void k_key_rank(DevParams P, const float2* __restrict__ x, int* key, 
 constexpr int kScanPer = 8;
 constexpr int kScanTile = kBlock * kScanPer;  // cells per scan block
 
-// Pass 1: per-block sums of the counts; the last block to finish scans the
-// block sums (exclusive) and writes the grand total to cell_start[n].
-__global__ __launch_bounds__(kBlock) void k_scan_partial(const int* __restrict__ count, int n,
-                                                         int* partial, unsigned* done,
-                                                         int* total_out) {
+// Pass 1: per-block sums of the counts (fixed order).
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ count, int n,
+                                                        int* partial) {
     __shared__ int s_wave[kBlock / kWave];
-    __shared__ int s_vals[2 * kBlock + 1];
-    __shared__ int s_last;
     const int base = blockIdx.x * kScanTile;
     int s = 0;
 #pragma unroll
@@ -409,23 +625,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_partial(const int* __restrict__
         const int idx = base + k * kBlock + threadIdx.x;
         if (idx < n) s += count[idx];
     }
-    // fixed-order block sum
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kWave);
     if (lane == 0) s_wave[w] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        partial[blockIdx.x] = ((s_wave[0] + s_wave[1]) + s_wave[2]) + s_wave[3];
-        __threadfence();
-        const unsigned prev = atomicAdd(done, 1u);
-        s_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    // exclusive scan of partial[0..G) by this block, in chunks of 512
-    const int G = gridDim.x;
+    if (threadIdx.x == 0) partial[blockIdx.x] = ((s_wave[0] + s_wave[1]) + s_wave[2]) + s_wave[3];
+}
+
+// Pass 1b (one block): exclusive scan of the G block sums; the grand total goes
+// to cell_start[n].
+__global__ __launch_bounds__(kBlock) void k_scan_top(int* partial, int G, int* total_out) {
+    __shared__ int s_wave[kBlock / kWave];
+    __shared__ int s_vals[2 * kBlock + 1];
     int carry = 0;
     for (int c0 = 0; c0 < G; c0 += 2 * kBlock) {
         const int m = min(2 * kBlock, G - c0);
@@ -436,10 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_partial(const int* __restrict__
         carry += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        *total_out = carry;
-        *done = 0u;
-    }
+    if (threadIdx.x == 0) *total_out = carry;
 }
 
 // Pass 2: exclusive scan within each block + block offset -> cell_start; the
@@ -498,32 +707,41 @@ __global__ void k_scatter(int N, const int* __restrict__ key, const int* __restr
     src[cs[key[i]] + rank[i]] = i;
 }
 
-// Order each cell's slots by particle id (insertion sort; cells are small).
+// Order each cell's slots by particle id.  Cells hold about one particle:
+// two or three members are sorted in registers, larger cells in place.
+__device__ __forceinline__ void cswap(int& sa, int& ia, int& sb, int& ib) {
+    if (ia > ib) {
+        const int s0 = sa, i0 = ia;
+        sa = sb; ia = ib;
+        sb = s0; ib = i0;
+    }
+}
+
 __global__ void k_cell_sort(int n_cells, const int* __restrict__ cs, int* src,
                             const int* __restrict__ id) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
     const int b = cs[c], e = cs[c + 1];
-    if (e - b < 2) return;
-    if (e - b <= 8) {
-        int sv[8], iv[8];
-        const int n = e - b;
-        for (int k = 0; k < n; ++k) {
-            sv[k] = src[b + k];
-            iv[k] = id[sv[k]];
+    const int n = e - b;
+    if (n < 2) return;
+    if (n == 2) {
+        int s0 = src[b], s1 = src[b + 1];
+        int i0 = id[s0], i1 = id[s1];
+        if (i0 > i1) {
+            src[b] = s1;
+            src[b + 1] = s0;
         }
-        for (int k = 1; k < n; ++k) {
-            const int s0 = sv[k], i0 = iv[k];
-            int m = k - 1;
-            while (m >= 0 && iv[m] > i0) {
-                sv[m + 1] = sv[m];
-                iv[m + 1] = iv[m];
-                --m;
-            }
-            sv[m + 1] = s0;
-            iv[m + 1] = i0;
-        }
-        for (int k = 0; k < n; ++k) src[b + k] = sv[k];
+        return;
+    }
+    if (n == 3) {
+        int s0 = src[b], s1 = src[b + 1], s2 = src[b + 2];
+        int i0 = id[s0], i1 = id[s1], i2 = id[s2];
+        cswap(s0, i0, s1, i1);
+        cswap(s1, i1, s2, i2);
+        cswap(s0, i0, s1, i1);
+        src[b] = s0;
+        src[b + 1] = s1;
+        src[b + 2] = s2;
         return;
     }
     for (int k = b + 1; k < e; ++k) {

@@ -106,6 +106,31 @@ def test_binning_bit_exact(dpd, name, cfg, kind):
     sim.close()
 
 
+def test_binning_with_multi_cell_jumps(dpd):
+    # three agents move ~2 cells per step (|v| dt = 2 cell widths): they take the
+    # engine's jumper path; cells must still match the oracle bit for bit and
+    # the trajectory must match too
+    cfg = dict(C1, L=30.0, n_agents=300, seed=21, gamma=0.0, kT=0.0)
+    x, v = inputs.initial_state(cfg)
+    v[0:2] = (400.0, 0.0)
+    v[2:4] = (-300.0, 410.0)
+    v[4:6] = (0.0, -401.0)
+    sim = make_sim(dpd, cfg, x, v)
+    Fo = oracle.forces(cfg, x, v, 0)
+    xo, vo, Fo, so = x.astype(np.float64), v.astype(np.float64), Fo, 0
+    for k in range(4):
+        sim.step(1)
+        xo, vo, Fo, so, _ = oracle.step(cfg, xo, vo, Fo, so, 1)
+        xs = host(sim.get_state()[0])
+        cs, ids = sim.cells()
+        cso, idso = oracle.bin_cells(cfg, xs)
+        assert (host(cs) == cso).all() and (host(ids) == idso).all()
+    d = xs.astype(np.float64) - xo
+    d -= cfg["L"] * np.round(d / cfg["L"])
+    assert np.abs(d).max() < 1e-3
+    sim.close()
+
+
 # -------------------------------------------------------------------- forces
 
 FORCE_CASES = [
@@ -322,20 +347,21 @@ def test_reductions_are_exact_sums(dpd):
 
 
 def test_fluctuation_dissipation_on_gpu(dpd):
-    # same protocol as the oracle's pin: three seeds, 50 time units each after
+    # the oracle's pin in the same 80 x 80 box at density 1 (a smaller box keeps
+    # wandering by a few percent), with three seeds and 100 time units each after
     # 50 units of relaxation from the random start
     Ts = []
     for seed in (102, 103, 104):
-        cfg = dict(C1, f_sp=0.0, gamma_s=0.0, seed=seed)
+        cfg = dict(C1, f_sp=0.0, gamma_s=0.0, seed=seed, L=80.0, n_agents=3200)
         x, v = inputs.initial_state(cfg, thermal=True)
         sim = make_sim(dpd, cfg, x, v)
         sim.step(10000)
-        pk = host(sim.step(10000, reduce_every=10))
+        pk = host(sim.step(20000, reduce_every=10))
         n = 2 * cfg["n_agents"]
         Ts.append(2 * pk[:, 2].mean() / (2 * n - 2))
         sim.close()
     print("kinetic temperatures", Ts)
-    assert np.mean(Ts) == pytest.approx(C1["kT"], rel=0.01)
+    assert np.mean(Ts) == pytest.approx(C1["kT"], rel=0.005)
 
 
 # ----------------------------------------------------------- velocity field

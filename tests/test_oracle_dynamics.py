@@ -177,18 +177,20 @@ def test_energy_error_scales_with_dt_squared(oracle_mod):
 def test_fluctuation_dissipation_temperature(oracle_mod):
     # F_p = gamma_s = 0: the DPD thermostat holds T_kin = sum m|v|^2 / (2N - 2) at kT.
     # The random start stores ~2 kT per particle of overlap energy that relaxes
-    # over some 30 time units, and a 50-unit average of T still wanders by ~1%
-    # between seeds (slow structural modes), so three seeds are averaged.
+    # over some 30 time units.  In the 40 x 40 box the kinetic temperature then
+    # keeps wandering by a few percent over tens of time units (slow structural
+    # rearrangements of a system that small); in an 80 x 80 box at the same
+    # density a 50-unit average is steady to ~0.1%, so the pin uses that box.
     Ts = []
-    for seed in (102, 103, 104):
-        cfg = dict(C1, f_sp=0.0, gamma_s=0.0, seed=seed)
+    for seed in (102, 103):
+        cfg = dict(C1, f_sp=0.0, gamma_s=0.0, seed=seed, L=80.0, n_agents=3200)
         x, v = inputs.initial_state(cfg, thermal=True)
         x, v, F = _init(oracle_mod, cfg, x, v)
         x, v, F, s, _ = oracle_mod.step(cfg, x, v, F, 0, 10000)
         _, _, _, _, pk = oracle_mod.step(cfg, x, v, F, s, 10000, every=10)
         n = 2 * cfg["n_agents"]
         Ts.append(2 * pk[:, 2].mean() / (2 * n - 2))
-    assert np.mean(Ts) == pytest.approx(C1["kT"], rel=0.01)
+    assert np.mean(Ts) == pytest.approx(C1["kT"], rel=0.005)
 
 
 def test_trajectory_deterministic_and_resumable(oracle_mod):
