@@ -44,17 +44,25 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_launch_particles: int):
+def measured_traffic():
     """HBM bytes per launch of the pair kernel from the committed rocprofv3
-    counter summary, if it was taken with the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "pair_kernel_dimers_4M_counters.json")
+    counter summary (lines "key: value"), if it was taken with the current
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pair_kernel_dimers_4M_counters.txt")
     if not os.path.exists(path):
         return None
+    d = {}
     with open(path) as f:
-        d = json.load(f)
+        for line in f:
+            k, sep, val = line.partition(":")
+            if sep:
+                d[k.strip()] = val.strip()
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    try:
+        return float(d["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(cfg, x, v, steps: int):
@@ -161,7 +169,7 @@ def main():
     avg_us = 1e3 * pair_ms / max(launches, 1)
     alg = pair_kernel_bytes(N, sim.n_c * sim.n_c)
     achieved = alg / (avg_us * 1e-6) / 1e9
-    traffic = measured_traffic(N)
+    traffic = measured_traffic()
     pkh = pk.cpu().numpy()
     log(f"elapsed {elapsed:.3f} s, {ms_per_step:.4f} ms/step, pair kernel {avg_us:.1f} us avg over "
         f"{launches} launches, {achieved:.0f} GB/s algorithmic; last KE {pkh[max(0, steps // reduce_every - 1), 2]:.1f}")
