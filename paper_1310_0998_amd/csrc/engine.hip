@@ -197,7 +197,11 @@ int fail(dpd_handle* h, int code, const std::string& msg) {
             return fail((h), DPD_EHIP, fmt("kernel launch: %s", hipGetErrorString(e_)));  \
     } while (0)
 
-// cell_start from count (count cleared), then slots sorted by (cell, id).
+// cell_start from count (count cleared) and the slot -> input map.  Within a
+// cell the slots are in arrival order; the pair kernel places each cell's
+// members by id itself.  With id_of_input != NULL every cell is also ordered by
+// id here (only for the state loaded with a given force, which no pair kernel
+// passes through before it is stored).
 int bin_from_counts(dpd_handle* h, const int* id_of_input) {
     const DevParams& P = h->d.P;
     const int G = h->d.n_scan_blocks;
@@ -209,8 +213,9 @@ int bin_from_counts(dpd_handle* h, const int* id_of_input) {
                        (const int*)h->scan_part, h->cs);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
                        (const int*)h->key, (const int*)h->rank, (const int*)h->cs, h->src);
-    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(P.n_cells)), dim3(kBlock), 0, h->stream,
-                       P.n_cells, (const int*)h->cs, h->src, id_of_input);
+    if (id_of_input)
+        hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(P.n_cells)), dim3(kBlock), 0, h->stream,
+                           P.n_cells, (const int*)h->cs, h->src, id_of_input);
     LAUNCHCHK(h);
     return DPD_OK;
 }
@@ -384,7 +389,7 @@ int dpd_set_state(dpd_handle* h, const float* x, const float* v, int64_t step, c
                            (const float2*)x, (const float2*)v, h->Ax, h->Au, h->Aid, h->key,
                            h->rank, h->count, h->status);
         LAUNCHCHK(h);
-        int rc = bin_from_counts(h, h->Aid);
+        int rc = bin_from_counts(h, F ? h->Aid : nullptr);
         if (rc) return rc;
         if (F) {
             hipLaunchKernelGGL(k_gather_state, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
@@ -435,7 +440,7 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
         int *inid = h->Aid, *outid = h->Bid;
         int rec = 0;
         for (int k = 1; k <= n_steps; ++k) {
-            int rc = bin_from_counts(h, inid);
+            int rc = bin_from_counts(h, nullptr);
             if (rc) return rc;
             const bool last = (k == n_steps);
             const bool red = want_pk && (k % reduce_every == 0);
@@ -490,7 +495,7 @@ int dpd_forces(dpd_handle* h, float* F_out) {
         hipLaunchKernelGGL(k_key_rank, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
                            (const float2*)h->Sx, h->key, h->rank, h->count);
         LAUNCHCHK(h);
-        int rc = bin_from_counts(h, h->Sid);
+        int rc = bin_from_counts(h, nullptr);
         if (rc) return rc;
         PairArgs a = {};
         a.cs = h->cs;

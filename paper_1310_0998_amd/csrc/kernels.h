@@ -23,10 +23,10 @@ constexpr int kBlock = 256;  // threads per block of the streaming kernels
 constexpr int kTileX = 8, kTileY = 7;                // default tile (cells)
 constexpr int kTileMax = 8;                          // largest tile side
 constexpr int kLocMax = (kTileMax + 2) * (kTileMax + 2);  // tile + halo cells
-constexpr int kCap = 192;   // staged particles (tile + halo)
-constexpr int kTP = 128;    // tile particles
-constexpr int kEcap = 224;  // kept pairs per tile
-constexpr int kCand = 640;  // half-stencil candidates per tile
+constexpr int kCap = 192;   // staged particles (tile + halo); indices fit a byte, 0xFF = none
+constexpr int kTP = 128;    // tile particles (7-bit index in a kept pair)
+constexpr int kEcap = 256;  // kept pairs per tile
+constexpr int kItems = kCap / kWave;  // staged particles per lane
 
 enum PairMode { MODE_STEP = 0, MODE_FINAL = 1, MODE_FORCES = 2 };
 
@@ -166,6 +166,25 @@ __device__ __forceinline__ void add_agent_force(const DevParams& P, float2 xi, f
     fy += (cb + csp) * dy - P.gamma_s * ui.y;
 }
 
+// Pair-force sums are kept in 64-bit fixed point with 32 fractional bits.
+// Integer addition is associative, so a particle's total does not depend on
+// the order its pairs are added in, and the force on j from a pair is exactly
+// the negation of the force on i.  One term is rounded to 2^-32 (~2e-10);
+// |F| must stay below 2^31 (a non-finite force is flagged separately).
+constexpr double kFixScale = 4294967296.0;        // 2^32
+constexpr double kFixInv = 1.0 / 4294967296.0;    // 2^-32
+
+__device__ __forceinline__ long long to_fixed(float f) {
+    const double d = rint((double)f * kFixScale);   // exact: f has 24 significant bits
+    const double hi = floor(d * kFixInv);
+    const double lo = fma(hi, -kFixScale, d);       // exact, in [0, 2^32)
+    return (long long)(((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ float from_fixed(long long q) {
+    return (float)((double)q * kFixInv);            // (double)q exact for |q| < 2^53
+}
+
 // Finish one particle: kicks, drift, key and outputs at sorted slot g.
 template <int MODE>
 __device__ __forceinline__ void finish_particle(const DevParams& P, const PairArgs& a, int g,
@@ -206,9 +225,10 @@ __device__ __forceinline__ void finish_particle(const DevParams& P, const PairAr
     if (!finite2(xn) || !finite2(un)) atomicOr(a.status, kStatusNonFinite);
 }
 
-// Slow path for a tile whose cells hold more than kCap particles (dense
-// clusters): every particle reads its neighbours straight from global memory,
-// still in (cell, id) order.
+// Slow path for a tile that overflows an LDS capacity (dense clusters): one
+// lane per cell walks the cell's members in id order (the canonical slot order)
+// and sums each member's pairs over the full 3x3 stencil straight from global
+// memory.  The sums are fixed point, so the result is bitwise the fast path's.
 template <int MODE>
 __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int cy0, int tw,
                             int th, double rv[3], bool reduce) {
@@ -217,16 +237,28 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
         const int gx = cx0 + ic % tw, gy = cy0 + ic / tw;
         const int c = gy * nc + gx;
         const int b = a.cs[c], e = a.cs[c + 1];
-        for (int g = b; g < e; ++g) {
-            int p = a.src[g];
-            if ((unsigned)p >= (unsigned)P.N) {
-                atomicOr(a.status, kStatusBinning);
-                p = 0;
+        int last = -1;
+        for (int r = 0; r < e - b; ++r) {
+            // the member with the r-th smallest id (ids are distinct)
+            int g = b, idi = 0x7FFFFFFF, p = 0;
+            for (int g1 = b; g1 < e; ++g1) {
+                int p1 = a.src[g1];
+                if ((unsigned)p1 >= (unsigned)P.N) {
+                    atomicOr(a.status, kStatusBinning);
+                    p1 = 0;
+                }
+                const int id1 = a.idin[p1];
+                if (id1 > last && id1 < idi) {
+                    idi = id1;
+                    g = g1;
+                    p = p1;
+                }
             }
+            last = idi;
             const float2 xi = a.xin[p], ui = a.uin[p];
-            const int idi = a.idin[p], pid = idi ^ 1;
-            float fx = 0.f, fy = 0.f;
-            bool found = false;
+            const int pid = idi ^ 1;
+            long long qx = 0, qy = 0;
+            bool found = false, bad = false;
             float2 xpart = xi;
             for (int oy = -1; oy <= 1; ++oy) {
                 for (int ox = -1; ox <= 1; ++ox) {
@@ -238,20 +270,27 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
                         if ((unsigned)q >= (unsigned)P.N) q = 0;
                         const int idj = a.idin[q];
                         const float2 xj = a.xin[q];
-                        const float dx = minimg_sub(xi.x, xj.x, P);
-                        const float dy = minimg_sub(xi.y, xj.y, P);
                         if (idj == pid) {
                             found = true;
                             xpart = xj;
                             continue;
                         }
+                        const float dx = minimg_sub(xi.x, xj.x, P);
+                        const float dy = minimg_sub(xi.y, xj.y, P);
                         const float gap = cutoff_gap(P, dx, dy);
                         const float r2 = fmaf(dx, dx, dy * dy);
-                        if (interacts(gap, r2))
+                        if (interacts(gap, r2)) {
+                            float fx = 0.f, fy = 0.f;
                             add_pair_force(P, dx, dy, gap, r2, ui, a.uin[q], idi, idj, a.step, fx, fy);
+                            bad |= !(__builtin_isfinite(fx) && __builtin_isfinite(fy));
+                            qx += to_fixed(fx);
+                            qy += to_fixed(fy);
+                        }
                     }
                 }
             }
+            if (bad) atomicOr(a.status, kStatusNonFinite);
+            float fx = from_fixed(qx), fy = from_fixed(qy);
             if (found) {
                 add_agent_force(P, xi, xpart, ui, idi, fx, fy);
             } else {
@@ -259,7 +298,7 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
                 fx -= P.gamma_s * ui.x;
                 fy -= P.gamma_s * ui.y;
             }
-            finish_particle<MODE>(P, a, g, xi, ui, idi, fx, fy, rv, reduce);
+            finish_particle<MODE>(P, a, b + r, xi, ui, idi, fx, fy, rv, reduce);
         }
     }
 }
@@ -291,38 +330,34 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask) {
 }
 
 // The fused pair / agent / integrator kernel: one 64-lane wavefront per tile of
-// up to kTileX x kTileY cells, the tile and a one-cell halo staged in LDS in
-// (cell, id) order.  Phases, each in a fixed order:
-//   A1 every tile particle lists its half-stencil candidates: the rest of its
-//      own cell and the cell to its right, the row above, and any halo cells of
-//      its 3x3 stencil - so each interior pair is listed once (by its earlier
-//      slot) and each halo pair once; the lists are concatenated in particle
-//      order;
-//   A2 the wavefront tests the candidates 64 at a time and keeps the pairs
-//      within r_c in list order (so each particle's kept pairs are contiguous),
-//      recording bonded partners both ways;
-//   B  one force evaluation per kept pair (Eqs. 2.2-2.4);
-//   C  each particle adds its kept pairs in order, subtracts the pairs kept by
-//      interior partners in pair order (Newton's third law), adds the agent
-//      forces and finishes the step.
+// up to kTileX x kTileY cells, the tile and a one-cell halo staged in LDS.
+//   S  stage: cell counts from cell_start (one scan gives the staged and the
+//      tile offsets of every local cell); each staged particle is gathered
+//      through src and placed at its rank by id within its cell, so the LDS
+//      order is the canonical (cell, id) order;
+//   A  every tile particle tests the staged particles of its 3x3 stencil (three
+//      contiguous row segments) and keeps a pair if the other particle is in
+//      the halo or comes later in the canonical order, so each pair within the
+//      tile is kept once; kept pairs are compacted by ballot; the bonded
+//      partner is recorded;
+//   B  one force evaluation per kept pair (Eqs. 2.2-2.4), added in fixed point
+//      to the first particle and subtracted from the second (Newton's third
+//      law) with LDS integer atomics - exact, so the order does not matter;
+//   C  every tile particle adds its agent forces and finishes the step.
 // A tile that overflows an LDS capacity is processed by tile_global instead.
 template <int MODE>
 __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int reduce) {
-    __shared__ int s_ofs[kLocMax + 1];
-    __shared__ int s_gbeg[kLocMax];
-    __shared__ int s_tofs[kLocMax];
-    __shared__ unsigned char s_lcell[kCap];
-    __shared__ float4 s_rec[kCap];          // x, y, id, tile index (0xFF: halo)
+    __shared__ int s_ofs[kLocMax + 1];       // first staged index of each local cell
+    __shared__ int s_gbeg[kLocMax];          // first global slot of each local cell
+    __shared__ unsigned char s_tofs[kLocMax];  // first tile index of each local cell
+    __shared__ unsigned char s_lcell[kCap];  // local cell of each staged index
+    __shared__ float4 s_rec[kCap];           // x, y, id, tile index (0xFF: halo)
     __shared__ float2 s_u[kCap];
-    __shared__ unsigned char s_tslot[kTP];
-    __shared__ unsigned char s_partner[kTP];
-    __shared__ int s_fcnt[kTP + 1];         // kept pairs per owner -> offsets
-    __shared__ int s_bcnt[kTP + 1];         // pairs as interior partner -> offsets
-    __shared__ int s_bfill[kTP];
-    __shared__ unsigned short s_cand[kCand];
-    __shared__ unsigned short s_pair[kEcap];
-    __shared__ unsigned char s_bkt[kEcap];
-    __shared__ float2 s_f[kEcap];
+    __shared__ unsigned char s_tslot[kTP];   // tile index -> staged index
+    __shared__ unsigned char s_partner[kTP]; // tile index -> staged index of the partner
+    __shared__ unsigned short s_pair[kEcap]; // kept pair: tile index << 8 | staged index
+    __shared__ long long s_acc[kTP][2];      // fixed-point pair-force sums
+    int* s_tmpid = reinterpret_cast<int*>(&s_acc[0][0]);  // staging only: ids in arrival order
 
     // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs, so give
     // each XCD a contiguous band of tiles (neighbouring halos share its L2).
@@ -340,190 +375,181 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
     const bool edge = (cx0 == 0) || (cx0 + tw >= P.nc) || (cy0 == 0) || (cy0 + th >= P.nc);
     const int lane = threadIdx.x;
 
-    // cell counts of the tile + halo, two local cells per lane
-    int cnt[2], tcnt[2];
+    // ---- S1: counts of the two local cells 2*lane and 2*lane + 1
+    int cnt[2] = {0, 0};
+    bool tcell[2] = {false, false};
+    bool big = false;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int lc = lane + h * kWave;
-        cnt[h] = 0;
-        tcnt[h] = 0;
+        const int lc = 2 * lane + h;
         if (lc < nloc) {
             const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
             const int c = wrap_cell(cy0 - 1 + ly, P.nc) * P.nc + wrap_cell(cx0 - 1 + lx, P.nc);
             const int b = a.cs[c];
-            cnt[h] = a.cs[c + 1] - b;
+            const int n = a.cs[c + 1] - b;
             s_gbeg[lc] = b;
-            if (lx >= 1 && lx <= tw && ly >= 1 && ly <= th) tcnt[h] = cnt[h];
+            big |= (n > kCap) || (n < 0);
+            cnt[h] = min(max(n, 0), kCap);
+            tcell[h] = (lx >= 1 && lx <= tw && ly >= 1 && ly <= th);
         }
     }
-    int t0, t1, u0, u1;
-    const int e0 = wave_scan_excl(cnt[0], t0), e1 = wave_scan_excl(cnt[1], t1);
-    const int f0 = wave_scan_excl(tcnt[0], u0), f1 = wave_scan_excl(tcnt[1], u1);
-    const int total = t0 + t1, ntile = u0 + u1;
-    if (lane < nloc) { s_ofs[lane] = e0; s_tofs[lane] = f0; }
-    if (lane + kWave < nloc) { s_ofs[lane + kWave] = t0 + e1; s_tofs[lane + kWave] = u0 + f1; }
+    // staged counts in the low 16 bits, tile counts in the high 16 (each <= 100 * kCap)
+    const int v0 = cnt[0] + (tcell[0] ? cnt[0] << 16 : 0);
+    const int v1 = cnt[1] + (tcell[1] ? cnt[1] << 16 : 0);
+    int tot;
+    const int ex = wave_scan_excl(v0 + v1, tot);
+    const int total = tot & 0xFFFF, ntile = tot >> 16;
+    const bool fits = !__any(big) && total <= kCap && ntile <= kTP;
+    if (2 * lane < nloc) {
+        s_ofs[2 * lane] = ex & 0xFFFF;
+        s_tofs[2 * lane] = (unsigned char)min(ex >> 16, 255);
+    }
+    if (2 * lane + 1 < nloc) {
+        s_ofs[2 * lane + 1] = (ex + v0) & 0xFFFF;
+        s_tofs[2 * lane + 1] = (unsigned char)min((ex + v0) >> 16, 255);
+    }
     if (lane == 0) s_ofs[nloc] = total;
     __syncthreads();
 
     double rv[3] = {0.0, 0.0, 0.0};
     bool done = false;
-    if (total <= kCap && ntile <= kTP) {
+    if (fits) {
+        // ---- S2: staged index -> local cell
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int lc = lane + h * kWave;
-            if (lc < nloc)
-                for (int q = s_ofs[lc]; q < s_ofs[lc] + cnt[h]; ++q) s_lcell[q] = (unsigned char)lc;
+            const int lc = 2 * lane + h;
+            if (lc < nloc) {
+                const int o = s_ofs[lc];
+                for (int q = o; q < o + cnt[h]; ++q) s_lcell[q] = (unsigned char)lc;
+            }
         }
         __syncthreads();
-        for (int q = lane; q < total; q += kWave) {
-            const int lc = s_lcell[q];
-            int p = a.src[s_gbeg[lc] + (q - s_ofs[lc])];
-            if ((unsigned)p >= (unsigned)P.N) {
-                atomicOr(a.status, kStatusBinning);
-                p = 0;
+        // ---- S3: gather in arrival order
+        float2 xq[kItems], uq[kItems];
+        int idq[kItems], lcq[kItems];
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int q = r * kWave + lane;
+            idq[r] = 0;
+            lcq[r] = 0;
+            xq[r] = make_float2(0.f, 0.f);
+            uq[r] = make_float2(0.f, 0.f);
+            if (q < total) {
+                const int lc = s_lcell[q];
+                int p = a.src[s_gbeg[lc] + (q - s_ofs[lc])];
+                if ((unsigned)p >= (unsigned)P.N) {
+                    atomicOr(a.status, kStatusBinning);
+                    p = 0;
+                }
+                lcq[r] = lc;
+                idq[r] = a.idin[p];
+                xq[r] = a.xin[p];
+                uq[r] = a.uin[p];
+                s_tmpid[q] = idq[r];
             }
-            const float2 xq = a.xin[p];
-            s_u[q] = a.uin[p];
-            const int idq = a.idin[p];
-            const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
-            int ti = 0xFF;
-            if (lx >= 1 && lx <= tw && ly >= 1 && ly <= th) {
-                ti = s_tofs[lc] + (q - s_ofs[lc]);
-                s_tslot[ti] = (unsigned char)q;
-                s_partner[ti] = 0xFF;
-            }
-            s_rec[q] = make_float4(xq.x, xq.y, __int_as_float(idq), __int_as_float(ti));
-        }
-        for (int k = lane; k <= ntile; k += kWave) {
-            s_fcnt[k] = 0;
-            s_bcnt[k] = 0;
-            if (k < ntile) s_bfill[k] = 0;
         }
         __syncthreads();
+        // ---- S4: place every particle at its rank by id within its cell
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int q = r * kWave + lane;
+            if (q < total) {
+                const int lc = lcq[r];
+                const int b = s_ofs[lc], e = s_ofs[lc + 1];
+                int rank = 0;
+                for (int t = b; t < e; ++t) rank += (s_tmpid[t] < idq[r]) ? 1 : 0;
+                const int qs = b + rank;
+                const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
+                int ti = 0xFF;
+                if (lx >= 1 && lx <= tw && ly >= 1 && ly <= th) {
+                    ti = s_tofs[lc] + rank;
+                    s_tslot[ti] = (unsigned char)qs;
+                }
+                s_rec[qs] = make_float4(xq[r].x, xq[r].y, __int_as_float(idq[r]), __int_as_float(ti));
+                s_u[qs] = uq[r];
+            }
+        }
+        __syncthreads();
+        for (int k = lane; k < ntile; k += kWave) {
+            s_acc[k][0] = 0;
+            s_acc[k][1] = 0;
+        }
 
-        // ---- phase A1: half-stencil candidate lists, concatenated in particle order
+        // ---- A: candidate test over the 3x3 stencil, kept pairs in order
         const int rounds = (ntile + kWave - 1) / kWave;
-        int C = 0;
+        int E = 0;
         for (int r = 0; r < rounds; ++r) {
             const int k = r * kWave + lane;
-            int b0 = 0, n0 = 0, b1 = 0, n1 = 0, b2 = 0, n2 = 0, b3 = 0, n3 = 0, b4 = 0, n4 = 0;
-            if (k < ntile) {
-                const int si = s_tslot[k];
+            const bool act = k < ntile;
+            int si = 0, b0 = 0, n0 = 0, b1 = 0, n1 = 0, b2 = 0, n2 = 0;
+            float4 ri = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (act) {
+                si = s_tslot[k];
                 const int lc = s_lcell[si];
                 const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
-                const int up = (ly + 1) * W, me = ly * W, dn = (ly - 1) * W;
-                b0 = s_ofs[up + lx - 1];                 // row above, three cells
-                n0 = s_ofs[up + lx + 2] - b0;
-                b1 = si + 1;                             // rest of own cell + right cell
-                n1 = s_ofs[me + lx + 2] - b1;
-                if (lx == 1) {                           // left halo cell of own row
-                    b2 = s_ofs[me];
-                    n2 = s_ofs[me + 1] - b2;
-                }
-                if (ly == 1) {                           // row below is halo: three cells
-                    b3 = s_ofs[dn + lx - 1];
-                    n3 = s_ofs[dn + lx + 2] - b3;
-                } else {
-                    if (lx == 1) {                       // left halo cell of row below
-                        b3 = s_ofs[dn];
-                        n3 = s_ofs[dn + 1] - b3;
-                    }
-                    if (lx == tw) {                      // right halo cell of row below
-                        b4 = s_ofs[dn + tw + 1];
-                        n4 = s_ofs[dn + tw + 2] - b4;
-                    }
-                }
+                const int dn = (ly - 1) * W + lx - 1, me = ly * W + lx - 1, up = (ly + 1) * W + lx - 1;
+                b0 = s_ofs[dn];
+                n0 = s_ofs[dn + 3] - b0;
+                b1 = s_ofs[me];
+                n1 = s_ofs[me + 3] - b1;
+                b2 = s_ofs[up];
+                n2 = s_ofs[up + 3] - b2;
+                ri = s_rec[si];
             }
-            int ctot;
-            const int off = C + wave_scan_excl(n0 + n1 + n2 + n3 + n4, ctot);
-            if (C + ctot <= kCand && k < ntile) {
-                const unsigned short kw = (unsigned short)(k << 8);
-                int o = off;
-                for (int t = 0; t < n0; ++t) s_cand[o++] = kw | (unsigned short)(b0 + t);
-                for (int t = 0; t < n1; ++t) s_cand[o++] = kw | (unsigned short)(b1 + t);
-                for (int t = 0; t < n2; ++t) s_cand[o++] = kw | (unsigned short)(b2 + t);
-                for (int t = 0; t < n3; ++t) s_cand[o++] = kw | (unsigned short)(b3 + t);
-                for (int t = 0; t < n4; ++t) s_cand[o++] = kw | (unsigned short)(b4 + t);
-            }
-            C += ctot;
-        }
-        __syncthreads();
-
-        // ---- phase A2: test the candidates 64 at a time, keep pairs in list order
-        int E = 0;
-        if (C <= kCand) {
-            for (int c0 = 0; c0 < C; c0 += kWave) {
-                const int c = c0 + lane;
-                bool keep = false;
-                int w = 0, own = 0, tj = 0xFF;
-                if (c < C) {
-                    w = s_cand[c];
-                    own = w >> 8;
-                    const int j = w & 0xFF, si = s_tslot[own];
-                    const float4 ri = s_rec[si], rj = s_rec[j];
-                    tj = __float_as_int(rj.w);
-                    if ((__float_as_int(ri.z) ^ 1) == __float_as_int(rj.z)) {
-                        s_partner[own] = (unsigned char)j;
-                        if (tj != 0xFF) s_partner[tj] = (unsigned char)si;
-                    } else {
-                        const float dx = edge ? minimg_sub(ri.x, rj.x, P) : ri.x - rj.x;
-                        const float dy = edge ? minimg_sub(ri.y, rj.y, P) : ri.y - rj.y;
-                        keep = interacts(cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy));
-                    }
-                }
+            const int n01 = n0 + n1, n = n01 + n2;
+            const int nmax = __builtin_amdgcn_readfirstlane(wave_max(n));
+            const int idi = __float_as_int(ri.z), pid = idi ^ 1;
+            int partner = 0xFF;
+            for (int t = 0; t < nmax; ++t) {
+                int j = (t < n0) ? b0 + t : ((t < n01) ? b1 + (t - n0) : b2 + (t - n01));
+                const bool valid = (t < n) && (j != si);
+                j = valid ? j : si;
+                const float4 rj = s_rec[j];
+                const int tj = __float_as_int(rj.w);
+                const bool isp = valid && (__float_as_int(rj.z) == pid);
+                partner = isp ? j : partner;
+                const float dx = edge ? minimg_sub(ri.x, rj.x, P) : ri.x - rj.x;
+                const float dy = edge ? minimg_sub(ri.y, rj.y, P) : ri.y - rj.y;
+                const bool keep = valid && !isp && (tj == 0xFF || j > si) &&
+                                  interacts(cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy));
                 const unsigned long long m = __ballot(keep);
                 if (keep) {
                     const int pos = E + lanes_below(m);
-                    if (pos < kEcap) {
-                        s_pair[pos] = (unsigned short)(((tj != 0xFF) << 15) | w);
-                        atomicAdd(&s_fcnt[own], 1);
-                        if (tj != 0xFF) atomicAdd(&s_bcnt[tj], 1);
-                    }
+                    if (pos < kEcap) s_pair[pos] = (unsigned short)((k << 8) | j);
                 }
                 E += __popcll(m);
             }
+            if (act) s_partner[k] = (unsigned char)partner;
         }
         __syncthreads();
 
-        if (C <= kCand && E <= kEcap) {
-            // ---- phase B: one force per kept pair
+        if (E <= kEcap) {
+            // ---- B: one force per kept pair, exact fixed-point sums
+            bool bad = false;
             for (int e = lane; e < E; e += kWave) {
                 const int w = s_pair[e];
-                const int own = (w >> 8) & 0x7F, j = w & 0xFF;
-                const int so = s_tslot[own];
+                const int k = w >> 8, j = w & 0xFF;
+                const int so = s_tslot[k];
                 const float4 ro = s_rec[so], rj = s_rec[j];
                 const float dx = edge ? minimg_sub(ro.x, rj.x, P) : ro.x - rj.x;
                 const float dy = edge ? minimg_sub(ro.y, rj.y, P) : ro.y - rj.y;
                 float fx = 0.f, fy = 0.f;
                 add_pair_force(P, dx, dy, cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy), s_u[so],
                                s_u[j], __float_as_int(ro.z), __float_as_int(rj.z), a.step, fx, fy);
-                s_f[e] = make_float2(fx, fy);
-            }
-            {
-                // owner-run offsets and partner-bucket offsets (two per lane)
-                const int a0 = lane < ntile ? s_fcnt[lane] : 0;
-                const int a1 = lane + kWave < ntile ? s_fcnt[lane + kWave] : 0;
-                const int c0 = lane < ntile ? s_bcnt[lane] : 0;
-                const int c1 = lane + kWave < ntile ? s_bcnt[lane + kWave] : 0;
-                int sa0, sa1, s0, s1;
-                const int y0 = wave_scan_excl(a0, sa0), y1 = wave_scan_excl(a1, sa1);
-                const int x0 = wave_scan_excl(c0, s0), x1 = wave_scan_excl(c1, s1);
-                __syncthreads();
-                if (lane < ntile) { s_fcnt[lane] = y0; s_bcnt[lane] = x0; }
-                if (lane + kWave < ntile) { s_fcnt[lane + kWave] = sa0 + y1; s_bcnt[lane + kWave] = s0 + x1; }
-                if (lane == 0) { s_fcnt[ntile] = sa0 + sa1; s_bcnt[ntile] = s0 + s1; }
-            }
-            __syncthreads();
-            for (int e = lane; e < E; e += kWave) {
-                const int w = s_pair[e];
-                if (w & 0x8000) {
-                    const int tj = __float_as_int(s_rec[w & 0xFF].w);
-                    s_bkt[s_bcnt[tj] + atomicAdd(&s_bfill[tj], 1)] = (unsigned char)e;
+                bad |= !(__builtin_isfinite(fx) && __builtin_isfinite(fy));
+                const long long qx = to_fixed(fx), qy = to_fixed(fy);
+                atomicAdd((unsigned long long*)&s_acc[k][0], (unsigned long long)qx);
+                atomicAdd((unsigned long long*)&s_acc[k][1], (unsigned long long)qy);
+                const int tj = __float_as_int(rj.w);
+                if (tj != 0xFF) {
+                    atomicAdd((unsigned long long*)&s_acc[tj][0], (unsigned long long)(-qx));
+                    atomicAdd((unsigned long long*)&s_acc[tj][1], (unsigned long long)(-qy));
                 }
             }
+            if (bad) atomicOr(a.status, kStatusNonFinite);
             __syncthreads();
 
-            // ---- phase C: fixed-order sums, agent forces, integration
+            // ---- C: agent forces and integration, tile particles in canonical order
             for (int r = 0; r < rounds; ++r) {
                 const int k = r * kWave + lane;
                 if (k >= ntile) continue;
@@ -532,28 +558,10 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 const float4 ri = s_rec[si];
                 const float2 xi = make_float2(ri.x, ri.y), ui = s_u[si];
                 const int idi = __float_as_int(ri.z);
-                float fx = 0.f, fy = 0.f;
-                for (int e = s_fcnt[k]; e < s_fcnt[k + 1]; ++e) {  // own pairs, list order
-                    const float2 f = s_f[e];
-                    fx += f.x;
-                    fy += f.y;
-                }
-                const int b = s_bcnt[k], en = s_bcnt[k + 1];
-                int last = -1;
-                for (int q0 = b; q0 < en; ++q0) {        // partners' pairs by pair index
-                    int best = 0x7FFFFFFF;
-                    for (int q = b; q < en; ++q) {
-                        const int e = s_bkt[q];
-                        if (e > last && e < best) best = e;
-                    }
-                    const float2 f = s_f[best];
-                    fx -= f.x;
-                    fy -= f.y;
-                    last = best;
-                }
-                const int jpk = s_partner[k];
-                if (jpk != 0xFF) {
-                    const float4 rp = s_rec[jpk];
+                float fx = from_fixed(s_acc[k][0]), fy = from_fixed(s_acc[k][1]);
+                const int jp = s_partner[k];
+                if (jp != 0xFF) {
+                    const float4 rp = s_rec[jp];
                     add_agent_force(P, xi, make_float2(rp.x, rp.y), ui, idi, fx, fy);
                 } else {
                     atomicOr(a.status, kStatusBond);
