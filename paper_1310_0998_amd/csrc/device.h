@@ -24,6 +24,9 @@ struct DevParams {
     int tile_x;       // pair-kernel tile width (cells)
     int tile_y;       // pair-kernel tile height (cells)
     int ntx, nty;     // tiles per side
+    int wmul_full;    // ceil(2^16 / (tile_x + 2)): local cell -> row by multiply-shift
+    int wmul_last;    // the same for the narrower last tile column
+    double inv_ntx;   // 1 / ntx: tile row = floor((tile + 1/2) / ntx) by one multiply
     int noise_kind;   // 0 Gaussian, 1 uniform
     int rng_kind;     // 0 Philox4x32-10, 1 Philox2x32-10
     float L;          // box side (FP32)

@@ -24,7 +24,7 @@ struct Layout {
     size_t off_Sx, off_Sv, off_SF, off_Sid;
     size_t off_Ax, off_Au, off_Aid, off_Bx, off_Bu, off_Bid;
     size_t off_key, off_rank, off_src, off_count, off_cs;
-    size_t off_scan_part, off_red, off_Fs, off_binacc, off_status;
+    size_t off_scan_part, off_red, off_Fs, off_binacc, off_status, off_ovf;
     size_t total;
 };
 
@@ -92,6 +92,14 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     P.tile_y = std::min(p->tile ? p->tile : kTileY, P.nc - 2);
     P.ntx = (P.nc + P.tile_x - 1) / P.tile_x;
     P.nty = (P.nc + P.tile_y - 1) / P.tile_y;
+    {
+        const int w_full = P.tile_x + 2, w_last = (P.nc - (P.ntx - 1) * P.tile_x) + 2;
+        P.wmul_full = (65536 + w_full - 1) / w_full;
+        P.wmul_last = (65536 + w_last - 1) / w_last;
+        // (tile + 1/2) / ntx lies at least 1/(2 ntx) >= 2^-17 from an integer, far
+        // beyond the 2^-21 error of the product for tile < 2^31
+        P.inv_ntx = 1.0 / (double)P.ntx;
+    }
     P.noise_kind = p->noise_kind;
     P.rng_kind = p->rng_kind;
     P.L = (float)p->L;
@@ -147,6 +155,7 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     L.off_Fs = take(N * 8);
     L.off_binacc = take((size_t)d->bin_M_max * d->bin_M_max * 3 * 8);
     L.off_status = take(16);
+    L.off_ovf = take(((size_t)d->n_tiles + 1) * 4);
     L.total = o;
     return DPD_OK;
 }
@@ -163,6 +172,7 @@ struct dpd_handle {
     float2 *Sx, *Sv, *SF, *Ax, *Au, *Bx, *Bu, *Fs;
     int *Sid, *Aid, *Bid, *key, *rank, *src, *count, *cs, *scan_part;
     unsigned* status;
+    int* ovf;  // [0]: count of tiles left to the overflow kernel, then their indices
     double* red;
     long long* binacc;
     int64_t step;
@@ -208,7 +218,7 @@ int bin_from_counts(dpd_handle* h, const int* id_of_input) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(G), dim3(kBlock), 0, h->stream, (const int*)h->count,
                        P.n_cells, h->scan_part);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, h->stream, h->scan_part, G,
-                       h->cs + P.n_cells);
+                       h->cs + P.n_cells, h->ovf);
     hipLaunchKernelGGL(k_scan_final, dim3(G), dim3(kBlock), 0, h->stream, h->count, P.n_cells,
                        (const int*)h->scan_part, h->cs);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
@@ -235,12 +245,15 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
         ev = h->ev_used++;
         HIPCHK(h, hipEventRecord(h->ev_start[ev], h->stream));
     }
+    PairArgs b = a;
+    b.ovf_count = h->ovf;
+    b.ovf_list = h->ovf + 1;
     if (mode == MODE_STEP)
-        hipLaunchKernelGGL(k_pair<MODE_STEP>, dim3(G), dim3(kWave), 0, h->stream, P, a, (int)reduce);
+        hipLaunchKernelGGL(k_pair<MODE_STEP>, dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
     else if (mode == MODE_FINAL)
-        hipLaunchKernelGGL(k_pair<MODE_FINAL>, dim3(G), dim3(kWave), 0, h->stream, P, a, (int)reduce);
+        hipLaunchKernelGGL(k_pair<MODE_FINAL>, dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
     else
-        hipLaunchKernelGGL(k_pair<MODE_FORCES>, dim3(G), dim3(kWave), 0, h->stream, P, a, 0);
+        hipLaunchKernelGGL(k_pair<MODE_FORCES>, dim3(G), dim3(kWave), 0, h->stream, P, b, 0);
     LAUNCHCHK(h);
     if (h->profiling) {
         HIPCHK(h, hipEventRecord(h->ev_stop[ev], h->stream));
@@ -255,6 +268,15 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
             h->ev_used = 0;
         }
     }
+    // tiles over an LDS capacity (dense clusters), if any
+    const int Go = std::min(G, 2048);
+    if (mode == MODE_STEP)
+        hipLaunchKernelGGL(k_pair_overflow<MODE_STEP>, dim3(Go), dim3(kWave), 0, h->stream, P, b, (int)reduce);
+    else if (mode == MODE_FINAL)
+        hipLaunchKernelGGL(k_pair_overflow<MODE_FINAL>, dim3(Go), dim3(kWave), 0, h->stream, P, b, (int)reduce);
+    else
+        hipLaunchKernelGGL(k_pair_overflow<MODE_FORCES>, dim3(Go), dim3(kWave), 0, h->stream, P, b, 0);
+    LAUNCHCHK(h);
     return DPD_OK;
 }
 
@@ -345,6 +367,7 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
         h->Fs = (float2*)(w + L.off_Fs);
         h->binacc = (long long*)(w + L.off_binacc);
         h->status = (unsigned*)(w + L.off_status);
+        h->ovf = (int*)(w + L.off_ovf);
         h->step = 0;
         h->have_state = false;
         h->err = "no error";
@@ -356,6 +379,7 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(d.P.n_cells)), dim3(kBlock), 0, h->stream,
                            h->count, 0, (long long)d.P.n_cells);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, (int*)h->status, 0, 4LL);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, h->ovf, 0, 1LL);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             std::string m = fmt("kernel launch: %s", hipGetErrorString(e));
@@ -559,6 +583,32 @@ int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode, float* 
     if (!std::isfinite(eps)) return fail(h, DPD_EINVAL, "eps must be finite");
     try {
         const DevParams& P = h->d.P;
+        // 64-bit fixed point: |v| <= 2^16 and <= 2^ceil(log2 n) contributors per bin
+        const long long n_src = mode == 0 ? P.N : P.N / 2;
+        int lg = 0;
+        while ((1LL << lg) < n_src + 1) ++lg;
+        const int S = std::min(32, 46 - lg);
+        const double qscale = std::ldexp(1.0, S);
+        if (mode == 0 && eps <= 0.0 && M <= 2048) {
+            // plain bins of particle velocities: one block per grid row, read
+            // straight from the canonical state
+            BinRowArgs r;
+            r.x = h->Sx;
+            r.v = h->Sv;
+            r.cs = h->cs;
+            r.u = (float2*)u_out;
+            r.n = (int*)n_out;
+            r.status = h->status;
+            r.M = M;
+            r.nc = P.nc;
+            r.L = h->p.L;
+            r.inv_dx = (double)M / h->p.L;
+            r.qscale = qscale;
+            r.vmax = 65536.0;
+            hipLaunchKernelGGL(k_bin_rows, dim3(M), dim3(kBinRowBlock), (size_t)M * 24, h->stream, r);
+            LAUNCHCHK(h);
+            return DPD_OK;
+        }
         // id-order copies of x and v into the scratch buffers
         hipLaunchKernelGGL(k_unpermute, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
                            (const int*)h->Sid, (const float2*)h->Sx, h->Bx);
@@ -580,12 +630,7 @@ int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode, float* 
         b.inv_dx = (double)M / h->p.L;
         b.dx = h->p.L / (double)M;
         b.eps = eps;
-        // 64-bit fixed point: |v| <= 2^16 and <= 2^ceil(log2 n) contributors per bin
-        int lg = 0;
-        while ((1LL << lg) < (long long)b.n_src + 1) ++lg;
-        int S = 46 - lg;
-        if (S > 32) S = 32;
-        b.qscale = std::ldexp(1.0, S);
+        b.qscale = qscale;
         b.vmax = 65536.0;
         hipLaunchKernelGGL(k_bin_accum, dim3(grid_for(b.n_src)), dim3(kBlock), 0, h->stream, b);
         hipLaunchKernelGGL(k_bin_finalize, dim3(grid_for(nbin)), dim3(kBlock), 0, h->stream,

@@ -45,6 +45,8 @@ struct PairArgs {
     float2* Fout;       // FINAL/FORCES: total force
     double* red;        // 3 doubles per tile (sum v_x, sum v_y, sum |v|^2) or null
     unsigned* status;
+    int* ovf_count;     // tiles handed to the global-memory kernel (cleared by k_scan_top)
+    int* ovf_list;      // their tile indices
     uint32_t step;      // step number of the force evaluation (mod 2^32)
 };
 
@@ -329,6 +331,35 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask) {
                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
+// Cell origin and size of tile t (row-major tiles of tile_x x tile_y cells).
+struct TileGeom {
+    int cx0, cy0, tw, th;
+};
+
+__device__ __forceinline__ TileGeom tile_geom(const DevParams& P, int t) {
+    TileGeom g;
+    const int ty = (int)(((double)t + 0.5) * P.inv_ntx), tx = t - ty * P.ntx;
+    g.cx0 = tx * P.tile_x;
+    g.cy0 = ty * P.tile_y;
+    g.tw = min(P.tile_x, P.nc - g.cx0);
+    g.th = min(P.tile_y, P.nc - g.cy0);
+    return g;
+}
+
+// Fixed-order sum of the per-lane partials of a 64-lane tile into red[3 t].
+__device__ __forceinline__ void tile_reduce(const PairArgs& a, int t, double rv[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) rv[k] += __shfl_down(rv[k], o, kWave);
+    }
+    if (threadIdx.x == 0) {
+        a.red[3 * t + 0] = rv[0];
+        a.red[3 * t + 1] = rv[1];
+        a.red[3 * t + 2] = rv[2];
+    }
+}
+
 // The fused pair / agent / integrator kernel: one 64-lane wavefront per tile of
 // up to kTileX x kTileY cells, the tile and a one-cell halo staged in LDS.
 //   S  stage: cell counts from cell_start (one scan gives the staged and the
@@ -355,9 +386,14 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
     __shared__ float2 s_u[kCap];
     __shared__ unsigned char s_tslot[kTP];   // tile index -> staged index
     __shared__ unsigned char s_partner[kTP]; // tile index -> staged index of the partner
-    __shared__ unsigned short s_pair[kEcap]; // kept pair: tile index << 8 | staged index
-    __shared__ long long s_acc[kTP][2];      // fixed-point pair-force sums
-    int* s_tmpid = reinterpret_cast<int*>(&s_acc[0][0]);  // staging only: ids in arrival order
+    __shared__ unsigned short s_pair[kEcap]; // kept pair: staged index of the tile particle << 8 | other
+    // one buffer, two lifetimes: ids in arrival order while staging, fixed-point
+    // force sums after
+    constexpr int kPhaseBytes = kTP * 16;
+    static_assert(kPhaseBytes >= kCap * 4, "phase buffer too small");
+    __shared__ __align__(16) unsigned char s_phase[kPhaseBytes];
+    int* s_tmpid = reinterpret_cast<int*>(s_phase);                       // [kCap]
+    long long (*s_acc)[2] = reinterpret_cast<long long (*)[2]>(s_phase);  // [kTP][2]
 
     // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs, so give
     // each XCD a contiguous band of tiles (neighbouring halos share its L2).
@@ -366,12 +402,11 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
     const int xcd = bid & 7, kk = bid >> 3;
     const int per = nt >> 3, rem = nt & 7;
     const int tile = xcd * per + min(xcd, rem) + kk;
-    const int ty = tile / P.ntx, tx = tile - ty * P.ntx;
-    const int cx0 = tx * P.tile_x, cy0 = ty * P.tile_y;
-    const int tw = min(P.tile_x, P.nc - cx0), th = min(P.tile_y, P.nc - cy0);
+    const TileGeom G = tile_geom(P, tile);
+    const int cx0 = G.cx0, cy0 = G.cy0, tw = G.tw, th = G.th;
     const int W = tw + 2, nloc = W * (th + 2);
     // local cell -> (lx, ly) by multiply-shift: exact for lc < 128 and W <= 10
-    const int wmul = (65536 + W - 1) / W;
+    const int wmul = (cx0 + tw == P.nc) ? P.wmul_last : P.wmul_full;
     const bool edge = (cx0 == 0) || (cx0 + tw >= P.nc) || (cy0 == 0) || (cy0 + th >= P.nc);
     const int lane = threadIdx.x;
 
@@ -384,7 +419,8 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
         const int lc = 2 * lane + h;
         if (lc < nloc) {
             const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
-            const int c = wrap_cell(cy0 - 1 + ly, P.nc) * P.nc + wrap_cell(cx0 - 1 + lx, P.nc);
+            const int c = (int)__umul24((unsigned)wrap_cell(cy0 - 1 + ly, P.nc), (unsigned)P.nc) +
+                          wrap_cell(cx0 - 1 + lx, P.nc);
             const int b = a.cs[c];
             const int n = a.cs[c + 1] - b;
             s_gbeg[lc] = b;
@@ -464,73 +500,97 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 if (lx >= 1 && lx <= tw && ly >= 1 && ly <= th) {
                     ti = s_tofs[lc] + rank;
                     s_tslot[ti] = (unsigned char)qs;
+                    s_partner[ti] = 0xFF;
                 }
                 s_rec[qs] = make_float4(xq[r].x, xq[r].y, __int_as_float(idq[r]), __int_as_float(ti));
                 s_u[qs] = uq[r];
             }
         }
         __syncthreads();
-        for (int k = lane; k < ntile; k += kWave) {
-            s_acc[k][0] = 0;
-            s_acc[k][1] = 0;
-        }
-
-        // ---- A: candidate test over the 3x3 stencil, kept pairs in order
+        // ---- A: every tile particle tests its half stencil in one loop over up
+        // to three ranges of staged indices:
+        //   own row: the rest of the own cell and the cell to the right (from the
+        //            left neighbour on when that is a halo cell);
+        //   row above: the three cells of the stencil;
+        //   row below: its three cells where they include halo cells (first tile
+        //            row, first or last tile column).
+        // A pair is kept from a particle if the other one is in the halo or later
+        // in the canonical order, so each pair inside the tile is kept once and
+        // each tile-halo pair once, from the tile side.  The bonded partner is
+        // recorded for both members.
         const int rounds = (ntile + kWave - 1) / kWave;
         int E = 0;
         for (int r = 0; r < rounds; ++r) {
             const int k = r * kWave + lane;
-            const bool act = k < ntile;
-            int si = 0, b0 = 0, n0 = 0, b1 = 0, n1 = 0, b2 = 0, n2 = 0;
+            int si = 0, b0 = 0, n0 = 0, b1 = 0, n01 = 0, b2 = 0, n = 0;
             float4 ri = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (act) {
+            if (k < ntile) {
                 si = s_tslot[k];
                 const int lc = s_lcell[si];
                 const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
                 const int dn = (ly - 1) * W + lx - 1, me = ly * W + lx - 1, up = (ly + 1) * W + lx - 1;
-                b0 = s_ofs[dn];
-                n0 = s_ofs[dn + 3] - b0;
-                b1 = s_ofs[me];
-                n1 = s_ofs[me + 3] - b1;
-                b2 = s_ofs[up];
-                n2 = s_ofs[up + 3] - b2;
+                b0 = (lx == 1) ? s_ofs[me] : si + 1;
+                n0 = s_ofs[me + 3] - b0;
+                const int bu = s_ofs[up];
+                n01 = n0 + (s_ofs[up + 3] - bu);
+                b1 = bu - n0;  // j = b1 + t for n0 <= t < n01
+                int nd = 0, bd = 0;
+                if (ly == 1 || lx == 1 || lx == tw) {
+                    bd = s_ofs[dn];
+                    nd = s_ofs[dn + 3] - bd;
+                }
+                b2 = bd - n01;  // j = b2 + t for n01 <= t < n
+                n = n01 + nd;
                 ri = s_rec[si];
             }
-            const int n01 = n0 + n1, n = n01 + n2;
-            const int nmax = __builtin_amdgcn_readfirstlane(wave_max(n));
-            const int idi = __float_as_int(ri.z), pid = idi ^ 1;
-            int partner = 0xFF;
-            for (int t = 0; t < nmax; ++t) {
-                int j = (t < n0) ? b0 + t : ((t < n01) ? b1 + (t - n0) : b2 + (t - n01));
-                const bool valid = (t < n) && (j != si);
-                j = valid ? j : si;
-                const float4 rj = s_rec[j];
+            const int tmax = __builtin_amdgcn_readfirstlane(wave_max(n));
+            const int pid = __float_as_int(ri.z) ^ 1;
+            int partner = 0xFF, ptile = 0xFF;  // partner's staged index; its tile index
+            // the record of candidate t + 1 is read while candidate t is tested
+            int jn = (0 < n) ? ((0 < n0) ? b0 : ((0 < n01) ? b1 : b2)) : si;
+            float4 rn = s_rec[jn];
+            for (int t = 0; t < tmax; ++t) {
+                const int j = jn;
+                const float4 rj = rn;
+                const int t1 = t + 1;
+                jn = t1 + ((t1 < n0) ? b0 : ((t1 < n01) ? b1 : b2));
+                jn = (t1 < n) ? jn : si;
+                rn = s_rec[jn];
                 const int tj = __float_as_int(rj.w);
-                const bool isp = valid && (__float_as_int(rj.z) == pid);
+                const bool mine = (t < n) && (j != si) && (tj == 0xFF || j > si);
+                const bool isp = mine && (__float_as_int(rj.z) == pid);
                 partner = isp ? j : partner;
+                ptile = isp ? tj : ptile;
                 const float dx = edge ? minimg_sub(ri.x, rj.x, P) : ri.x - rj.x;
                 const float dy = edge ? minimg_sub(ri.y, rj.y, P) : ri.y - rj.y;
-                const bool keep = valid && !isp && (tj == 0xFF || j > si) &&
-                                  interacts(cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy));
-                const unsigned long long m = __ballot(keep);
-                if (keep) {
-                    const int pos = E + lanes_below(m);
-                    if (pos < kEcap) s_pair[pos] = (unsigned short)((k << 8) | j);
+                const bool keep = mine && !isp && interacts(cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy));
+                const unsigned long long msk = __ballot(keep);
+                const int nk = __popcll(msk);
+                if (E + nk <= kEcap) {
+                    if (keep) s_pair[E + lanes_below(msk)] = (unsigned short)((si << 8) | j);
                 }
-                E += __popcll(m);
+                E += nk;
             }
-            if (act) s_partner[k] = (unsigned char)partner;
+            if (k < ntile) {
+                if (partner != 0xFF) s_partner[k] = (unsigned char)partner;
+                if (ptile != 0xFF) s_partner[ptile] = (unsigned char)si;
+            }
         }
         __syncthreads();
 
         if (E <= kEcap) {
+            for (int k = lane; k < ntile; k += kWave) {
+                s_acc[k][0] = 0;
+                s_acc[k][1] = 0;
+            }
+            __syncthreads();
             // ---- B: one force per kept pair, exact fixed-point sums
             bool bad = false;
             for (int e = lane; e < E; e += kWave) {
                 const int w = s_pair[e];
-                const int k = w >> 8, j = w & 0xFF;
-                const int so = s_tslot[k];
+                const int so = w >> 8, j = w & 0xFF;
                 const float4 ro = s_rec[so], rj = s_rec[j];
+                const int k = __float_as_int(ro.w);
                 const float dx = edge ? minimg_sub(ro.x, rj.x, P) : ro.x - rj.x;
                 const float dy = edge ? minimg_sub(ro.y, rj.y, P) : ro.y - rj.y;
                 float fx = 0.f, fy = 0.f;
@@ -574,18 +634,26 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
             done = true;
         }
     }
-    if (!done) tile_global<MODE>(P, a, cx0, cy0, tw, th, rv, reduce != 0);
-    if (reduce) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) rv[k] += __shfl_down(rv[k], o, kWave);
-        }
-        if (lane == 0) {
-            a.red[3 * tile + 0] = rv[0];
-            a.red[3 * tile + 1] = rv[1];
-            a.red[3 * tile + 2] = rv[2];
-        }
+    if (!done) {
+        // over an LDS capacity: leave the tile to k_pair_overflow
+        if (lane == 0) a.ovf_list[atomicAdd(a.ovf_count, 1)] = tile;
+        return;
+    }
+    if (reduce) tile_reduce(a, tile, rv);
+}
+
+// The tiles k_pair left over, one 64-lane wavefront per listed tile, through
+// the global-memory path (same results bit for bit).  Launched right after
+// k_pair with a fixed grid; with an empty list every wavefront exits at once.
+template <int MODE>
+__global__ __launch_bounds__(kWave) void k_pair_overflow(DevParams P, PairArgs a, int reduce) {
+    const int n = *a.ovf_count;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int tile = a.ovf_list[i];
+        const TileGeom G = tile_geom(P, tile);
+        double rv[3] = {0.0, 0.0, 0.0};
+        tile_global<MODE>(P, a, G.cx0, G.cy0, G.tw, G.th, rv, reduce != 0);
+        if (reduce) tile_reduce(a, tile, rv);
     }
 }
 
@@ -643,7 +711,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ 
 
 // Pass 1b (one block): exclusive scan of the G block sums; the grand total goes
 // to cell_start[n].
-__global__ __launch_bounds__(kBlock) void k_scan_top(int* partial, int G, int* total_out) {
+__global__ __launch_bounds__(kBlock) void k_scan_top(int* partial, int G, int* total_out,
+                                                     int* ovf_count) {
+    if (threadIdx.x == 0) *ovf_count = 0;  // the previous pair launch has finished
     __shared__ int s_wave[kBlock / kWave];
     __shared__ int s_vals[2 * kBlock + 1];
     int carry = 0;
@@ -919,6 +989,87 @@ __global__ void k_bin_accum(BinArgs b) {
             atomicAdd((unsigned long long*)&b.acc[3 * k + 0], (unsigned long long)qx);
             atomicAdd((unsigned long long*)&b.acc[3 * k + 1], (unsigned long long)qy);
             atomicAdd((unsigned long long*)&b.acc[3 * k + 2], 1ull);
+        }
+    }
+}
+
+// Plain bins of particle velocities from the canonical state: block j owns
+// grid row j.  The cell rows that can hold particles of that row (one row of
+// margin on each side) are contiguous in the (cell, id) order; the block sums
+// the particles whose grid row is j into LDS fixed-point accumulators and writes
+// the row's means and counts.  No global atomics; the sums are exact, so the
+// result is bitwise that of k_bin_accum + k_bin_finalize.
+struct BinRowArgs {
+    const float2* x;   // canonical order
+    const float2* v;
+    const int* cs;     // cell_start of that order
+    float2* u;
+    int* n;
+    unsigned* status;
+    int M;
+    int nc;
+    double L;
+    double inv_dx;     // M / L
+    double qscale;
+    double vmax;
+};
+
+constexpr int kBinRowBlock = 512;
+
+__global__ __launch_bounds__(kBinRowBlock) void k_bin_rows(BinRowArgs b) {
+#pragma clang fp contract(off)
+    extern __shared__ long long s_bin[];  // 3 M: sum q_x, sum q_y, count
+    const int j = blockIdx.x, M = b.M, nc = b.nc;
+    for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) s_bin[i] = 0;
+    __syncthreads();
+    long long r0 = (long long)j * nc / M - 1;
+    long long r1 = ((long long)(j + 1) * nc + M - 1) / M;  // inclusive
+    int ra[2], rb[2], nr = 0;
+    if (r1 - r0 + 1 >= nc) {
+        ra[0] = 0; rb[0] = nc - 1; nr = 1;
+    } else if (r0 < 0) {
+        ra[0] = nc - 1; rb[0] = nc - 1;
+        ra[1] = 0; rb[1] = (int)r1; nr = 2;
+    } else if (r1 >= nc) {
+        ra[0] = (int)r0; rb[0] = nc - 1;
+        ra[1] = 0; rb[1] = (int)(r1 - nc); nr = 2;
+    } else {
+        ra[0] = (int)r0; rb[0] = (int)r1; nr = 1;
+    }
+    for (int s = 0; s < nr; ++s) {
+        const int g0 = b.cs[(long long)ra[s] * nc], g1 = b.cs[(long long)(rb[s] + 1) * nc];
+        for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+            const float2 xx = b.x[g];
+            const double py = (double)xx.y;
+            if (clamp_floor(py * b.inv_dx, M) != j) continue;
+            const double px = (double)xx.x;
+            if (!(px >= 0.0 && px < b.L) || !(py >= 0.0 && py < b.L)) {
+                atomicOr(b.status, kStatusNonFinite);
+                continue;
+            }
+            const float2 vv = b.v[g];
+            const double vx = (double)vv.x, vy = (double)vv.y;
+            if (!(fabs(vx) <= b.vmax) || !(fabs(vy) <= b.vmax)) {
+                atomicOr(b.status, kStatusRange);
+                continue;
+            }
+            const int bx = clamp_floor(px * b.inv_dx, M);
+            atomicAdd((unsigned long long*)&s_bin[3 * bx + 0], (unsigned long long)llrint(vx * b.qscale));
+            atomicAdd((unsigned long long*)&s_bin[3 * bx + 1], (unsigned long long)llrint(vy * b.qscale));
+            atomicAdd((unsigned long long*)&s_bin[3 * bx + 2], 1ull);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+        const long long c = s_bin[3 * i + 2];
+        const long long k = (long long)j * M + i;
+        b.n[k] = (int)c;
+        if (c > 0) {
+            const double inv = 1.0 / (b.qscale * (double)c);
+            b.u[k] = make_float2((float)((double)s_bin[3 * i + 0] * inv),
+                                 (float)((double)s_bin[3 * i + 1] * inv));
+        } else {
+            b.u[k] = make_float2(0.f, 0.f);
         }
     }
 }

@@ -304,6 +304,28 @@ def test_momentum_conserved_on_gpu(dpd):
     sim.close()
 
 
+def test_dense_cluster_steps(dpd):
+    # a dense cluster overflows the LDS capacities of its tiles, which then take
+    # the global-memory kernel in the step, final and force modes; the pair sums
+    # are exact in both kernels, so momentum is conserved and the forces of the
+    # stepped state match the oracle
+    cfg = dict(C1, f_sp=0.0, gamma_s=0.0)
+    x, v = inputs.initial_state(cfg, kind="clustered", thermal=True)
+    sim = make_sim(dpd, cfg, x, v)
+    pk = host(sim.step(6, reduce_every=3))
+    P0 = oracle.momentum_ke(cfg, v.astype(np.float64))
+    assert np.abs(pk[:, :2] - P0[:2]).max() <= 1e-5 * np.abs(v).sum()
+    xs, vs, _, step = sim.get_state()
+    xs, vs = host(xs), host(vs)
+    v64 = vs.astype(np.float64)
+    ref = [math.fsum(v64[:, 0]), math.fsum(v64[:, 1]), 0.5 * math.fsum((v64 * v64).sum(1))]
+    assert pk[-1] == pytest.approx(ref, rel=1e-12, abs=1e-12)
+    F = host(sim.forces())
+    per, glob = force_errors(cfg, xs, vs, step, F)
+    assert per.max() <= 1e-5 and glob <= 1e-5, (per.max(), glob)
+    sim.close()
+
+
 def test_stokes_momentum_decay_on_gpu(dpd):
     cfg = dict(C1, f_sp=0.0, gamma_s=0.8)
     x, v = inputs.initial_state(cfg, thermal=True)
@@ -381,6 +403,29 @@ def test_bin_velocity_matches_oracle(dpd, M, eps, mode):
     q = 2.0 ** -min(32, 46 - math.ceil(math.log2(len(x) // (1 + mode) + 1)))
     err = np.abs(host(u).astype(np.float64) - uo)
     assert (err <= q + 2.0 ** -23 * np.abs(uo)).all()
+    sim.close()
+
+
+@pytest.mark.parametrize("how", ["set_state_with_F", "after_forces", "edge_layout"])
+def test_bin_velocity_row_path_every_entry(dpd, how):
+    # plain particle bins are read straight from the stored (cell, id) order;
+    # check them after every way of reaching a stored state
+    cfg = C1
+    kind = "edge" if how == "edge_layout" else "random"
+    x, v = inputs.initial_state(cfg, kind=kind, thermal=True)
+    sim = make_sim(dpd, cfg, x, v)
+    sim.step(3)
+    xs, vs, Fs, step = sim.get_state()
+    if how == "set_state_with_F":
+        sim.set_state(xs, vs, step, Fs)
+    elif how == "after_forces":
+        sim.forces()
+    for M in (40, 64, 7):
+        u, n = sim.bin_velocity(M, 0.0, 0)
+        uo, no = oracle.bin_velocity(cfg, host(xs), host(vs), M, 0.0, 0)
+        assert (host(n) == no).all()
+        q = 2.0 ** -min(32, 46 - math.ceil(math.log2(len(x) + 1)))
+        assert (np.abs(host(u).astype(np.float64) - uo) <= q + 2.0 ** -23 * np.abs(uo)).all()
     sim.close()
 
 
