@@ -74,7 +74,7 @@ typedef struct dpd_params {
                             1: Philox2x32-10 on (min id, max id), key folds seed and step */
     int32_t  sp_split;   /* 0: f_sp/2 on head and tail; 1: f_sp on the head only      */
     int32_t  bin_M_max;  /* largest grid side dpd_bin_velocity will be asked for (0: 256) */
-    int32_t  tile;       /* pair-kernel tile side in cells (0: automatic)             */
+    int32_t  tile;       /* pair-kernel tile side in cells, 1..8 (0: 8 x 7 cells)     */
     int32_t  reserved[3];
 } dpd_params;
 
@@ -168,12 +168,14 @@ int64_t dpd_cells_per_side(const dpd_params* p);
 int dpd_rng_words(const dpd_params* p, const int32_t* i, const int32_t* j, int64_t step,
                   int32_t n, uint32_t* words_out, float* alpha_out, void* stream);
 
-/* Bracket every launch of the fused pair kernel with HIP events on the
- * handle's stream (on != 0) or stop doing so (on == 0). */
+/* Bracket every 8th launch of the fused pair kernel (the first, ninth, ...
+ * after switching on) with HIP events on the handle's stream (on != 0), or stop
+ * doing so (on == 0).  Only a sample is bracketed because an event record
+ * between two kernels costs a few microseconds of GPU time. */
 int dpd_set_profiling(dpd_handle* h, int32_t on);
 
-/* Total device time (ms) and number of launches of the fused pair kernel
- * recorded since profiling was switched on.  Synchronises the stream. */
+/* Total device time (ms) and number of the bracketed launches of the fused
+ * pair kernel since profiling was switched on.  Synchronises the stream. */
 int dpd_pair_kernel_time(dpd_handle* h, double* ms_total, int64_t* launches);
 
 /* Plain device-to-device copy of `bytes` (multiple of 16) by a simple

@@ -31,12 +31,14 @@ struct Layout {
 struct Derived {
     DevParams P;
     int n_tiles;
-    int n_scan_blocks;
+    int n_scan_blocks;  // chunks of the cell-count scan
     int bin_M_max;
     Layout lay;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr uint64_t kProfEvery = 8;  // pair launches per profiled launch
 
 std::string fmt(const char* f, ...) {
     char buf[512];
@@ -150,12 +152,12 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     L.off_src = take(N * 4);
     L.off_count = take((size_t)P.n_cells * 4);
     L.off_cs = take(((size_t)P.n_cells + 1) * 4);
-    L.off_scan_part = take((size_t)d->n_scan_blocks * 4);
     L.off_red = take((size_t)d->n_tiles * 3 * 8);
     L.off_Fs = take(N * 8);
     L.off_binacc = take((size_t)d->bin_M_max * d->bin_M_max * 3 * 8);
     L.off_status = take(16);
     L.off_ovf = take(((size_t)d->n_tiles + 1) * 4);
+    L.off_scan_part = take((size_t)d->n_scan_blocks * 4);
     L.total = o;
     return DPD_OK;
 }
@@ -170,9 +172,10 @@ struct dpd_handle {
     hipStream_t stream;
     char* ws;
     float2 *Sx, *Sv, *SF, *Ax, *Au, *Bx, *Bu, *Fs;
-    int *Sid, *Aid, *Bid, *key, *rank, *src, *count, *cs, *scan_part;
+    int *Sid, *Aid, *Bid, *key, *rank, *src, *count, *cs;
     unsigned* status;
     int* ovf;  // [0]: count of tiles left to the overflow kernel, then their indices
+    int* scan_part;
     double* red;
     long long* binacc;
     int64_t step;
@@ -183,6 +186,7 @@ struct dpd_handle {
     size_t ev_used;
     double prof_ms;
     int64_t prof_n;
+    uint64_t prof_seq;
 };
 
 namespace {
@@ -217,10 +221,8 @@ int bin_from_counts(dpd_handle* h, const int* id_of_input) {
     const int G = h->d.n_scan_blocks;
     hipLaunchKernelGGL(k_scan_reduce, dim3(G), dim3(kBlock), 0, h->stream, (const int*)h->count,
                        P.n_cells, h->scan_part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, h->stream, h->scan_part, G,
-                       h->cs + P.n_cells, h->ovf);
     hipLaunchKernelGGL(k_scan_final, dim3(G), dim3(kBlock), 0, h->stream, h->count, P.n_cells,
-                       (const int*)h->scan_part, h->cs);
+                       (const int*)h->scan_part, h->cs, h->ovf);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
                        (const int*)h->key, (const int*)h->rank, (const int*)h->cs, h->src);
     if (id_of_input)
@@ -234,7 +236,10 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
     const DevParams& P = h->d.P;
     const int G = h->d.n_tiles;
     size_t ev = 0;
-    if (h->profiling) {
+    // with profiling on, every kProfEvery-th launch is bracketed by events (an
+    // event record between two kernels costs a few microseconds of GPU time)
+    const bool timed = h->profiling && (h->prof_seq++ % kProfEvery == 0);
+    if (timed) {
         if (h->ev_used == h->ev_start.size()) {
             hipEvent_t e0, e1;
             HIPCHK(h, hipEventCreate(&e0));
@@ -255,7 +260,7 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
     else
         hipLaunchKernelGGL(k_pair<MODE_FORCES>, dim3(G), dim3(kWave), 0, h->stream, P, b, 0);
     LAUNCHCHK(h);
-    if (h->profiling) {
+    if (timed) {
         HIPCHK(h, hipEventRecord(h->ev_stop[ev], h->stream));
         if (h->ev_used >= 256) {  // fold the recorded pairs into the totals
             HIPCHK(h, hipEventSynchronize(h->ev_stop[ev]));
@@ -269,7 +274,7 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
         }
     }
     // tiles over an LDS capacity (dense clusters), if any
-    const int Go = std::min(G, 2048);
+    const int Go = std::min(G, 256);
     if (mode == MODE_STEP)
         hipLaunchKernelGGL(k_pair_overflow<MODE_STEP>, dim3(Go), dim3(kWave), 0, h->stream, P, b, (int)reduce);
     else if (mode == MODE_FINAL)
@@ -362,12 +367,12 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
         h->src = (int*)(w + L.off_src);
         h->count = (int*)(w + L.off_count);
         h->cs = (int*)(w + L.off_cs);
-        h->scan_part = (int*)(w + L.off_scan_part);
         h->red = (double*)(w + L.off_red);
         h->Fs = (float2*)(w + L.off_Fs);
         h->binacc = (long long*)(w + L.off_binacc);
         h->status = (unsigned*)(w + L.off_status);
         h->ovf = (int*)(w + L.off_ovf);
+        h->scan_part = (int*)(w + L.off_scan_part);
         h->step = 0;
         h->have_state = false;
         h->err = "no error";
@@ -375,6 +380,7 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
         h->ev_used = 0;
         h->prof_ms = 0.0;
         h->prof_n = 0;
+        h->prof_seq = 0;
         // clear the counters the kernels rely on
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(d.P.n_cells)), dim3(kBlock), 0, h->stream,
                            h->count, 0, (long long)d.P.n_cells);
@@ -673,6 +679,7 @@ int dpd_set_profiling(dpd_handle* h, int32_t on) {
         h->prof_ms = 0.0;
         h->prof_n = 0;
         h->ev_used = 0;
+        h->prof_seq = 0;
     }
     h->profiling = on != 0;
     return DPD_OK;

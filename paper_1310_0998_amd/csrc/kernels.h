@@ -45,7 +45,7 @@ struct PairArgs {
     float2* Fout;       // FINAL/FORCES: total force
     double* red;        // 3 doubles per tile (sum v_x, sum v_y, sum |v|^2) or null
     unsigned* status;
-    int* ovf_count;     // tiles handed to the global-memory kernel (cleared by k_scan_top)
+    int* ovf_count;     // tiles handed to the global-memory kernel (cleared by the cell-count scan)
     int* ovf_list;      // their tile indices
     uint32_t step;      // step number of the force evaluation (mod 2^32)
 };
@@ -687,10 +687,16 @@ __global__ void k_key_rank(DevParams P, const float2* __restrict__ x, int* key, 
     rank[i] = atomicAdd(&count[k], 1);
 }
 
+// Exclusive scan of the per-cell counts -> cell_start, in two passes over
+// chunks of kScanTile cells: k_scan_reduce writes each chunk's sum; in
+// k_scan_final every block adds up the sums of the chunks before its own (a few
+// KB read from L2, in a fixed order), scans its chunk and clears the counts for
+// the next binning.  The last block writes the grand total to cell_start[n].
+// k_scan_final also clears the pair kernel's tile overflow counter (the
+// previous pair launch has finished).
 constexpr int kScanPer = 8;
-constexpr int kScanTile = kBlock * kScanPer;  // cells per scan block
+constexpr int kScanTile = kBlock * kScanPer;  // cells per chunk
 
-// Pass 1: per-block sums of the counts (fixed order).
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ count, int n,
                                                         int* partial) {
     __shared__ int s_wave[kBlock / kWave];
@@ -709,33 +715,22 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ 
     if (threadIdx.x == 0) partial[blockIdx.x] = ((s_wave[0] + s_wave[1]) + s_wave[2]) + s_wave[3];
 }
 
-// Pass 1b (one block): exclusive scan of the G block sums; the grand total goes
-// to cell_start[n].
-__global__ __launch_bounds__(kBlock) void k_scan_top(int* partial, int G, int* total_out,
-                                                     int* ovf_count) {
-    if (threadIdx.x == 0) *ovf_count = 0;  // the previous pair launch has finished
-    __shared__ int s_wave[kBlock / kWave];
-    __shared__ int s_vals[2 * kBlock + 1];
-    int carry = 0;
-    for (int c0 = 0; c0 < G; c0 += 2 * kBlock) {
-        const int m = min(2 * kBlock, G - c0);
-        for (int k = threadIdx.x; k < m; k += kBlock) s_vals[k] = partial[c0 + k];
-        __syncthreads();
-        const int tot = block_scan_excl_512(s_vals, m, s_wave);
-        for (int k = threadIdx.x; k < m; k += kBlock) partial[c0 + k] = s_vals[k] + carry;
-        carry += tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *total_out = carry;
-}
-
-// Pass 2: exclusive scan within each block + block offset -> cell_start; the
-// counts are cleared for the next use.
-__global__ __launch_bounds__(kBlock) void k_scan_final(int* count, int n, const int* partial,
-                                                       int* cs) {
+__global__ __launch_bounds__(kBlock) void k_scan_final(int* count, int n, const int* __restrict__ partial,
+                                                       int* cs, int* ovf_count) {
     __shared__ int s_v[kScanTile + kScanTile / 32];
     __shared__ int s_tsum[2 * kBlock + 1];
     __shared__ int s_wave[kBlock / kWave];
+    __shared__ int s_red[kBlock / kWave];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ovf_count = 0;
+    // sum of the chunks before this one
+    int before = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kBlock) before += partial[k];
+    {
+        const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) before += __shfl_down(before, o, kWave);
+        if (lane == 0) s_red[w] = before;
+    }
     const int base = blockIdx.x * kScanTile;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
@@ -744,6 +739,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(int* count, int n, const 
         s_v[li + (li >> 5)] = (idx < n) ? count[idx] : 0;
     }
     __syncthreads();
+    const int prefix = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
     int loc[kScanPer];
     int sum = 0;
 #pragma unroll
@@ -752,14 +748,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(int* count, int n, const 
         loc[k] = sum;
         sum += s_v[li + (li >> 5)];
     }
-    // thread sums -> exclusive offsets (one value per thread)
     s_tsum[threadIdx.x] = sum;
     __syncthreads();
-    // scan 256 values with the 512-wide helper (upper half zero)
-    if (threadIdx.x < kBlock) s_tsum[kBlock + threadIdx.x] = 0;
-    __syncthreads();
-    block_scan_excl_512(s_tsum, kBlock, s_wave);
-    const int off = partial[blockIdx.x] + s_tsum[threadIdx.x];
+    const int agg = block_scan_excl_512(s_tsum, kBlock, s_wave);
+    const int off = prefix + s_tsum[threadIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
         const int li = threadIdx.x * kScanPer + k;
@@ -775,9 +767,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(int* count, int n, const 
             count[idx] = 0;
         }
     }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) cs[n] = prefix + agg;
 }
 
-// slot = cell_start[key] + rank
 __global__ void k_scatter(int N, const int* __restrict__ key, const int* __restrict__ rank,
                           const int* __restrict__ cs, int* src) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
