@@ -152,7 +152,7 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     L.off_src = take(N * 4);
     L.off_count = take((size_t)P.n_cells * 4);
     L.off_cs = take(((size_t)P.n_cells + 1) * 4);
-    L.off_red = take((size_t)d->n_tiles * 3 * 8);
+    L.off_red = take(((size_t)d->n_tiles + kRedParts) * 3 * 8);  // per tile, then per part
     L.off_Fs = take(N * 8);
     L.off_binacc = take((size_t)d->bin_M_max * d->bin_M_max * 3 * 8);
     L.off_status = take(16);
@@ -180,6 +180,11 @@ struct dpd_handle {
     long long* binacc;
     int64_t step;
     bool have_state;
+    // the last dpd_step also made the next step's half kick and drift (and its
+    // cell counts); the next dpd_step starts from these buffers
+    bool prepared;
+    float2 *prep_x, *prep_u;
+    int* prep_id;
     std::string err;
     bool profiling;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -274,7 +279,7 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
         }
     }
     // tiles over an LDS capacity (dense clusters), if any
-    const int Go = std::min(G, 256);
+    const int Go = std::min(G, 64);
     if (mode == MODE_STEP)
         hipLaunchKernelGGL(k_pair_overflow<MODE_STEP>, dim3(Go), dim3(kWave), 0, h->stream, P, b, (int)reduce);
     else if (mode == MODE_FINAL)
@@ -301,6 +306,17 @@ int read_status(dpd_handle* h) {
         return fail(h, DPD_ERANGE, "a velocity exceeded the range of the binned field");
     if (st[0] & kStatusBinning)
         return fail(h, DPD_EHIP, "internal error: cell counts inconsistent with the particle count");
+    return DPD_OK;
+}
+
+// Drop the prepared next step (its cell counts are cleared so that the next
+// binning starts from zero).
+int unprepare(dpd_handle* h) {
+    if (!h->prepared) return DPD_OK;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(h->d.P.n_cells)), dim3(kBlock), 0, h->stream,
+                       h->count, 0, (long long)h->d.P.n_cells);
+    LAUNCHCHK(h);
+    h->prepared = false;
     return DPD_OK;
 }
 
@@ -375,6 +391,9 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
         h->scan_part = (int*)(w + L.off_scan_part);
         h->step = 0;
         h->have_state = false;
+        h->prepared = false;
+        h->prep_x = h->prep_u = nullptr;
+        h->prep_id = nullptr;
         h->err = "no error";
         h->profiling = false;
         h->ev_used = 0;
@@ -415,6 +434,8 @@ int dpd_set_state(dpd_handle* h, const float* x, const float* v, int64_t step, c
     if (!x || !v) return fail(h, DPD_EINVAL, "x and v must not be NULL");
     try {
         const DevParams& P = h->d.P;
+        int rc0 = unprepare(h);
+        if (rc0) return rc0;
         hipLaunchKernelGGL(k_load_input, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
                            (const float2*)x, (const float2*)v, h->Ax, h->Au, h->Aid, h->key,
                            h->rank, h->count, h->status);
@@ -460,14 +481,29 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
     try {
         const DevParams& P = h->d.P;
         const bool want_pk = reduce_every > 0 && pk_out != nullptr;
-        // first half kick + drift from the stored state
-        hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
-                           (const float2*)h->Sx, (const float2*)h->Sv, (const float2*)h->SF,
-                           (const int*)h->Sid, h->Ax, h->Au, h->Aid, h->key, h->rank, h->count,
-                           h->status);
-        LAUNCHCHK(h);
-        float2 *inx = h->Ax, *inu = h->Au, *outx = h->Bx, *outu = h->Bu;
-        int *inid = h->Aid, *outid = h->Bid;
+        float2 *inx, *inu, *outx, *outu;
+        int *inid, *outid;
+        if (h->prepared) {
+            // the previous call already made this step's half kick, drift and keys
+            inx = h->prep_x;
+            inu = h->prep_u;
+            inid = h->prep_id;
+        } else {
+            // first half kick + drift from the stored state
+            hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
+                               (const float2*)h->Sx, (const float2*)h->Sv, (const float2*)h->SF,
+                               (const int*)h->Sid, h->Ax, h->Au, h->Aid, h->key, h->rank, h->count,
+                               h->status);
+            LAUNCHCHK(h);
+            inx = h->Ax;
+            inu = h->Au;
+            inid = h->Aid;
+        }
+        h->prepared = false;
+        const bool in_a = (inx == h->Ax);
+        outx = in_a ? h->Bx : h->Ax;
+        outu = in_a ? h->Bu : h->Au;
+        outid = in_a ? h->Bid : h->Aid;
         int rec = 0;
         for (int k = 1; k <= n_steps; ++k) {
             int rc = bin_from_counts(h, nullptr);
@@ -483,25 +519,32 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
             a.status = h->status;
             a.red = h->red;
             a.step = (uint32_t)((uint64_t)(h->step + k) & 0xffffffffu);
+            a.keyout = h->key;
+            a.rankout = h->rank;
+            a.count = h->count;
             if (last) {
                 a.xout = h->Sx;
                 a.uout = h->Sv;
                 a.idout = h->Sid;
                 a.Fout = h->SF;
+                a.pxout = outx;
+                a.puout = outu;
+                a.pidout = outid;
                 rc = launch_pair(h, MODE_FINAL, a, red);
             } else {
                 a.xout = outx;
                 a.uout = outu;
                 a.idout = outid;
-                a.keyout = h->key;
-                a.rankout = h->rank;
-                a.count = h->count;
                 rc = launch_pair(h, MODE_STEP, a, red);
             }
             if (rc) return rc;
             if (red) {
+                const int parts = std::min(kRedParts, h->d.n_tiles);
+                double* part = h->red + 3 * (size_t)h->d.n_tiles;
+                hipLaunchKernelGGL(k_reduce_part, dim3(parts), dim3(kBlock), 0, h->stream,
+                                   (const double*)h->red, h->d.n_tiles, part);
                 hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, h->stream,
-                                   (const double*)h->red, h->d.n_tiles, h->p.mass, pk_out + 3 * rec);
+                                   (const double*)part, parts, h->p.mass, pk_out + 3 * rec);
                 LAUNCHCHK(h);
                 ++rec;
             }
@@ -509,6 +552,11 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
             std::swap(inu, outu);
             std::swap(inid, outid);
         }
+        // the last launch left the next step's start in what is now `in`
+        h->prepared = true;
+        h->prep_x = inx;
+        h->prep_u = inu;
+        h->prep_id = inid;
         h->step += n_steps;
         return DPD_OK;
     } catch (...) {
@@ -522,6 +570,8 @@ int dpd_forces(dpd_handle* h, float* F_out) {
     if (!F_out) return fail(h, DPD_EINVAL, "F_out is NULL");
     try {
         const DevParams& P = h->d.P;
+        int rc0 = unprepare(h);
+        if (rc0) return rc0;
         hipLaunchKernelGGL(k_key_rank, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
                            (const float2*)h->Sx, h->key, h->rank, h->count);
         LAUNCHCHK(h);
@@ -599,6 +649,7 @@ int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode, float* 
             // plain bins of particle velocities: one block per grid row, read
             // straight from the canonical state
             BinRowArgs r;
+            r.Q = std::max(1, std::min(8, M / 32));
             r.x = h->Sx;
             r.v = h->Sv;
             r.cs = h->cs;
@@ -611,11 +662,15 @@ int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode, float* 
             r.inv_dx = (double)M / h->p.L;
             r.qscale = qscale;
             r.vmax = 65536.0;
-            hipLaunchKernelGGL(k_bin_rows, dim3(M), dim3(kBinRowBlock), (size_t)M * 24, h->stream, r);
+            const size_t lds = (size_t)((M + r.Q - 1) / r.Q) * 24;
+            hipLaunchKernelGGL(k_bin_rows, dim3(r.Q, M), dim3(kBinRowBlock), lds, h->stream, r);
             LAUNCHCHK(h);
             return DPD_OK;
         }
-        // id-order copies of x and v into the scratch buffers
+        // id-order copies of x and v into the scratch buffers (which may hold the
+        // prepared next step)
+        int rc0 = unprepare(h);
+        if (rc0) return rc0;
         hipLaunchKernelGGL(k_unpermute, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
                            (const int*)h->Sid, (const float2*)h->Sx, h->Bx);
         hipLaunchKernelGGL(k_unpermute, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,

@@ -43,6 +43,9 @@ struct PairArgs {
     int* rankout;       // STEP: rank of the particle within its new cell
     int* count;         // STEP: per-cell counters (atomically incremented)
     float2* Fout;       // FINAL/FORCES: total force
+    float2* pxout;      // FINAL, if not null: also the next step's drifted position,
+    float2* puout;      //   half-step velocity and id (as k_kick_drift would make them),
+    int* pidout;        //   with keyout, rankout and count as in STEP
     double* red;        // 3 doubles per tile (sum v_x, sum v_y, sum |v|^2) or null
     unsigned* status;
     int* ovf_count;     // tiles handed to the global-memory kernel (cleared by the cell-count scan)
@@ -201,7 +204,9 @@ __device__ __forceinline__ void finish_particle(const DevParams& P, const PairAr
         if (!finite2(F)) atomicOr(a.status, kStatusNonFinite);
         return;
     }
-    const float2 v = make_float2(ui.x + P.h * fx, ui.y + P.h * fy);
+    // half kicks as explicit fused multiply-adds, so that every kernel that kicks
+    // (this one, k_kick_drift) rounds them identically
+    const float2 v = make_float2(fmaf(P.h, fx, ui.x), fmaf(P.h, fy, ui.y));
     if (reduce) {
         rv[0] += (double)v.x;
         rv[1] += (double)v.y;
@@ -212,10 +217,22 @@ __device__ __forceinline__ void finish_particle(const DevParams& P, const PairAr
         a.uout[g] = v;
         a.idout[g] = idi;
         a.Fout[g] = F;
-        if (!finite2(v) || !finite2(F)) atomicOr(a.status, kStatusNonFinite);
+        bool bad = !finite2(v) || !finite2(F);
+        if (a.pxout) {  // start the next call's first step: half kick, drift, key, rank
+            const float2 un = make_float2(fmaf(P.h, fx, v.x), fmaf(P.h, fy, v.y));
+            const float2 xn = make_float2(drift_wrap(xi.x, un.x, P), drift_wrap(xi.y, un.y, P));
+            const int key = cell_key(xn, P);
+            a.pxout[g] = xn;
+            a.puout[g] = un;
+            a.pidout[g] = idi;
+            a.keyout[g] = key;
+            a.rankout[g] = atomicAdd(&a.count[key], 1);
+            bad |= !finite2(xn) || !finite2(un);
+        }
+        if (bad) atomicOr(a.status, kStatusNonFinite);
         return;
     }
-    const float2 un = make_float2(v.x + P.h * fx, v.y + P.h * fy);
+    const float2 un = make_float2(fmaf(P.h, fx, v.x), fmaf(P.h, fy, v.y));
     const float2 xn = make_float2(drift_wrap(xi.x, un.x, P), drift_wrap(xi.y, un.y, P));
     const int key = cell_key(xn, P);
     const int rank = atomicAdd(&a.count[key], 1);
@@ -850,7 +867,7 @@ __global__ void k_kick_drift(DevParams P, const float2* __restrict__ x, const fl
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= P.N) return;
     const float2 f = F[g], vv = v[g], xx = x[g];
-    const float2 u = make_float2(vv.x + P.h * f.x, vv.y + P.h * f.y);
+    const float2 u = make_float2(fmaf(P.h, f.x, vv.x), fmaf(P.h, f.y, vv.y));
     const float2 xn = make_float2(drift_wrap(xx.x, u.x, P), drift_wrap(xx.y, u.y, P));
     const int k = cell_key(xn, P);
     xo[g] = xn;
@@ -861,15 +878,38 @@ __global__ void k_kick_drift(DevParams P, const float2* __restrict__ x, const fl
     if (!finite2(xn) || !finite2(u)) atomicOr(status, kStatusNonFinite);
 }
 
-// Fixed-order sum of the per-tile partials -> (P_x, P_y, KE).
-__global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restrict__ red,
-                                                         int n_tiles, double mass, double* out) {
+// Fixed-order sum of the per-tile partials -> (P_x, P_y, KE), in two stages:
+// k_reduce_part sums fixed consecutive ranges of tiles (one block each), then
+// k_reduce_final sums the block results.
+constexpr int kRedParts = 256;
+
+__global__ __launch_bounds__(kBlock) void k_reduce_part(const double* __restrict__ red, int n_tiles,
+                                                        double* part) {
     __shared__ double s_red[kBlock / kWave][3];
+    const int per = (n_tiles + gridDim.x - 1) / gridDim.x;
+    const int t0 = blockIdx.x * per, t1 = min(n_tiles, t0 + per);
     double v[3] = {0.0, 0.0, 0.0};
-    for (int t = threadIdx.x; t < n_tiles; t += kBlock) {
+    for (int t = t0 + threadIdx.x; t < t1; t += kBlock) {
         v[0] += red[3 * t + 0];
         v[1] += red[3 * t + 1];
         v[2] += red[3 * t + 2];
+    }
+    block_sum3(v, s_red);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = v[0];
+        part[3 * blockIdx.x + 1] = v[1];
+        part[3 * blockIdx.x + 2] = v[2];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restrict__ part,
+                                                         int n_parts, double mass, double* out) {
+    __shared__ double s_red[kBlock / kWave][3];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < n_parts; t += kBlock) {
+        v[0] += part[3 * t + 0];
+        v[1] += part[3 * t + 1];
+        v[2] += part[3 * t + 2];
     }
     block_sum3(v, s_red);
     if (threadIdx.x == 0) {
@@ -985,12 +1025,13 @@ __global__ void k_bin_accum(BinArgs b) {
     }
 }
 
-// Plain bins of particle velocities from the canonical state: block j owns
-// grid row j.  The cell rows that can hold particles of that row (one row of
-// margin on each side) are contiguous in the (cell, id) order; the block sums
-// the particles whose grid row is j into LDS fixed-point accumulators and writes
-// the row's means and counts.  No global atomics; the sums are exact, so the
-// result is bitwise that of k_bin_accum + k_bin_finalize.
+// Plain bins of particle velocities from the canonical state.  Block (q, j)
+// owns bins [q M/Q, (q+1) M/Q) of grid row j.  The cells that can hold those
+// bins (one cell of margin on each side) are, row by row, contiguous in the
+// (cell, id) order; the block sums the particles whose bin it owns into LDS
+// fixed-point accumulators and writes the bins' means and counts.  No global
+// atomics; the sums are exact, so the result is bitwise that of k_bin_accum +
+// k_bin_finalize.
 struct BinRowArgs {
     const float2* x;   // canonical order
     const float2* v;
@@ -999,6 +1040,7 @@ struct BinRowArgs {
     int* n;
     unsigned* status;
     int M;
+    int Q;             // column parts per grid row
     int nc;
     double L;
     double inv_dx;     // M / L
@@ -1006,55 +1048,73 @@ struct BinRowArgs {
     double vmax;
 };
 
-constexpr int kBinRowBlock = 512;
+constexpr int kBinRowBlock = 256;
+
+// Up to two ranges [lo, hi] of cell indices modulo nc covering [a, b] (b - a + 1 < nc).
+__device__ __forceinline__ int wrapped_ranges(long long a, long long b, int nc, int lo[2], int hi[2]) {
+    if (b - a + 1 >= nc) {
+        lo[0] = 0; hi[0] = nc - 1;
+        return 1;
+    }
+    if (a < 0) {
+        lo[0] = (int)(a + nc); hi[0] = nc - 1;
+        lo[1] = 0; hi[1] = (int)b;
+        return 2;
+    }
+    if (b >= nc) {
+        lo[0] = (int)a; hi[0] = nc - 1;
+        lo[1] = 0; hi[1] = (int)(b - nc);
+        return 2;
+    }
+    lo[0] = (int)a; hi[0] = (int)b;
+    return 1;
+}
 
 __global__ __launch_bounds__(kBinRowBlock) void k_bin_rows(BinRowArgs b) {
 #pragma clang fp contract(off)
-    extern __shared__ long long s_bin[];  // 3 M: sum q_x, sum q_y, count
-    const int j = blockIdx.x, M = b.M, nc = b.nc;
-    for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) s_bin[i] = 0;
+    extern __shared__ long long s_bin[];  // 3 per owned bin: sum q_x, sum q_y, count
+    const int M = b.M, Q = b.Q, nc = b.nc;
+    const int j = blockIdx.y, q = blockIdx.x;
+    const int i0 = (int)((long long)q * M / Q), i1 = (int)((long long)(q + 1) * M / Q);
+    const int nb = i1 - i0;
+    for (int i = threadIdx.x; i < 3 * nb; i += blockDim.x) s_bin[i] = 0;
     __syncthreads();
-    long long r0 = (long long)j * nc / M - 1;
-    long long r1 = ((long long)(j + 1) * nc + M - 1) / M;  // inclusive
-    int ra[2], rb[2], nr = 0;
-    if (r1 - r0 + 1 >= nc) {
-        ra[0] = 0; rb[0] = nc - 1; nr = 1;
-    } else if (r0 < 0) {
-        ra[0] = nc - 1; rb[0] = nc - 1;
-        ra[1] = 0; rb[1] = (int)r1; nr = 2;
-    } else if (r1 >= nc) {
-        ra[0] = (int)r0; rb[0] = nc - 1;
-        ra[1] = 0; rb[1] = (int)(r1 - nc); nr = 2;
-    } else {
-        ra[0] = (int)r0; rb[0] = (int)r1; nr = 1;
-    }
-    for (int s = 0; s < nr; ++s) {
-        const int g0 = b.cs[(long long)ra[s] * nc], g1 = b.cs[(long long)(rb[s] + 1) * nc];
-        for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-            const float2 xx = b.x[g];
-            const double py = (double)xx.y;
-            if (clamp_floor(py * b.inv_dx, M) != j) continue;
-            const double px = (double)xx.x;
-            if (!(px >= 0.0 && px < b.L) || !(py >= 0.0 && py < b.L)) {
-                atomicOr(b.status, kStatusNonFinite);
-                continue;
+    int rlo[2], rhi[2], clo[2], chi[2];
+    const int nr = wrapped_ranges((long long)j * nc / M - 1, ((long long)(j + 1) * nc + M - 1) / M, nc, rlo, rhi);
+    const int ncr = wrapped_ranges((long long)i0 * nc / M - 1, ((long long)i1 * nc + M - 1) / M, nc, clo, chi);
+    for (int ra = 0; ra < nr; ++ra) {
+        for (int row = rlo[ra]; row <= rhi[ra]; ++row) {
+            const long long rb = (long long)row * nc;
+            for (int ca = 0; ca < ncr; ++ca) {
+                const int g0 = b.cs[rb + clo[ca]], g1 = b.cs[rb + chi[ca] + 1];
+                for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+                    const float2 xx = b.x[g];
+                    const double py = (double)xx.y, px = (double)xx.x;
+                    if (clamp_floor(py * b.inv_dx, M) != j) continue;
+                    const int bx = clamp_floor(px * b.inv_dx, M);
+                    if (bx < i0 || bx >= i1) continue;
+                    if (!(px >= 0.0 && px < b.L) || !(py >= 0.0 && py < b.L)) {
+                        atomicOr(b.status, kStatusNonFinite);
+                        continue;
+                    }
+                    const float2 vv = b.v[g];
+                    const double vx = (double)vv.x, vy = (double)vv.y;
+                    if (!(fabs(vx) <= b.vmax) || !(fabs(vy) <= b.vmax)) {
+                        atomicOr(b.status, kStatusRange);
+                        continue;
+                    }
+                    const int k = bx - i0;
+                    atomicAdd((unsigned long long*)&s_bin[3 * k + 0], (unsigned long long)llrint(vx * b.qscale));
+                    atomicAdd((unsigned long long*)&s_bin[3 * k + 1], (unsigned long long)llrint(vy * b.qscale));
+                    atomicAdd((unsigned long long*)&s_bin[3 * k + 2], 1ull);
+                }
             }
-            const float2 vv = b.v[g];
-            const double vx = (double)vv.x, vy = (double)vv.y;
-            if (!(fabs(vx) <= b.vmax) || !(fabs(vy) <= b.vmax)) {
-                atomicOr(b.status, kStatusRange);
-                continue;
-            }
-            const int bx = clamp_floor(px * b.inv_dx, M);
-            atomicAdd((unsigned long long*)&s_bin[3 * bx + 0], (unsigned long long)llrint(vx * b.qscale));
-            atomicAdd((unsigned long long*)&s_bin[3 * bx + 1], (unsigned long long)llrint(vy * b.qscale));
-            atomicAdd((unsigned long long*)&s_bin[3 * bx + 2], 1ull);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
         const long long c = s_bin[3 * i + 2];
-        const long long k = (long long)j * M + i;
+        const long long k = (long long)j * M + i0 + i;
         b.n[k] = (int)c;
         if (c > 0) {
             const double inv = 1.0 / (b.qscale * (double)c);

@@ -293,6 +293,35 @@ def test_run_to_run_bitwise_and_resume(dpd):
         s.close()
 
 
+@pytest.mark.parametrize("between", ["nothing", "forces", "bin_velocity_windows",
+                                     "bin_velocity_plain", "get_state"])
+def test_split_steps_bitwise(dpd, between):
+    # a dpd_step call leaves the next step's half kick and drift prepared; the
+    # next call starts from it, and every other entry point either leaves it
+    # alone or drops it: either way 5 + 5 steps equal 10 steps bit for bit
+    cfg = C1
+    x, v = inputs.initial_state(cfg, thermal=True)
+    ref = make_sim(dpd, cfg, x, v)
+    ref.step(10)
+    xr, vr, Fr, sr = (host(t) if not isinstance(t, int) else t for t in ref.get_state())
+    sim = make_sim(dpd, cfg, x, v)
+    sim.step(5)
+    if between == "forces":
+        sim.forces()
+    elif between == "bin_velocity_windows":
+        sim.bin_velocity(16, 7.5, 0)
+    elif between == "bin_velocity_plain":
+        sim.bin_velocity(40, 0.0, 0)
+    elif between == "get_state":
+        sim.get_state()
+    sim.step(5)
+    xs, vs, Fs, ss = sim.get_state()
+    assert ss == sr == 10
+    assert (host(xs) == xr).all() and (host(vs) == vr).all() and (host(Fs) == Fr).all()
+    ref.close()
+    sim.close()
+
+
 def test_momentum_conserved_on_gpu(dpd):
     cfg = dict(C1, f_sp=0.0, gamma_s=0.0)
     x, v = inputs.initial_state(cfg, thermal=True)
