@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--workload", default="dimers_4M")
     ap.add_argument("--rng-kind", type=int, default=0)
     ap.add_argument("--noise-kind", type=int, default=0)
+    ap.add_argument("--skin", type=float, default=0.0,
+                    help="Verlet skin (0: cell list rebuilt every step)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run a plain copy kernel of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -110,7 +112,8 @@ def main():
     from paper_1310_0998_amd import dpd, inputs
 
     wl = inputs.WORKLOADS[args.workload]
-    cfg = dict(inputs.physics(wl), rng_kind=args.rng_kind, noise_kind=args.noise_kind)
+    cfg = dict(inputs.physics(wl), rng_kind=args.rng_kind, noise_kind=args.noise_kind,
+               skin=args.skin)
     bin_M = wl.get("bin_M", 256)
     bin_every = wl.get("bin_every", 20)
     reduce_every = wl.get("reduce_every", 100)
@@ -154,6 +157,7 @@ def main():
     run(warm, False)
     sim.sync()
     torch.cuda.synchronize()
+    reb0 = sim.rebuilds()
     sim.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -162,6 +166,7 @@ def main():
     t1 = time.perf_counter()
     sim.sync()
     pair_ms, launches = sim.pair_kernel_time()
+    reb = sim.rebuilds() - reb0
     sim.set_profiling(False)
     elapsed = t1 - t0
     value = N * steps / elapsed
@@ -204,6 +209,8 @@ def main():
             "rng": ["philox4x32-10", "philox2x32-10"][cfg["rng_kind"]],
             "noise": ["gaussian", "uniform"][cfg["noise_kind"]],
             "state": "fp32 (fp64 wrap and reductions)",
+            "cell_list": (f"Verlet skin {args.skin:g}: {reb} rebuilds in {steps} timed steps"
+                          if args.skin > 0 else "rebuilt every step"),
             "parallelism": "single-gpu",
         },
         "roofline": {

@@ -58,7 +58,8 @@ extern "C" {
 typedef struct dpd_params {
     int64_t  n_agents;   /* agents, >= 1; particles N = 2 n_agents <= 2^30           */
     double   L;          /* box side, exactly representable in FP32, >= 3 r_c         */
-    double   r_c;        /* pair cutoff (Eq. 2.2), > 0; cells per side n_c = floor(L/r_c) */
+    double   r_c;        /* pair cutoff (Eq. 2.2), > 0; cells per side
+                            n_c = floor(L / (r_c + skin)), >= 3                      */
     double   A;          /* conservative amplitude (Eq. 2.3), >= 0                    */
     double   gamma;      /* pair friction (Eq. 2.3), >= 0                             */
     double   kT;         /* thermal energy (Eq. 2.3), >= 0; sigma = sqrt(2 gamma kT)  */
@@ -74,8 +75,16 @@ typedef struct dpd_params {
                             1: Philox2x32-10 on (min id, max id), key folds seed and step */
     int32_t  sp_split;   /* 0: f_sp/2 on head and tail; 1: f_sp on the head only      */
     int32_t  bin_M_max;  /* largest grid side dpd_bin_velocity will be asked for (0: 256) */
-    int32_t  tile;       /* pair-kernel tile side in cells, 1..8 (0: 8 x 7 cells)     */
-    int32_t  reserved[3];
+    int32_t  tile;       /* pair-kernel tile side in cells, 1..8 (0: about 56 cells)   */
+    float    skin;       /* Verlet skin (>= 0, in units of length).  0: the cell list
+                            is rebuilt every step with cells of width >= r_c.  > 0:
+                            cells are >= r_c + skin wide and a rebuild also stores,
+                            per tile, every pair closer than r_c + skin; later steps
+                            test only those pairs, until some particle has moved more
+                            than skin / 2 since the rebuild, which triggers the next
+                            one (checked on the device, every step).  Results are
+                            bitwise the same for every skin. */
+    int32_t  reserved[2];
 } dpd_params;
 
 typedef struct dpd_handle dpd_handle;
@@ -154,11 +163,14 @@ int dpd_sync(dpd_handle* h);
 /* The cell list of the current state: cell_start_out device int32[n_c^2 + 1]
  * (first slot of each cell, row-major cells cy * n_c + cx with
  * c = min(n_c - 1, floor(x * n_c / L)) per axis in FP64), ids_out device
- * int32[N] (particle ids ordered by (cell, id)).  Synchronises the stream. */
+ * int32[N] (particle ids ordered by (cell, id)).  With a Verlet skin it is the
+ * list of the last rebuild: cells floor(L / (r_c + skin)) per side, binned
+ * from the positions of that step (no particle has moved more than skin / 2
+ * since).  Synchronises the stream. */
 int dpd_get_cells(dpd_handle* h, int32_t* cell_start_out, int32_t* ids_out);
 
-/* Cells per side of the cell list for p (n_c = floor(L / r_c)), or a negative
- * error code. */
+/* Cells per side of the cell list for p (n_c = floor(L / (r_c + skin)), the
+ * skin being 0 unless set), or a negative error code. */
 int64_t dpd_cells_per_side(const dpd_params* p);
 
 /* The generator output for n pairs (i[k], j[k]) at `step` with p's seed,
@@ -177,6 +189,13 @@ int dpd_set_profiling(dpd_handle* h, int32_t on);
 /* Total device time (ms) and number of the bracketed launches of the fused
  * pair kernel since profiling was switched on.  Synchronises the stream. */
 int dpd_pair_kernel_time(dpd_handle* h, double* ms_total, int64_t* launches);
+
+/* Number of steps since dpd_create that rebuilt the cell list under a Verlet
+ * skin (skin > 0: the first step of a dpd_step call after dpd_create,
+ * dpd_set_state, dpd_forces or a windowed / centre-of-mass dpd_bin_velocity,
+ * and every step after one on which some particle had moved more than skin / 2
+ * since the last rebuild); 0 without a skin.  Synchronises the stream. */
+int dpd_cell_list_rebuilds(dpd_handle* h, int64_t* rebuilds);
 
 /* Plain device-to-device copy of `bytes` (multiple of 16) by a simple
  * streaming kernel, for calibrating hardware byte counters.  Enqueued on

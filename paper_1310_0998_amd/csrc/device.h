@@ -27,6 +27,9 @@ struct DevParams {
     int wmul_full;    // ceil(2^16 / (tile_x + 2)): local cell -> row by multiply-shift
     int wmul_last;    // the same for the narrower last tile column
     double inv_ntx;   // 1 / ntx: tile row = floor((tile + 1/2) / ntx) by one multiply
+    int skin_on;      // Verlet skin in use
+    float list_rc2;   // (r_c + skin)^2, rounded up: pairs kept in the tile lists
+    float half_skin2; // (skin / 2)^2, rounded down: displacement that forces a rebuild
     int noise_kind;   // 0 Gaussian, 1 uniform
     int rng_kind;     // 0 Philox4x32-10, 1 Philox2x32-10
     float L;          // box side (FP32)

@@ -25,6 +25,7 @@ struct Layout {
     size_t off_Ax, off_Au, off_Aid, off_Bx, off_Bu, off_Bid;
     size_t off_key, off_rank, off_src, off_count, off_cs;
     size_t off_scan_part, off_red, off_Fs, off_binacc, off_status, off_ovf;
+    size_t off_count2, off_xref, off_rec, off_flags;  // Verlet skin
     size_t total;
 };
 
@@ -65,8 +66,13 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
         *err = fmt("L = %.17g is not exactly representable in FP32", p->L);
         return DPD_EINVAL;
     }
-    const double ncd = std::floor(p->L / p->r_c);
-    if (!(ncd >= 3.0)) { *err = "L must be at least 3 r_c (n_c >= 3)"; return DPD_EINVAL; }
+    if (!std::isfinite((double)p->skin) || p->skin < 0.0f || (double)p->skin > 0.5 * p->L) {
+        *err = "skin must be finite, >= 0 and below L / 2";
+        return DPD_EINVAL;
+    }
+    const double width = p->r_c + (double)p->skin;  // smallest cell width
+    const double ncd = std::floor(p->L / width);
+    if (!(ncd >= 3.0)) { *err = "L must be at least 3 (r_c + skin) (n_c >= 3)"; return DPD_EINVAL; }
     if (ncd > 46340.0) { *err = "too many cells (n_c^2 must fit in int32)"; return DPD_EINVAL; }
     const double vals[] = {p->A, p->gamma, p->kT, p->kappa, p->bond_l, p->gamma_s};
     for (double v : vals)
@@ -89,9 +95,17 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     P.N = (int)(2 * p->n_agents);
     P.nc = (int)ncd;
     P.n_cells = P.nc * P.nc;
-    // tile + halo must not wrap onto itself: tile side <= n_c - 2
-    P.tile_x = std::min(p->tile ? p->tile : kTileX, P.nc - 2);
-    P.tile_y = std::min(p->tile ? p->tile : kTileY, P.nc - 2);
+    // tile + halo must not wrap onto itself: tile side <= n_c - 2.  With a skin
+    // the cells are wider; the default tile keeps about 56 particles.
+    int tx = kTileX, ty = kTileY;
+    if (p->skin > 0.0f) {
+        const double cell_n = (2.0 * (double)p->n_agents) / ((double)ncd * ncd);  // particles per cell
+        const double sc = std::sqrt(std::max(cell_n, 1e-9));
+        tx = std::max(1, std::min(kTileMax, (int)std::lround(kTileX / sc)));
+        ty = std::max(1, std::min(kTileMax, (int)std::lround(kTileY / sc)));
+    }
+    P.tile_x = std::min(p->tile ? p->tile : tx, P.nc - 2);
+    P.tile_y = std::min(p->tile ? p->tile : ty, P.nc - 2);
     P.ntx = (P.nc + P.tile_x - 1) / P.tile_x;
     P.nty = (P.nc + P.tile_y - 1) / P.tile_y;
     {
@@ -126,6 +140,15 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     P.L_d = p->L;
     P.dt_d = p->dt;
     P.inv_w = (double)P.nc / p->L;
+    P.skin_on = p->skin > 0.0f ? 1 : 0;
+    {
+        // pairs listed up to r_c + skin (rounded up); a rebuild once some particle
+        // is more than skin / 2 from its rebuild position (rounded down)
+        const double lr = p->r_c + (double)p->skin;
+        P.list_rc2 = (float)(lr * lr * (1.0 + 1e-6));
+        const double hs = 0.5 * (double)p->skin;
+        P.half_skin2 = (float)(hs * hs * (1.0 - 1e-6));
+    }
     P.seed_lo = (uint32_t)(p->seed & 0xffffffffu);
     P.seed_hi = (uint32_t)(p->seed >> 32);
 
@@ -158,6 +181,14 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     L.off_status = take(16);
     L.off_ovf = take(((size_t)d->n_tiles + 1) * 4);
     L.off_scan_part = take((size_t)d->n_scan_blocks * 4);
+    L.off_flags = take(64);  // two displacement flags (by step parity)
+    if (P.skin_on) {
+        L.off_count2 = take((size_t)P.n_cells * 4);
+        L.off_xref = take(N * 8);
+        L.off_rec = take((size_t)d->n_tiles * kRecStride);
+    } else {
+        L.off_count2 = L.off_xref = L.off_rec = 0;
+    }
     L.total = o;
     return DPD_OK;
 }
@@ -176,6 +207,11 @@ struct dpd_handle {
     unsigned* status;
     int* ovf;  // [0]: count of tiles left to the overflow kernel, then their indices
     int* scan_part;
+    // Verlet skin: second counter array, rebuild positions, tile records, flags
+    int* count2;
+    float2* xref;
+    unsigned char* rec;
+    int* flags;
     double* red;
     long long* binacc;
     int64_t step;
@@ -221,20 +257,29 @@ int fail(dpd_handle* h, int code, const std::string& msg) {
 // members by id itself.  With id_of_input != NULL every cell is also ordered by
 // id here (only for the state loaded with a given force, which no pair kernel
 // passes through before it is stored).
-int bin_from_counts(dpd_handle* h, const int* id_of_input) {
+int bin_from_counts(dpd_handle* h, int* count, const int* rebuild, int* moved_clear,
+                    const int* id_of_input) {
     const DevParams& P = h->d.P;
     const int G = h->d.n_scan_blocks;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(G), dim3(kBlock), 0, h->stream, (const int*)h->count,
-                       P.n_cells, h->scan_part);
-    hipLaunchKernelGGL(k_scan_final, dim3(G), dim3(kBlock), 0, h->stream, h->count, P.n_cells,
-                       (const int*)h->scan_part, h->cs, h->ovf);
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
-                       (const int*)h->key, (const int*)h->rank, (const int*)h->cs, h->src);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(G), dim3(kBlock), 0, h->stream, (const int*)count,
+                       P.n_cells, h->scan_part, rebuild, moved_clear, h->flags + 2);
+    hipLaunchKernelGGL(k_scan_final, dim3(G), dim3(kBlock), 0, h->stream, count, P.n_cells,
+                       (const int*)h->scan_part, h->cs, h->ovf, rebuild);
+    hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(P.N), 4096)), dim3(kBlock), 0, h->stream,
+                       P.N, (const int*)h->key, (const int*)h->rank, (const int*)h->cs, h->src,
+                       rebuild);
     if (id_of_input)
         hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(P.n_cells)), dim3(kBlock), 0, h->stream,
                            P.n_cells, (const int*)h->cs, h->src, id_of_input);
     LAUNCHCHK(h);
     return DPD_OK;
+}
+
+// Per-cell counter array of step s (with a Verlet skin the two arrays alternate
+// by step parity: step s fills the one for the keys of x_{s+1} while the other,
+// consumed by the binning of step s, is cleared tile by tile).
+int* counter_of(dpd_handle* h, int64_t s) {
+    return (h->count2 && (s & 1)) ? h->count2 : h->count;
 }
 
 int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
@@ -258,12 +303,19 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
     PairArgs b = a;
     b.ovf_count = h->ovf;
     b.ovf_list = h->ovf + 1;
-    if (mode == MODE_STEP)
-        hipLaunchKernelGGL(k_pair<MODE_STEP>, dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
+    // the Verlet-skin variant of the kernel only where a skin is set (a force
+    // evaluation alone keeps no record)
+    const bool skin = P.skin_on && mode != MODE_FORCES;
+    if (mode == MODE_STEP && skin)
+        hipLaunchKernelGGL((k_pair<MODE_STEP, true>), dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
+    else if (mode == MODE_STEP)
+        hipLaunchKernelGGL((k_pair<MODE_STEP, false>), dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
+    else if (mode == MODE_FINAL && skin)
+        hipLaunchKernelGGL((k_pair<MODE_FINAL, true>), dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
     else if (mode == MODE_FINAL)
-        hipLaunchKernelGGL(k_pair<MODE_FINAL>, dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
+        hipLaunchKernelGGL((k_pair<MODE_FINAL, false>), dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
     else
-        hipLaunchKernelGGL(k_pair<MODE_FORCES>, dim3(G), dim3(kWave), 0, h->stream, P, b, 0);
+        hipLaunchKernelGGL((k_pair<MODE_FORCES, false>), dim3(G), dim3(kWave), 0, h->stream, P, b, 0);
     LAUNCHCHK(h);
     if (timed) {
         HIPCHK(h, hipEventRecord(h->ev_stop[ev], h->stream));
@@ -315,6 +367,9 @@ int unprepare(dpd_handle* h) {
     if (!h->prepared) return DPD_OK;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(h->d.P.n_cells)), dim3(kBlock), 0, h->stream,
                        h->count, 0, (long long)h->d.P.n_cells);
+    if (h->count2)
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(h->d.P.n_cells)), dim3(kBlock), 0, h->stream,
+                           h->count2, 0, (long long)h->d.P.n_cells);
     LAUNCHCHK(h);
     h->prepared = false;
     return DPD_OK;
@@ -389,6 +444,10 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
         h->status = (unsigned*)(w + L.off_status);
         h->ovf = (int*)(w + L.off_ovf);
         h->scan_part = (int*)(w + L.off_scan_part);
+        h->flags = (int*)(w + L.off_flags);
+        h->count2 = d.P.skin_on ? (int*)(w + L.off_count2) : nullptr;
+        h->xref = d.P.skin_on ? (float2*)(w + L.off_xref) : nullptr;
+        h->rec = d.P.skin_on ? (unsigned char*)(w + L.off_rec) : nullptr;
         h->step = 0;
         h->have_state = false;
         h->prepared = false;
@@ -405,6 +464,15 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
                            h->count, 0, (long long)d.P.n_cells);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, (int*)h->status, 0, 4LL);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, h->ovf, 0, 1LL);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, h->flags, 0, 16LL);
+        if (d.P.skin_on) {
+            hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(d.P.n_cells)), dim3(kBlock), 0, h->stream,
+                               h->count2, 0, (long long)d.P.n_cells);
+            // no tile record is valid before the first rebuild
+            const long long words = (long long)d.n_tiles * (long long)(kRecStride / 4);
+            hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(words)), dim3(kBlock), 0, h->stream,
+                               (int*)h->rec, 0, words);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             std::string m = fmt("kernel launch: %s", hipGetErrorString(e));
@@ -440,7 +508,7 @@ int dpd_set_state(dpd_handle* h, const float* x, const float* v, int64_t step, c
                            (const float2*)x, (const float2*)v, h->Ax, h->Au, h->Aid, h->key,
                            h->rank, h->count, h->status);
         LAUNCHCHK(h);
-        int rc = bin_from_counts(h, F ? h->Aid : nullptr);
+        int rc = bin_from_counts(h, h->count, nullptr, nullptr, F ? h->Aid : nullptr);
         if (rc) return rc;
         if (F) {
             hipLaunchKernelGGL(k_gather_state, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
@@ -489,11 +557,15 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
             inu = h->prep_u;
             inid = h->prep_id;
         } else {
-            // first half kick + drift from the stored state
+            // first half kick + drift from the stored state; with a skin the first
+            // step rebuilds
             hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
                                (const float2*)h->Sx, (const float2*)h->Sv, (const float2*)h->SF,
-                               (const int*)h->Sid, h->Ax, h->Au, h->Aid, h->key, h->rank, h->count,
-                               h->status);
+                               (const int*)h->Sid, h->Ax, h->Au, h->Aid, h->key, h->rank,
+                               counter_of(h, h->step), h->status);
+            if (P.skin_on)
+                hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream,
+                                   h->flags + (h->step & 1), 1, 1LL);
             LAUNCHCHK(h);
             inx = h->Ax;
             inu = h->Au;
@@ -506,7 +578,13 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
         outid = in_a ? h->Bid : h->Aid;
         int rec = 0;
         for (int k = 1; k <= n_steps; ++k) {
-            int rc = bin_from_counts(h, nullptr);
+            // forces of step s = step + k: the binning consumes the keys of x_s
+            // (counters of step s - 1) if this step rebuilds
+            const int64_t s = h->step + k;
+            int* consumed = counter_of(h, s - 1);
+            const int* rebuild = P.skin_on ? h->flags + ((s - 1) & 1) : nullptr;
+            int* moved = P.skin_on ? h->flags + (s & 1) : nullptr;
+            int rc = bin_from_counts(h, consumed, rebuild, moved, nullptr);
             if (rc) return rc;
             const bool last = (k == n_steps);
             const bool red = want_pk && (k % reduce_every == 0);
@@ -521,7 +599,14 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
             a.step = (uint32_t)((uint64_t)(h->step + k) & 0xffffffffu);
             a.keyout = h->key;
             a.rankout = h->rank;
-            a.count = h->count;
+            a.count = counter_of(h, s);
+            if (P.skin_on) {
+                a.rebuild = rebuild;
+                a.rec = h->rec;
+                a.xref = h->xref;
+                a.moved = moved;
+                a.count_clear = consumed;
+            }
             if (last) {
                 a.xout = h->Sx;
                 a.uout = h->Sv;
@@ -575,7 +660,7 @@ int dpd_forces(dpd_handle* h, float* F_out) {
         hipLaunchKernelGGL(k_key_rank, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
                            (const float2*)h->Sx, h->key, h->rank, h->count);
         LAUNCHCHK(h);
-        int rc = bin_from_counts(h, nullptr);
+        int rc = bin_from_counts(h, h->count, nullptr, nullptr, nullptr);
         if (rc) return rc;
         PairArgs a = {};
         a.cs = h->cs;
@@ -752,6 +837,16 @@ int dpd_pair_kernel_time(dpd_handle* h, double* ms_total, int64_t* launches) {
     h->ev_used = 0;
     if (ms_total) *ms_total = h->prof_ms;
     if (launches) *launches = h->prof_n;
+    return DPD_OK;
+}
+
+int dpd_cell_list_rebuilds(dpd_handle* h, int64_t* rebuilds) {
+    if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
+    if (!rebuilds) return fail(h, DPD_EINVAL, "rebuilds is NULL");
+    int n = 0;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(&n, h->flags + 2, sizeof n, hipMemcpyDeviceToHost));
+    *rebuilds = n;
     return DPD_OK;
 }
 

@@ -27,6 +27,22 @@ constexpr int kCap = 192;   // staged particles (tile + halo); indices fit a byt
 constexpr int kTP = 128;    // tile particles (7-bit index in a kept pair)
 constexpr int kEcap = 256;  // kept pairs per tile
 constexpr int kItems = kCap / kWave;  // staged particles per lane
+constexpr int kLcap = 512;  // listed pairs per tile (Verlet skin)
+
+// What a rebuild stores per tile for the steps that follow it (Verlet skin):
+// the staged set (global slot and tile index of every staged particle, in the
+// canonical order of the rebuild), the tile particles' staged indices and
+// bonded partners, and every tile pair closer than r_c + skin (staged index of
+// the tile particle << 8 | staged index of the other).
+struct TileRec {
+    int ntile, total, nlist, valid;
+    int slot[kCap];
+    unsigned char tix[kCap];
+    unsigned char tslot[kTP];
+    unsigned char partner[kTP];
+    unsigned short pairs[kLcap];
+};
+constexpr size_t kRecStride = (sizeof(TileRec) + 255) / 256 * 256;
 
 enum PairMode { MODE_STEP = 0, MODE_FINAL = 1, MODE_FORCES = 2 };
 
@@ -50,6 +66,12 @@ struct PairArgs {
     unsigned* status;
     int* ovf_count;     // tiles handed to the global-memory kernel (cleared by the cell-count scan)
     int* ovf_list;      // their tile indices
+    // Verlet skin (all null without it)
+    const int* rebuild; // nonzero: this step rebuilds the cell list (null: always)
+    unsigned char* rec; // tile records, kRecStride bytes each
+    float2* xref;       // position of every slot at the last rebuild
+    int* moved;         // set when a particle has moved more than skin / 2 since then
+    int* count_clear;   // the other per-cell counter array, cleared cell by cell
     uint32_t step;      // step number of the force evaluation (mod 2^32)
 };
 
@@ -190,11 +212,29 @@ __device__ __forceinline__ float from_fixed(long long q) {
     return (float)((double)q * kFixInv);            // (double)q exact for |q| < 2^53
 }
 
-// Finish one particle: kicks, drift, key and outputs at sorted slot g.
-template <int MODE>
+// With a Verlet skin: the position at the last rebuild is recorded (or read),
+// and a particle whose next position is more than skin / 2 from it asks for a
+// rebuild before the next force evaluation.
+__device__ __forceinline__ bool moved_too_far(const DevParams& P, const PairArgs& a, int g,
+                                              float2 xi, float2 xn, bool rebuilt) {
+    float2 xr;
+    if (rebuilt) {
+        a.xref[g] = xi;
+        xr = xi;
+    } else {
+        xr = a.xref[g];
+    }
+    const float dx = minimg_sub(xn.x, xr.x, P), dy = minimg_sub(xn.y, xr.y, P);
+    return !(fmaf(dx, dx, dy * dy) <= P.half_skin2);
+}
+
+// Finish one particle: kicks, drift, key and outputs at sorted slot g.  SKIN:
+// the displacement test of a Verlet skin is compiled in (it also needs a.moved).
+template <int MODE, bool SKIN>
 __device__ __forceinline__ void finish_particle(const DevParams& P, const PairArgs& a, int g,
                                                 float2 xi, float2 ui, int idi, float fx,
-                                                float fy, double rv[3], bool reduce) {
+                                                float fy, double rv[3], bool reduce,
+                                                bool rebuilt = true) {
     const float2 F = make_float2(fx, fy);
     if (MODE == MODE_FORCES) {
         a.xout[g] = xi;
@@ -228,6 +268,7 @@ __device__ __forceinline__ void finish_particle(const DevParams& P, const PairAr
             a.keyout[g] = key;
             a.rankout[g] = atomicAdd(&a.count[key], 1);
             bad |= !finite2(xn) || !finite2(un);
+            if (SKIN && a.moved && moved_too_far(P, a, g, xi, xn, rebuilt)) atomicOr(a.moved, 1);
         }
         if (bad) atomicOr(a.status, kStatusNonFinite);
         return;
@@ -242,15 +283,23 @@ __device__ __forceinline__ void finish_particle(const DevParams& P, const PairAr
     a.keyout[g] = key;
     a.rankout[g] = rank;
     if (!finite2(xn) || !finite2(un)) atomicOr(a.status, kStatusNonFinite);
+    if (SKIN && a.moved && moved_too_far(P, a, g, xi, xn, rebuilt)) atomicOr(a.moved, 1);
 }
 
 // Slow path for a tile that overflows an LDS capacity (dense clusters): one
 // lane per cell walks the cell's members in id order (the canonical slot order)
 // and sums each member's pairs over the full 3x3 stencil straight from global
 // memory.  The sums are fixed point, so the result is bitwise the fast path's.
-template <int MODE>
+// REBUILT is a template parameter, not a runtime flag: the lanes' loops here
+// diverge, and a wave-uniform flag tested inside them was compiled into a lane
+// mask taken under one loop's exec mask and reused under another's, which sent
+// some lanes down the wrong side of the test.  The velocity sums are always
+// accumulated (the caller decides whether to store them).
+template <int MODE, bool REBUILT>
 __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int cy0, int tw,
-                            int th, double rv[3], bool reduce) {
+                            int th, double rv[3]) {
+    // between rebuilds (Verlet skin) the data already sits in the cell order of
+    // the last rebuild: slot g holds particle g
     const int nc = P.nc;
     for (int ic = threadIdx.x; ic < tw * th; ic += blockDim.x) {
         const int gx = cx0 + ic % tw, gy = cy0 + ic / tw;
@@ -261,7 +310,7 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
             // the member with the r-th smallest id (ids are distinct)
             int g = b, idi = 0x7FFFFFFF, p = 0;
             for (int g1 = b; g1 < e; ++g1) {
-                int p1 = a.src[g1];
+                int p1 = REBUILT ? a.src[g1] : g1;
                 if ((unsigned)p1 >= (unsigned)P.N) {
                     atomicOr(a.status, kStatusBinning);
                     p1 = 0;
@@ -285,7 +334,7 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
                     const int b2 = a.cs[c2], e2 = a.cs[c2 + 1];
                     for (int g2 = b2; g2 < e2; ++g2) {
                         if (g2 == g) continue;
-                        int q = a.src[g2];
+                        int q = REBUILT ? a.src[g2] : g2;
                         if ((unsigned)q >= (unsigned)P.N) q = 0;
                         const int idj = a.idin[q];
                         const float2 xj = a.xin[q];
@@ -317,7 +366,7 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
                 fx -= P.gamma_s * ui.x;
                 fy -= P.gamma_s * ui.y;
             }
-            finish_particle<MODE>(P, a, b + r, xi, ui, idi, fx, fy, rv, reduce);
+            finish_particle<MODE, true>(P, a, b + r, xi, ui, idi, fx, fy, rv, true, REBUILT);
         }
     }
 }
@@ -378,22 +427,30 @@ __device__ __forceinline__ void tile_reduce(const PairArgs& a, int t, double rv[
 }
 
 // The fused pair / agent / integrator kernel: one 64-lane wavefront per tile of
-// up to kTileX x kTileY cells, the tile and a one-cell halo staged in LDS.
+// up to kTileMax x kTileMax cells, the tile and a one-cell halo staged in LDS.
+// On a step that rebuilds the cell list (every step without a Verlet skin):
 //   S  stage: cell counts from cell_start (one scan gives the staged and the
 //      tile offsets of every local cell); each staged particle is gathered
 //      through src and placed at its rank by id within its cell, so the LDS
 //      order is the canonical (cell, id) order;
-//   A  every tile particle tests the staged particles of its 3x3 stencil (three
-//      contiguous row segments) and keeps a pair if the other particle is in
-//      the halo or comes later in the canonical order, so each pair within the
-//      tile is kept once; kept pairs are compacted by ballot; the bonded
-//      partner is recorded;
+//   A  every tile particle tests the staged particles of its half stencil and
+//      keeps a pair if the other particle is in the halo or comes later in the
+//      canonical order, so each pair within the tile is kept once; kept pairs
+//      are compacted by ballot; the bonded partner is recorded.  With a skin,
+//      the pairs closer than r_c + skin also go to the tile's record.
+// On a step between rebuilds (Verlet skin), instead:
+//   L  the staged set is read back from the tile's record (the data already
+//      sits in the order of the rebuild), and only the recorded pairs are
+//      tested;
+// and then on every step:
 //   B  one force evaluation per kept pair (Eqs. 2.2-2.4), added in fixed point
 //      to the first particle and subtracted from the second (Newton's third
 //      law) with LDS integer atomics - exact, so the order does not matter;
 //   C  every tile particle adds its agent forces and finishes the step.
-// A tile that overflows an LDS capacity is processed by tile_global instead.
-template <int MODE>
+// A tile that overflows an LDS capacity is left to k_pair_overflow.
+// SKIN compiles the Verlet-skin code (records, list steps, displacement test)
+// in; without it the kernel carries none of it.
+template <int MODE, bool SKIN>
 __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int reduce) {
     __shared__ int s_ofs[kLocMax + 1];       // first staged index of each local cell
     __shared__ int s_gbeg[kLocMax];          // first global slot of each local cell
@@ -401,6 +458,7 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
     __shared__ unsigned char s_lcell[kCap];  // local cell of each staged index
     __shared__ float4 s_rec[kCap];           // x, y, id, tile index (0xFF: halo)
     __shared__ float2 s_u[kCap];
+    __shared__ int s_slot[SKIN ? kCap : 1];  // global slot of each staged index (skin only)
     __shared__ unsigned char s_tslot[kTP];   // tile index -> staged index
     __shared__ unsigned char s_partner[kTP]; // tile index -> staged index of the partner
     __shared__ unsigned short s_pair[kEcap]; // kept pair: staged index of the tile particle << 8 | other
@@ -426,235 +484,324 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
     const int wmul = (cx0 + tw == P.nc) ? P.wmul_last : P.wmul_full;
     const bool edge = (cx0 == 0) || (cx0 + tw >= P.nc) || (cy0 == 0) || (cy0 + th >= P.nc);
     const int lane = threadIdx.x;
+    const bool rebuild = !SKIN || (MODE == MODE_FORCES) || a.rebuild == nullptr || *a.rebuild != 0;
+    const bool keep_list = SKIN && MODE != MODE_FORCES;
+    TileRec* R = SKIN ? reinterpret_cast<TileRec*>(a.rec + (size_t)tile * kRecStride) : nullptr;
+    if (SKIN && a.count_clear) {  // the counters this step does not fill: this tile's cells
+        const int row = lane >> 3, col = lane & 7;
+        if (col < tw && row < th) a.count_clear[(cy0 + row) * P.nc + cx0 + col] = 0;
+    }
 
-    // ---- S1: counts of the two local cells 2*lane and 2*lane + 1
-    int cnt[2] = {0, 0};
-    bool tcell[2] = {false, false};
-    bool big = false;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int lc = 2 * lane + h;
-        if (lc < nloc) {
-            const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
-            const int c = (int)__umul24((unsigned)wrap_cell(cy0 - 1 + ly, P.nc), (unsigned)P.nc) +
-                          wrap_cell(cx0 - 1 + lx, P.nc);
-            const int b = a.cs[c];
-            const int n = a.cs[c + 1] - b;
-            s_gbeg[lc] = b;
-            big |= (n > kCap) || (n < 0);
-            cnt[h] = min(max(n, 0), kCap);
-            tcell[h] = (lx >= 1 && lx <= tw && ly >= 1 && ly <= th);
-        }
-    }
-    // staged counts in the low 16 bits, tile counts in the high 16 (each <= 100 * kCap)
-    const int v0 = cnt[0] + (tcell[0] ? cnt[0] << 16 : 0);
-    const int v1 = cnt[1] + (tcell[1] ? cnt[1] << 16 : 0);
-    int tot;
-    const int ex = wave_scan_excl(v0 + v1, tot);
-    const int total = tot & 0xFFFF, ntile = tot >> 16;
-    const bool fits = !__any(big) && total <= kCap && ntile <= kTP;
-    if (2 * lane < nloc) {
-        s_ofs[2 * lane] = ex & 0xFFFF;
-        s_tofs[2 * lane] = (unsigned char)min(ex >> 16, 255);
-    }
-    if (2 * lane + 1 < nloc) {
-        s_ofs[2 * lane + 1] = (ex + v0) & 0xFFFF;
-        s_tofs[2 * lane + 1] = (unsigned char)min((ex + v0) >> 16, 255);
-    }
-    if (lane == 0) s_ofs[nloc] = total;
-    __syncthreads();
-
-    double rv[3] = {0.0, 0.0, 0.0};
-    bool done = false;
-    if (fits) {
-        // ---- S2: staged index -> local cell
+    int ntile = 0, E = 0;
+    bool ok = false;
+    if (rebuild) {
+        // ---- S1: counts of the two local cells 2*lane and 2*lane + 1
+        int cnt[2] = {0, 0};
+        bool tcell[2] = {false, false};
+        bool big = false;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int lc = 2 * lane + h;
             if (lc < nloc) {
-                const int o = s_ofs[lc];
-                for (int q = o; q < o + cnt[h]; ++q) s_lcell[q] = (unsigned char)lc;
+                const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
+                const int c = (int)__umul24((unsigned)wrap_cell(cy0 - 1 + ly, P.nc), (unsigned)P.nc) +
+                              wrap_cell(cx0 - 1 + lx, P.nc);
+                const int b = a.cs[c];
+                const int n = a.cs[c + 1] - b;
+                s_gbeg[lc] = b;
+                big |= (n > kCap) || (n < 0);
+                cnt[h] = min(max(n, 0), kCap);
+                tcell[h] = (lx >= 1 && lx <= tw && ly >= 1 && ly <= th);
             }
         }
+        // staged counts in the low 16 bits, tile counts in the high 16 (each <= 100 * kCap)
+        const int v0 = cnt[0] + (tcell[0] ? cnt[0] << 16 : 0);
+        const int v1 = cnt[1] + (tcell[1] ? cnt[1] << 16 : 0);
+        int tot;
+        const int ex = wave_scan_excl(v0 + v1, tot);
+        const int total = tot & 0xFFFF;
+        ntile = tot >> 16;
+        const bool fits = !__any(big) && total <= kCap && ntile <= kTP;
+        if (2 * lane < nloc) {
+            s_ofs[2 * lane] = ex & 0xFFFF;
+            s_tofs[2 * lane] = (unsigned char)min(ex >> 16, 255);
+        }
+        if (2 * lane + 1 < nloc) {
+            s_ofs[2 * lane + 1] = (ex + v0) & 0xFFFF;
+            s_tofs[2 * lane + 1] = (unsigned char)min((ex + v0) >> 16, 255);
+        }
+        if (lane == 0) s_ofs[nloc] = total;
         __syncthreads();
-        // ---- S3: gather in arrival order
-        float2 xq[kItems], uq[kItems];
-        int idq[kItems], lcq[kItems];
+
+        if (fits) {
+            // ---- S2: staged index -> local cell
 #pragma unroll
-        for (int r = 0; r < kItems; ++r) {
-            const int q = r * kWave + lane;
-            idq[r] = 0;
-            lcq[r] = 0;
-            xq[r] = make_float2(0.f, 0.f);
-            uq[r] = make_float2(0.f, 0.f);
-            if (q < total) {
-                const int lc = s_lcell[q];
-                int p = a.src[s_gbeg[lc] + (q - s_ofs[lc])];
-                if ((unsigned)p >= (unsigned)P.N) {
+            for (int h = 0; h < 2; ++h) {
+                const int lc = 2 * lane + h;
+                if (lc < nloc) {
+                    const int o = s_ofs[lc];
+                    for (int q = o; q < o + cnt[h]; ++q) s_lcell[q] = (unsigned char)lc;
+                }
+            }
+            __syncthreads();
+            // ---- S3: gather in arrival order
+            float2 xq[kItems], uq[kItems];
+            int idq[kItems], lcq[kItems];
+#pragma unroll
+            for (int r = 0; r < kItems; ++r) {
+                const int q = r * kWave + lane;
+                idq[r] = 0;
+                lcq[r] = 0;
+                xq[r] = make_float2(0.f, 0.f);
+                uq[r] = make_float2(0.f, 0.f);
+                if (q < total) {
+                    const int lc = s_lcell[q];
+                    int p = a.src[s_gbeg[lc] + (q - s_ofs[lc])];
+                    if ((unsigned)p >= (unsigned)P.N) {
+                        atomicOr(a.status, kStatusBinning);
+                        p = 0;
+                    }
+                    lcq[r] = lc;
+                    idq[r] = a.idin[p];
+                    xq[r] = a.xin[p];
+                    uq[r] = a.uin[p];
+                    s_tmpid[q] = idq[r];
+                }
+            }
+            __syncthreads();
+            // ---- S4: place every particle at its rank by id within its cell
+#pragma unroll
+            for (int r = 0; r < kItems; ++r) {
+                const int q = r * kWave + lane;
+                if (q < total) {
+                    const int lc = lcq[r];
+                    const int b = s_ofs[lc], e = s_ofs[lc + 1];
+                    int rank = 0;
+                    for (int t = b; t < e; ++t) rank += (s_tmpid[t] < idq[r]) ? 1 : 0;
+                    const int qs = b + rank;
+                    const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
+                    int ti = 0xFF;
+                    if (lx >= 1 && lx <= tw && ly >= 1 && ly <= th) {
+                        ti = s_tofs[lc] + rank;
+                        s_tslot[ti] = (unsigned char)qs;
+                        s_partner[ti] = 0xFF;
+                    }
+                    const int g = s_gbeg[lc] + rank;
+                    s_rec[qs] = make_float4(xq[r].x, xq[r].y, __int_as_float(idq[r]), __int_as_float(ti));
+                    s_u[qs] = uq[r];
+                    if constexpr (SKIN) s_slot[qs] = g;
+                    if (keep_list) {
+                        R->slot[qs] = g;
+                        R->tix[qs] = (unsigned char)ti;
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- A: every tile particle tests its half stencil in one loop over up
+            // to three ranges of staged indices:
+            //   own row: the rest of the own cell and the cell to the right (from
+            //            the left neighbour on when that is a halo cell);
+            //   row above: the three cells of the stencil;
+            //   row below: its three cells where they include halo cells (first
+            //            tile row, first or last tile column).
+            // A pair is kept from a particle if the other one is in the halo or
+            // later in the canonical order, so each pair inside the tile is kept
+            // once and each tile-halo pair once, from the tile side.  The bonded
+            // partner is recorded for both members.
+            const int rounds = (ntile + kWave - 1) / kWave;
+            int EL = 0;
+            for (int r = 0; r < rounds; ++r) {
+                const int k = r * kWave + lane;
+                int si = 0, b0 = 0, n0 = 0, b1 = 0, n01 = 0, b2 = 0, n = 0;
+                float4 ri = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (k < ntile) {
+                    si = s_tslot[k];
+                    const int lc = s_lcell[si];
+                    const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
+                    const int dn = (ly - 1) * W + lx - 1, me = ly * W + lx - 1, up = (ly + 1) * W + lx - 1;
+                    b0 = (lx == 1) ? s_ofs[me] : si + 1;
+                    n0 = s_ofs[me + 3] - b0;
+                    const int bu = s_ofs[up];
+                    n01 = n0 + (s_ofs[up + 3] - bu);
+                    b1 = bu - n0;  // j = b1 + t for n0 <= t < n01
+                    int nd = 0, bd = 0;
+                    if (ly == 1 || lx == 1 || lx == tw) {
+                        bd = s_ofs[dn];
+                        nd = s_ofs[dn + 3] - bd;
+                    }
+                    b2 = bd - n01;  // j = b2 + t for n01 <= t < n
+                    n = n01 + nd;
+                    ri = s_rec[si];
+                }
+                const int tmax = __builtin_amdgcn_readfirstlane(wave_max(n));
+                const int pid = __float_as_int(ri.z) ^ 1;
+                int partner = 0xFF, ptile = 0xFF;  // partner's staged index; its tile index
+                // the record of candidate t + 1 is read while candidate t is tested
+                int jn = (0 < n) ? ((0 < n0) ? b0 : ((0 < n01) ? b1 : b2)) : si;
+                float4 rn = s_rec[jn];
+                for (int t = 0; t < tmax; ++t) {
+                    const int j = jn;
+                    const float4 rj = rn;
+                    const int t1 = t + 1;
+                    jn = t1 + ((t1 < n0) ? b0 : ((t1 < n01) ? b1 : b2));
+                    jn = (t1 < n) ? jn : si;
+                    rn = s_rec[jn];
+                    const int tj = __float_as_int(rj.w);
+                    const bool mine = (t < n) && (j != si) && (tj == 0xFF || j > si);
+                    const bool isp = mine && (__float_as_int(rj.z) == pid);
+                    partner = isp ? j : partner;
+                    ptile = isp ? tj : ptile;
+                    const float dx = edge ? minimg_sub(ri.x, rj.x, P) : ri.x - rj.x;
+                    const float dy = edge ? minimg_sub(ri.y, rj.y, P) : ri.y - rj.y;
+                    const float r2 = fmaf(dx, dx, dy * dy);
+                    const unsigned short w = (unsigned short)((si << 8) | j);
+                    const bool keep = mine && !isp && interacts(cutoff_gap(P, dx, dy), r2);
+                    const unsigned long long msk = __ballot(keep);
+                    const int nk = __popcll(msk);
+                    if (E + nk <= kEcap) {
+                        if (keep) s_pair[E + lanes_below(msk)] = w;
+                    }
+                    E += nk;
+                    if (keep_list) {
+                        const bool lk = mine && !isp && r2 > 0.f && r2 < P.list_rc2;
+                        const unsigned long long ml = __ballot(lk);
+                        const int nl = __popcll(ml);
+                        if (EL + nl <= kLcap) {
+                            if (lk) R->pairs[EL + lanes_below(ml)] = w;
+                        }
+                        EL += nl;
+                    }
+                }
+                if (k < ntile) {
+                    if (partner != 0xFF) s_partner[k] = (unsigned char)partner;
+                    if (ptile != 0xFF) s_partner[ptile] = (unsigned char)si;
+                }
+            }
+            __syncthreads();
+            ok = (E <= kEcap) && (!keep_list || EL <= kLcap);
+            if (keep_list) {
+                for (int k = lane; k < ntile; k += kWave) {
+                    R->tslot[k] = s_tslot[k];
+                    R->partner[k] = s_partner[k];
+                }
+                if (lane == 0) {
+                    R->ntile = ntile;
+                    R->total = total;
+                    R->nlist = EL;
+                    R->valid = ok ? 1 : 0;
+                }
+            }
+        } else if (keep_list && lane == 0) {
+            R->valid = 0;
+        }
+    } else if constexpr (SKIN) {
+        // ---- L: between rebuilds: the staged set and the pair list of the record
+        const int valid = R->valid;
+        if (valid) {
+            ntile = min(R->ntile, kTP);
+            const int total = min(R->total, kCap), nlist = min(R->nlist, kLcap);
+            for (int q = lane; q < total; q += kWave) {
+                int g = R->slot[q];
+                if ((unsigned)g >= (unsigned)P.N) {
                     atomicOr(a.status, kStatusBinning);
-                    p = 0;
+                    g = 0;
                 }
-                lcq[r] = lc;
-                idq[r] = a.idin[p];
-                xq[r] = a.xin[p];
-                uq[r] = a.uin[p];
-                s_tmpid[q] = idq[r];
+                const float2 xg = a.xin[g];
+                s_rec[q] = make_float4(xg.x, xg.y, __int_as_float(a.idin[g]), __int_as_float((int)R->tix[q]));
+                s_u[q] = a.uin[g];
+                s_slot[q] = g;
             }
-        }
-        __syncthreads();
-        // ---- S4: place every particle at its rank by id within its cell
-#pragma unroll
-        for (int r = 0; r < kItems; ++r) {
-            const int q = r * kWave + lane;
-            if (q < total) {
-                const int lc = lcq[r];
-                const int b = s_ofs[lc], e = s_ofs[lc + 1];
-                int rank = 0;
-                for (int t = b; t < e; ++t) rank += (s_tmpid[t] < idq[r]) ? 1 : 0;
-                const int qs = b + rank;
-                const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
-                int ti = 0xFF;
-                if (lx >= 1 && lx <= tw && ly >= 1 && ly <= th) {
-                    ti = s_tofs[lc] + rank;
-                    s_tslot[ti] = (unsigned char)qs;
-                    s_partner[ti] = 0xFF;
+            for (int k = lane; k < ntile; k += kWave) {
+                s_tslot[k] = R->tslot[k];
+                s_partner[k] = R->partner[k];
+            }
+            __syncthreads();
+            for (int e0 = 0; e0 < nlist; e0 += kWave) {
+                const int e = e0 + lane;
+                bool keep = false;
+                unsigned short w = 0;
+                if (e < nlist) {
+                    w = R->pairs[e];
+                    const float4 ri = s_rec[w >> 8], rj = s_rec[w & 0xFF];
+                    const float dx = edge ? minimg_sub(ri.x, rj.x, P) : ri.x - rj.x;
+                    const float dy = edge ? minimg_sub(ri.y, rj.y, P) : ri.y - rj.y;
+                    keep = interacts(cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy));
                 }
-                s_rec[qs] = make_float4(xq[r].x, xq[r].y, __int_as_float(idq[r]), __int_as_float(ti));
-                s_u[qs] = uq[r];
-            }
-        }
-        __syncthreads();
-        // ---- A: every tile particle tests its half stencil in one loop over up
-        // to three ranges of staged indices:
-        //   own row: the rest of the own cell and the cell to the right (from the
-        //            left neighbour on when that is a halo cell);
-        //   row above: the three cells of the stencil;
-        //   row below: its three cells where they include halo cells (first tile
-        //            row, first or last tile column).
-        // A pair is kept from a particle if the other one is in the halo or later
-        // in the canonical order, so each pair inside the tile is kept once and
-        // each tile-halo pair once, from the tile side.  The bonded partner is
-        // recorded for both members.
-        const int rounds = (ntile + kWave - 1) / kWave;
-        int E = 0;
-        for (int r = 0; r < rounds; ++r) {
-            const int k = r * kWave + lane;
-            int si = 0, b0 = 0, n0 = 0, b1 = 0, n01 = 0, b2 = 0, n = 0;
-            float4 ri = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (k < ntile) {
-                si = s_tslot[k];
-                const int lc = s_lcell[si];
-                const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
-                const int dn = (ly - 1) * W + lx - 1, me = ly * W + lx - 1, up = (ly + 1) * W + lx - 1;
-                b0 = (lx == 1) ? s_ofs[me] : si + 1;
-                n0 = s_ofs[me + 3] - b0;
-                const int bu = s_ofs[up];
-                n01 = n0 + (s_ofs[up + 3] - bu);
-                b1 = bu - n0;  // j = b1 + t for n0 <= t < n01
-                int nd = 0, bd = 0;
-                if (ly == 1 || lx == 1 || lx == tw) {
-                    bd = s_ofs[dn];
-                    nd = s_ofs[dn + 3] - bd;
-                }
-                b2 = bd - n01;  // j = b2 + t for n01 <= t < n
-                n = n01 + nd;
-                ri = s_rec[si];
-            }
-            const int tmax = __builtin_amdgcn_readfirstlane(wave_max(n));
-            const int pid = __float_as_int(ri.z) ^ 1;
-            int partner = 0xFF, ptile = 0xFF;  // partner's staged index; its tile index
-            // the record of candidate t + 1 is read while candidate t is tested
-            int jn = (0 < n) ? ((0 < n0) ? b0 : ((0 < n01) ? b1 : b2)) : si;
-            float4 rn = s_rec[jn];
-            for (int t = 0; t < tmax; ++t) {
-                const int j = jn;
-                const float4 rj = rn;
-                const int t1 = t + 1;
-                jn = t1 + ((t1 < n0) ? b0 : ((t1 < n01) ? b1 : b2));
-                jn = (t1 < n) ? jn : si;
-                rn = s_rec[jn];
-                const int tj = __float_as_int(rj.w);
-                const bool mine = (t < n) && (j != si) && (tj == 0xFF || j > si);
-                const bool isp = mine && (__float_as_int(rj.z) == pid);
-                partner = isp ? j : partner;
-                ptile = isp ? tj : ptile;
-                const float dx = edge ? minimg_sub(ri.x, rj.x, P) : ri.x - rj.x;
-                const float dy = edge ? minimg_sub(ri.y, rj.y, P) : ri.y - rj.y;
-                const bool keep = mine && !isp && interacts(cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy));
                 const unsigned long long msk = __ballot(keep);
                 const int nk = __popcll(msk);
                 if (E + nk <= kEcap) {
-                    if (keep) s_pair[E + lanes_below(msk)] = (unsigned short)((si << 8) | j);
+                    if (keep) s_pair[E + lanes_below(msk)] = w;
                 }
                 E += nk;
             }
-            if (k < ntile) {
-                if (partner != 0xFF) s_partner[k] = (unsigned char)partner;
-                if (ptile != 0xFF) s_partner[ptile] = (unsigned char)si;
-            }
-        }
-        __syncthreads();
-
-        if (E <= kEcap) {
-            for (int k = lane; k < ntile; k += kWave) {
-                s_acc[k][0] = 0;
-                s_acc[k][1] = 0;
-            }
             __syncthreads();
-            // ---- B: one force per kept pair, exact fixed-point sums
-            bool bad = false;
-            for (int e = lane; e < E; e += kWave) {
-                const int w = s_pair[e];
-                const int so = w >> 8, j = w & 0xFF;
-                const float4 ro = s_rec[so], rj = s_rec[j];
-                const int k = __float_as_int(ro.w);
-                const float dx = edge ? minimg_sub(ro.x, rj.x, P) : ro.x - rj.x;
-                const float dy = edge ? minimg_sub(ro.y, rj.y, P) : ro.y - rj.y;
-                float fx = 0.f, fy = 0.f;
-                add_pair_force(P, dx, dy, cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy), s_u[so],
-                               s_u[j], __float_as_int(ro.z), __float_as_int(rj.z), a.step, fx, fy);
-                bad |= !(__builtin_isfinite(fx) && __builtin_isfinite(fy));
-                const long long qx = to_fixed(fx), qy = to_fixed(fy);
-                atomicAdd((unsigned long long*)&s_acc[k][0], (unsigned long long)qx);
-                atomicAdd((unsigned long long*)&s_acc[k][1], (unsigned long long)qy);
-                const int tj = __float_as_int(rj.w);
-                if (tj != 0xFF) {
-                    atomicAdd((unsigned long long*)&s_acc[tj][0], (unsigned long long)(-qx));
-                    atomicAdd((unsigned long long*)&s_acc[tj][1], (unsigned long long)(-qy));
-                }
-            }
-            if (bad) atomicOr(a.status, kStatusNonFinite);
-            __syncthreads();
-
-            // ---- C: agent forces and integration, tile particles in canonical order
-            for (int r = 0; r < rounds; ++r) {
-                const int k = r * kWave + lane;
-                if (k >= ntile) continue;
-                const int si = s_tslot[k];
-                const int lc = s_lcell[si];
-                const float4 ri = s_rec[si];
-                const float2 xi = make_float2(ri.x, ri.y), ui = s_u[si];
-                const int idi = __float_as_int(ri.z);
-                float fx = from_fixed(s_acc[k][0]), fy = from_fixed(s_acc[k][1]);
-                const int jp = s_partner[k];
-                if (jp != 0xFF) {
-                    const float4 rp = s_rec[jp];
-                    add_agent_force(P, xi, make_float2(rp.x, rp.y), ui, idi, fx, fy);
-                } else {
-                    atomicOr(a.status, kStatusBond);
-                    fx -= P.gamma_s * ui.x;
-                    fy -= P.gamma_s * ui.y;
-                }
-                const int g = s_gbeg[lc] + (si - s_ofs[lc]);
-                finish_particle<MODE>(P, a, g, xi, ui, idi, fx, fy, rv, reduce != 0);
-            }
-            done = true;
+            ok = E <= kEcap;
         }
     }
-    if (!done) {
+
+    double rv[3] = {0.0, 0.0, 0.0};
+    if (!ok) {
         // over an LDS capacity: leave the tile to k_pair_overflow
         if (lane == 0) a.ovf_list[atomicAdd(a.ovf_count, 1)] = tile;
         return;
+    }
+    for (int k = lane; k < ntile; k += kWave) {
+        s_acc[k][0] = 0;
+        s_acc[k][1] = 0;
+    }
+    __syncthreads();
+    // ---- B: one force per kept pair, exact fixed-point sums
+    bool bad = false;
+    for (int e = lane; e < E; e += kWave) {
+        const int w = s_pair[e];
+        const int so = w >> 8, j = w & 0xFF;
+        const float4 ro = s_rec[so], rj = s_rec[j];
+        const int k = __float_as_int(ro.w);
+        const float dx = edge ? minimg_sub(ro.x, rj.x, P) : ro.x - rj.x;
+        const float dy = edge ? minimg_sub(ro.y, rj.y, P) : ro.y - rj.y;
+        float fx = 0.f, fy = 0.f;
+        add_pair_force(P, dx, dy, cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy), s_u[so], s_u[j],
+                       __float_as_int(ro.z), __float_as_int(rj.z), a.step, fx, fy);
+        bad |= !(__builtin_isfinite(fx) && __builtin_isfinite(fy));
+        const long long qx = to_fixed(fx), qy = to_fixed(fy);
+        atomicAdd((unsigned long long*)&s_acc[k][0], (unsigned long long)qx);
+        atomicAdd((unsigned long long*)&s_acc[k][1], (unsigned long long)qy);
+        const int tj = __float_as_int(rj.w);
+        if (tj != 0xFF) {
+            atomicAdd((unsigned long long*)&s_acc[tj][0], (unsigned long long)(-qx));
+            atomicAdd((unsigned long long*)&s_acc[tj][1], (unsigned long long)(-qy));
+        }
+    }
+    if (bad) atomicOr(a.status, kStatusNonFinite);
+    __syncthreads();
+
+    // ---- C: agent forces and integration, tile particles in canonical order
+    const int rounds = (ntile + kWave - 1) / kWave;
+    for (int r = 0; r < rounds; ++r) {
+        const int k = r * kWave + lane;
+        if (k >= ntile) continue;
+        const int si = s_tslot[k];
+        const float4 ri = s_rec[si];
+        const float2 xi = make_float2(ri.x, ri.y), ui = s_u[si];
+        const int idi = __float_as_int(ri.z);
+        float fx = from_fixed(s_acc[k][0]), fy = from_fixed(s_acc[k][1]);
+        const int jp = s_partner[k];
+        if (jp != 0xFF) {
+            const float4 rp = s_rec[jp];
+            add_agent_force(P, xi, make_float2(rp.x, rp.y), ui, idi, fx, fy);
+        } else {
+            atomicOr(a.status, kStatusBond);
+            fx -= P.gamma_s * ui.x;
+            fy -= P.gamma_s * ui.y;
+        }
+        int g;
+        if constexpr (SKIN) {
+            g = s_slot[si];
+        } else {
+            const int lc = s_lcell[si];
+            g = s_gbeg[lc] + (si - s_ofs[lc]);
+        }
+        finish_particle<MODE, SKIN>(P, a, g, xi, ui, idi, fx, fy, rv, reduce != 0, rebuild);
     }
     if (reduce) tile_reduce(a, tile, rv);
 }
@@ -662,16 +809,25 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
 // The tiles k_pair left over, one 64-lane wavefront per listed tile, through
 // the global-memory path (same results bit for bit).  Launched right after
 // k_pair with a fixed grid; with an empty list every wavefront exits at once.
-template <int MODE>
-__global__ __launch_bounds__(kWave) void k_pair_overflow(DevParams P, PairArgs a, int reduce) {
-    const int n = *a.ovf_count;
+template <int MODE, bool REBUILT>
+__device__ __forceinline__ void overflow_tiles(const DevParams& P, const PairArgs& a, int n,
+                                               int reduce) {
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int tile = a.ovf_list[i];
         const TileGeom G = tile_geom(P, tile);
         double rv[3] = {0.0, 0.0, 0.0};
-        tile_global<MODE>(P, a, G.cx0, G.cy0, G.tw, G.th, rv, reduce != 0);
+        tile_global<MODE, REBUILT>(P, a, G.cx0, G.cy0, G.tw, G.th, rv);
         if (reduce) tile_reduce(a, tile, rv);
     }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kWave) void k_pair_overflow(DevParams P, PairArgs a, int reduce) {
+    const int n = *a.ovf_count;
+    if (MODE == MODE_FORCES || a.rebuild == nullptr || *a.rebuild != 0)
+        overflow_tiles<MODE, true>(P, a, n, reduce);
+    else
+        overflow_tiles<MODE, false>(P, a, n, reduce);
 }
 
 // ---- binning ------------------------------------------------------------------
@@ -714,9 +870,18 @@ __global__ void k_key_rank(DevParams P, const float2* __restrict__ x, int* key, 
 constexpr int kScanPer = 8;
 constexpr int kScanTile = kBlock * kScanPer;  // cells per chunk
 
+// With a Verlet skin the binning kernels run only on rebuild steps: `rebuild`
+// (null: always) says whether this one is; k_scan_reduce also clears the flag
+// the coming pair launch will set (`moved_clear`) and counts the rebuilds.
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ count, int n,
-                                                        int* partial) {
+                                                        int* partial, const int* rebuild,
+                                                        int* moved_clear, int* rebuilds) {
     __shared__ int s_wave[kBlock / kWave];
+    if (moved_clear && blockIdx.x == 0 && threadIdx.x == 0) {
+        *moved_clear = 0;
+        if (rebuild && *rebuild) atomicAdd(rebuilds, 1);
+    }
+    if (rebuild && *rebuild == 0) return;
     const int base = blockIdx.x * kScanTile;
     int s = 0;
 #pragma unroll
@@ -733,12 +898,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ 
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_final(int* count, int n, const int* __restrict__ partial,
-                                                       int* cs, int* ovf_count) {
+                                                       int* cs, int* ovf_count, const int* rebuild) {
     __shared__ int s_v[kScanTile + kScanTile / 32];
     __shared__ int s_tsum[2 * kBlock + 1];
     __shared__ int s_wave[kBlock / kWave];
     __shared__ int s_red[kBlock / kWave];
     if (blockIdx.x == 0 && threadIdx.x == 0) *ovf_count = 0;
+    if (rebuild && *rebuild == 0) return;
     // sum of the chunks before this one
     int before = 0;
     for (int k = threadIdx.x; k < (int)blockIdx.x; k += kBlock) before += partial[k];
@@ -788,10 +954,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(int* count, int n, const 
 }
 
 __global__ void k_scatter(int N, const int* __restrict__ key, const int* __restrict__ rank,
-                          const int* __restrict__ cs, int* src) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    src[cs[key[i]] + rank[i]] = i;
+                          const int* __restrict__ cs, int* src, const int* rebuild) {
+    if (rebuild && *rebuild == 0) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+        src[cs[key[i]] + rank[i]] = i;
 }
 
 // Order each cell's slots by particle id.  Cells hold about one particle:

@@ -49,12 +49,14 @@ class Params(ctypes.Structure):
         ("sp_split", ctypes.c_int32),
         ("bin_M_max", ctypes.c_int32),
         ("tile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("skin", ctypes.c_float),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
 _INT_FIELDS = {"n_agents", "seed", "noise_kind", "rng_kind", "sp_split", "bin_M_max", "tile"}
-_DEFAULTS = dict(mass=1.0, seed=0, noise_kind=0, rng_kind=0, sp_split=0, bin_M_max=0, tile=0)
+_DEFAULTS = dict(mass=1.0, seed=0, noise_kind=0, rng_kind=0, sp_split=0, bin_M_max=0, tile=0,
+                 skin=0.0)
 
 
 def make_params(cfg: Mapping) -> Params:
@@ -96,6 +98,7 @@ def lib() -> ctypes.CDLL:
             "dpd_rng_words": (ctypes.c_int, [P, vp, vp, i64, i32, vp, vp, vp]),
             "dpd_set_profiling": (ctypes.c_int, [vp, i32]),
             "dpd_pair_kernel_time": (ctypes.c_int, [vp, ctypes.POINTER(f64), ctypes.POINTER(i64)]),
+            "dpd_cell_list_rebuilds": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
             "dpd_copy_kernel": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
         }
         for name, (res, args) in sig.items():
@@ -237,6 +240,12 @@ class Sim:
         n = ctypes.c_int64(0)
         self._c(lib().dpd_pair_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+    def rebuilds(self) -> int:
+        """Steps that rebuilt the cell list under a Verlet skin (0 without one)."""
+        n = ctypes.c_int64(0)
+        self._c(lib().dpd_cell_list_rebuilds(self._h, ctypes.byref(n)))
+        return int(n.value)
 
 
 def rng_words(cfg: Mapping, i: torch.Tensor, j: torch.Tensor, step: int):

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(dpd):
 
 
 def test_params_struct_layout_matches_header(dpd):
-    # 1 int64 + 11 doubles + 1 uint64 + 5 int32 + 3 reserved int32 = 128 bytes
+    # 1 int64 + 11 doubles + 1 uint64 + 5 int32 + 1 float + 2 reserved int32 = 128 bytes
     assert ctypes.sizeof(dpd.Params) == 8 + 11 * 8 + 8 + 8 * 4
 
 

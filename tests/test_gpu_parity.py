@@ -322,6 +322,61 @@ def test_split_steps_bitwise(dpd, between):
     sim.close()
 
 
+@pytest.mark.parametrize("skin,kind,steps,L,n_agents", [
+    (0.3, "random", 300, 40.0, 800), (0.6, "random", 300, 40.0, 800), (0.3, "edge", 200, 40.0, 800),
+    (0.35, "random", 200, 47.0, 1104),
+    # density 3 (softer repulsion, so that the random start does not tear
+    # bonds): every tile overflows the LDS capacities, on rebuild steps and
+    # between them (global-memory path with the slots of the last rebuild)
+    (0.3, "dense", 60, 23.0, 800)])
+def test_skin_trajectory_bitwise(dpd, skin, kind, steps, L, n_agents):
+    # With a Verlet skin the cells are r_c + skin wide and the steps between
+    # rebuilds test only the pairs listed at the last rebuild.  The pair set
+    # within r_c is the same and the pair sums are exact, so the trajectory is
+    # bitwise the one of the path that rebuilds every step with r_c-wide cells.
+    cfg = dict(C1, L=L, n_agents=n_agents)
+    if kind == "dense":
+        cfg["A"] = 5.0
+        kind = "random"
+    x, v = inputs.initial_state(cfg, kind=kind, thermal=True)
+    ref = make_sim(dpd, cfg, x, v)
+    sk = make_sim(dpd, dict(cfg, skin=skin), x, v)
+    half = steps // 2
+    pr = [host(ref.step(half, reduce_every=half)), host(ref.step(steps - half, reduce_every=steps - half))]
+    ps = [host(sk.step(half, reduce_every=half)), host(sk.step(steps - half, reduce_every=steps - half))]
+    a, b = ref.get_state(), sk.get_state()
+    assert a[3] == b[3] == steps
+    for k in range(3):
+        assert (host(a[k]) == host(b[k])).all(), ("x", "v", "F")[k]
+    for p, q in zip(pr, ps):  # the FP64 sums run in another order
+        assert q == pytest.approx(p, rel=1e-12, abs=1e-9)
+    nreb = sk.rebuilds()
+    print(f"skin {skin} {kind}: {nreb} rebuilds in {steps} steps")
+    assert ref.rebuilds() == 0
+    assert 2 <= nreb < steps // 2  # the lists were used
+    ref.close()
+    sk.close()
+
+
+def test_skin_forces_and_bins(dpd):
+    # the force call and the binned field with a skin, against the oracle
+    cfg = dict(C1, skin=0.4)
+    x, v = inputs.initial_state(cfg, thermal=True)
+    sim = make_sim(dpd, cfg, x, v)
+    sim.step(50)
+    xs, vs, _, step = sim.get_state()
+    xs, vs = host(xs), host(vs)
+    F = host(sim.forces())
+    per, glob = force_errors(cfg, xs, vs, step, F)
+    assert per.max() <= 1e-5 and glob <= 1e-5
+    sim.step(7)
+    xs, vs, _, _ = sim.get_state()
+    u, n = sim.bin_velocity(40, 0.0, 0)
+    uo, no = oracle.bin_velocity(cfg, host(xs), host(vs), 40, 0.0, 0)
+    assert (host(n) == no).all()
+    sim.close()
+
+
 def test_momentum_conserved_on_gpu(dpd):
     cfg = dict(C1, f_sp=0.0, gamma_s=0.0)
     x, v = inputs.initial_state(cfg, thermal=True)
