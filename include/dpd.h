@@ -133,7 +133,11 @@ int dpd_forces(dpd_handle* h, float* F_out);
  * every step.  If reduce_every > 0 and pk_out != NULL, after every
  * reduce_every-th step the FP64 totals (P_x, P_y, KE) = (sum m v_x, sum m v_y,
  * sum m |v|^2 / 2) are written to device pk_out[3 r .. 3 r + 2], r = 0, 1, ...
- * (pk_out holds 3 * floor(n_steps / reduce_every) doubles).  Asynchronous.
+ * (pk_out holds 3 * floor(n_steps / reduce_every) doubles; for a batch, record
+ * r holds the totals of every replica q at pk_out[3 (r R + q) ..]).  With a
+ * graph chunk set (dpd_set_graph_chunk) whole chunks are replayed from captured
+ * graphs when reduce_every is 0 or a multiple of the chunk; the results are
+ * bitwise those of the launches one by one.  Asynchronous.
  * Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP. */
 int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_out);
 
@@ -148,8 +152,10 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
  * the mean velocity (0 where nothing contributes); n_out: device M*M int32
  * contributor counts.  Sums are exact in 64-bit fixed point (scale 2^S with
  * S = min(32, 46 - ceil(log2(contributors + 1))), |v| <= 2^16), so the result
- * is independent of the order of contributions.  Asynchronous; a velocity
- * beyond 2^16 is reported by the next synchronising call as DPD_ERANGE.
+ * is independent of the order of contributions.  For a batch, replica q's
+ * field follows at u_out + 2 q M M and n_out + q M M (each on its own box).
+ * Asynchronous; a velocity beyond 2^16 is reported by the next synchronising
+ * call as DPD_ERANGE.
  * Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP. */
 int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode,
                      float* u_out, int32_t* n_out);
@@ -157,6 +163,48 @@ int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode,
 /* Wait for the stream and return the first device-side failure since the last
  * synchronising call (clearing it), or DPD_OK. */
 int dpd_sync(dpd_handle* h);
+
+/* ---- batches of replicas, captured step chunks, tile schedules ------------- */
+
+/* A batch of n_rep independent systems, e.g. the points of a parameter sweep
+ * over area fraction and the two friction coefficients (Sec. 5, Sec. 5.1):
+ * p[0 .. n_rep-1] are their parameters (any sizes, boxes and constants; skin
+ * must be 0), each system keeping its own ids 0 .. N_q - 1 and its own noise
+ * key.  The batch's per-step kernels cover every replica in one launch each;
+ * each replica's
+ * trajectory is bitwise the one of a handle made for it alone.  All state
+ * arrays of the entry points above are the replicas' arrays concatenated in
+ * replica order (replica q's N_q x 2 block follows replica q - 1's);
+ * dpd_get_cells returns the concatenated cell lists (replica q's cells follow
+ * replica q - 1's, slots counted over the batch).  A handle made by dpd_create
+ * is a batch of one.  Errors as dpd_workspace_bytes / dpd_create. */
+int dpd_batch_workspace_bytes(const dpd_params* p, int32_t n_rep, size_t* bytes);
+int dpd_create_batch(const dpd_params* p, int32_t n_rep, void* workspace, size_t bytes,
+                     void* stream, dpd_handle** out);
+
+/* Replay dpd_step in chunks of `steps` (even, <= 4096; 0: off) launches
+ * captured once into a HIP graph (on a stream of the handle's own; replayed on
+ * the handle's stream), which removes the host's per-launch cost.  Not used
+ * with a Verlet skin or while profiling.  Errors: DPD_EINVAL. */
+int dpd_set_graph_chunk(dpd_handle* h, int32_t steps);
+
+/* Pair-kernel schedule: tiles of tile_x x tile_y cells (1..8, clamped per
+ * replica to n_c - 2; the workspace holds the tiles of any sides >= 4, or of
+ * the sides the handle was made with if smaller) and the tile order (0: each
+ * of the 8 XCDs takes a band of consecutive tiles; 1: launch order).  The
+ * results do not depend on the schedule.  Not with a Verlet skin.
+ * Errors: DPD_EINVAL. */
+int dpd_set_schedule(dpd_handle* h, int32_t tile_x, int32_t tile_y, int32_t tile_order);
+int dpd_get_schedule(dpd_handle* h, int32_t* tile_x, int32_t* tile_y, int32_t* tile_order);
+
+/* Time trial_steps steps of the current state under each candidate schedule
+ * (tile sides from 8 x 7 down to 4 x 4, both tile orders), keep the fastest
+ * and restore the state exactly as it was (state, step, no prepared step).
+ * Outputs (host, any may be NULL): the chosen schedule and its time per step
+ * in ms.  Synchronises the stream.  Not with a Verlet skin.
+ * Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP, device flags. */
+int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* tile_y,
+                 int32_t* tile_order, double* best_ms);
 
 /* ---- diagnostics used by tests and the benchmark --------------------------- */
 

@@ -52,6 +52,10 @@ struct DevParams {
     double dt_d;      // time step (FP64)
     double inv_w;     // nc / L (FP64): cell = floor(x * inv_w)
     uint32_t seed_lo, seed_hi;
+    // a replica of a batch: its first particle slot, cell and tile in the
+    // concatenated arrays of the batch (all 0 for a single system), its mass
+    int pbase, cbase, tbase;
+    double mass_d;
 };
 
 // ---- Philox (Salmon, Moraes, Dror & Shaw, SC'11) ---------------------------

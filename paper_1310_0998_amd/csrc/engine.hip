@@ -1,5 +1,11 @@
 // engine.hip -- host side of the DPD engine: parameter checks, workspace
 // layout, launch sequences and the C ABI declared in include/dpd.h.
+//
+// A handle holds one system or a batch of independent replicas.  The replicas'
+// particles, cells and tiles are concatenated (replica r owns a contiguous
+// range of each), so the per-step kernels (cell-count scan, scatter, pair
+// kernel) cover the whole batch in one launch each.  A single system is the
+// one-replica case and uses the kernels that take its parameters by value.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,20 +32,32 @@ struct Layout {
     size_t off_key, off_rank, off_src, off_count, off_cs;
     size_t off_scan_part, off_red, off_Fs, off_binacc, off_status, off_ovf;
     size_t off_count2, off_xref, off_rec, off_flags;  // Verlet skin
+    size_t off_reps, off_tile_rep, off_stepb;         // batch tables, graph step
+    size_t off_Tx, off_Tv, off_TF, off_Tid;           // state saved by the tuner
     size_t total;
 };
 
-struct Derived {
+// One replica: its parameters and derived launch constants.
+struct Rep {
+    dpd_params p;
     DevParams P;
-    int n_tiles;
-    int n_scan_blocks;  // chunks of the cell-count scan
-    int bin_M_max;
+};
+
+// The whole handle: replicas, totals and the workspace layout.
+struct Derived {
+    std::vector<Rep> reps;
+    long long N = 0, cells = 0, tiles = 0;
+    long long tiles_alloc = 0;  // capacity of the per-tile arrays
+    int n_scan_blocks = 0;      // chunks of the cell-count scan
+    int bin_M_max = 0;
+    bool skin = false;
     Layout lay;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr uint64_t kProfEvery = 8;  // pair launches per profiled launch
+constexpr int kTuneMinTile = 4;     // smallest tile side the tuner tries
 
 std::string fmt(const char* f, ...) {
     char buf[512];
@@ -50,8 +68,29 @@ std::string fmt(const char* f, ...) {
     return buf;
 }
 
-// Validate parameters and derive the launch constants and workspace layout.
-int derive(const dpd_params* p, Derived* d, std::string* err) {
+// Tile tx x ty cells (clamped so that a tile and its halo do not wrap onto
+// themselves: side <= n_c - 2) and the constants the pair kernel derives from it.
+void set_tiling(DevParams& P, int tx, int ty) {
+    P.tile_x = std::max(1, std::min(tx, P.nc - 2));
+    P.tile_y = std::max(1, std::min(ty, P.nc - 2));
+    P.ntx = (P.nc + P.tile_x - 1) / P.tile_x;
+    P.nty = (P.nc + P.tile_y - 1) / P.tile_y;
+    const int w_full = P.tile_x + 2, w_last = (P.nc - (P.ntx - 1) * P.tile_x) + 2;
+    P.wmul_full = (65536 + w_full - 1) / w_full;
+    P.wmul_last = (65536 + w_last - 1) / w_last;
+    // (tile + 1/2) / ntx lies at least 1/(2 ntx) >= 2^-17 from an integer, far
+    // beyond the 2^-21 error of the product for tile < 2^31
+    P.inv_ntx = 1.0 / (double)P.ntx;
+}
+
+long long tiles_of(const DevParams& P, int tx, int ty) {
+    DevParams Q = P;
+    set_tiling(Q, tx, ty);
+    return (long long)Q.ntx * Q.nty;
+}
+
+// Validate the parameters of one system and derive its launch constants.
+int derive_one(const dpd_params* p, DevParams& P, std::string* err) {
     if (!p) { *err = "params is NULL"; return DPD_EINVAL; }
     if (p->n_agents < 1 || p->n_agents > (int64_t(1) << 29)) {
         *err = fmt("n_agents = %lld outside [1, 2^29]", (long long)p->n_agents);
@@ -91,12 +130,11 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     if (p->bin_M_max < 0 || p->bin_M_max > 8192) { *err = "bin_M_max must be in [0, 8192]"; return DPD_EINVAL; }
     if (p->tile < 0 || p->tile > kTileMax) { *err = fmt("tile must be in [0, %d]", kTileMax); return DPD_EINVAL; }
 
-    DevParams& P = d->P;
+    P = DevParams{};
     P.N = (int)(2 * p->n_agents);
     P.nc = (int)ncd;
     P.n_cells = P.nc * P.nc;
-    // tile + halo must not wrap onto itself: tile side <= n_c - 2.  With a skin
-    // the cells are wider; the default tile keeps about 56 particles.
+    // the default tile holds about 56 particles; with a skin the cells are wider
     int tx = kTileX, ty = kTileY;
     if (p->skin > 0.0f) {
         const double cell_n = (2.0 * (double)p->n_agents) / ((double)ncd * ncd);  // particles per cell
@@ -104,18 +142,7 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
         tx = std::max(1, std::min(kTileMax, (int)std::lround(kTileX / sc)));
         ty = std::max(1, std::min(kTileMax, (int)std::lround(kTileY / sc)));
     }
-    P.tile_x = std::min(p->tile ? p->tile : tx, P.nc - 2);
-    P.tile_y = std::min(p->tile ? p->tile : ty, P.nc - 2);
-    P.ntx = (P.nc + P.tile_x - 1) / P.tile_x;
-    P.nty = (P.nc + P.tile_y - 1) / P.tile_y;
-    {
-        const int w_full = P.tile_x + 2, w_last = (P.nc - (P.ntx - 1) * P.tile_x) + 2;
-        P.wmul_full = (65536 + w_full - 1) / w_full;
-        P.wmul_last = (65536 + w_last - 1) / w_last;
-        // (tile + 1/2) / ntx lies at least 1/(2 ntx) >= 2^-17 from an integer, far
-        // beyond the 2^-21 error of the product for tile < 2^31
-        P.inv_ntx = 1.0 / (double)P.ntx;
-    }
+    set_tiling(P, p->tile ? p->tile : tx, p->tile ? p->tile : ty);
     P.noise_kind = p->noise_kind;
     P.rng_kind = p->rng_kind;
     P.L = (float)p->L;
@@ -151,12 +178,63 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     }
     P.seed_lo = (uint32_t)(p->seed & 0xffffffffu);
     P.seed_hi = (uint32_t)(p->seed >> 32);
+    P.mass_d = p->mass;
+    return DPD_OK;
+}
 
-    d->n_tiles = P.ntx * P.nty;
-    d->n_scan_blocks = (P.n_cells + kScanTile - 1) / kScanTile;
-    d->bin_M_max = p->bin_M_max ? p->bin_M_max : 256;
+// Offsets of every replica in the concatenated particle, cell and tile arrays.
+void assign_offsets(Derived* d) {
+    long long pb = 0, cb = 0, tb = 0;
+    for (Rep& r : d->reps) {
+        r.P.pbase = (int)pb;
+        r.P.cbase = (int)cb;
+        r.P.tbase = (int)tb;
+        pb += r.P.N;
+        cb += r.P.n_cells;
+        tb += (long long)r.P.ntx * r.P.nty;
+    }
+    d->N = pb;
+    d->cells = cb;
+    d->tiles = tb;
+}
 
-    const size_t N = (size_t)P.N;
+// Validate n_rep parameter sets and lay out the workspace for them.
+int derive(const dpd_params* p, int n_rep, Derived* d, std::string* err) {
+    if (!p) { *err = "params is NULL"; return DPD_EINVAL; }
+    if (n_rep < 1 || n_rep > 65536) { *err = fmt("n_rep = %d outside [1, 65536]", n_rep); return DPD_EINVAL; }
+    d->reps.assign(n_rep, Rep{});
+    int bin_M_max = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        std::string e;
+        int rc = derive_one(p + r, d->reps[r].P, &e);
+        if (rc) {
+            *err = n_rep > 1 ? fmt("replica %d: %s", r, e.c_str()) : e;
+            return rc;
+        }
+        d->reps[r].p = p[r];
+        bin_M_max = std::max(bin_M_max, p[r].bin_M_max ? p[r].bin_M_max : 256);
+        if (n_rep > 1 && p[r].skin > 0.0f) {
+            *err = "a batch of replicas runs without a Verlet skin (skin must be 0)";
+            return DPD_EINVAL;
+        }
+    }
+    d->skin = d->reps[0].P.skin_on != 0;
+    assign_offsets(d);
+    if (d->N > (int64_t(1) << 30) || d->cells > 2147483647LL) {
+        *err = "the batch holds more than 2^30 particles or 2^31 cells";
+        return DPD_EINVAL;
+    }
+    // the per-tile arrays hold the tiles of any schedule the tuner may choose
+    long long ta = 0;
+    for (const Rep& r : d->reps)
+        ta += std::max((long long)r.P.ntx * r.P.nty,
+                       tiles_of(r.P, std::min(r.P.tile_x, kTuneMinTile), std::min(r.P.tile_y, kTuneMinTile)));
+    if (d->skin) ta = d->tiles;  // the skin keeps the tiling it was created with
+    d->tiles_alloc = ta;
+    d->n_scan_blocks = (int)((d->cells + kScanTile - 1) / kScanTile);
+    d->bin_M_max = bin_M_max;
+
+    const size_t N = (size_t)d->N, C = (size_t)d->cells, T = (size_t)d->tiles_alloc;
     Layout& L = d->lay;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -173,21 +251,29 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
     L.off_key = take(N * 4);
     L.off_rank = take(N * 4);
     L.off_src = take(N * 4);
-    L.off_count = take((size_t)P.n_cells * 4);
-    L.off_cs = take(((size_t)P.n_cells + 1) * 4);
-    L.off_red = take(((size_t)d->n_tiles + kRedParts) * 3 * 8);  // per tile, then per part
+    L.off_count = take(C * 4);
+    L.off_cs = take((C + 1) * 4);
+    L.off_red = take((T + kRedParts) * 3 * 8);  // per tile, then per part
     L.off_Fs = take(N * 8);
     L.off_binacc = take((size_t)d->bin_M_max * d->bin_M_max * 3 * 8);
     L.off_status = take(16);
-    L.off_ovf = take(((size_t)d->n_tiles + 1) * 4);
+    L.off_ovf = take((T + 1) * 4);
     L.off_scan_part = take((size_t)d->n_scan_blocks * 4);
-    L.off_flags = take(64);  // two displacement flags (by step parity)
-    if (P.skin_on) {
-        L.off_count2 = take((size_t)P.n_cells * 4);
+    L.off_flags = take(64);  // two displacement flags (by step parity), rebuild count
+    L.off_stepb = take(64);
+    L.off_reps = take((size_t)n_rep * sizeof(DevParams));
+    L.off_tile_rep = take(n_rep > 1 ? T * 4 : 4);
+    if (d->skin) {
+        L.off_count2 = take(C * 4);
         L.off_xref = take(N * 8);
-        L.off_rec = take((size_t)d->n_tiles * kRecStride);
+        L.off_rec = take(T * kRecStride);
+        L.off_Tx = L.off_Tv = L.off_TF = L.off_Tid = 0;
     } else {
         L.off_count2 = L.off_xref = L.off_rec = 0;
+        L.off_Tx = take(N * 8);
+        L.off_Tv = take(N * 8);
+        L.off_TF = take(N * 8);
+        L.off_Tid = take(N * 4);
     }
     L.total = o;
     return DPD_OK;
@@ -195,15 +281,24 @@ int derive(const dpd_params* p, Derived* d, std::string* err) {
 
 inline int grid_for(long long n, int block = kBlock) { return (int)((n + block - 1) / block); }
 
+// A captured chunk of steps, replayed by dpd_step.
+struct Graph {
+    int K;
+    bool reduce_last;
+    hipGraphExec_t exec;
+};
+
 }  // namespace
 
 struct dpd_handle {
-    dpd_params p;
     Derived d;
+    int R;  // replicas
     hipStream_t stream;
     char* ws;
     float2 *Sx, *Sv, *SF, *Ax, *Au, *Bx, *Bu, *Fs;
     int *Sid, *Aid, *Bid, *key, *rank, *src, *count, *cs;
+    float2 *Tx, *Tv, *TF;
+    int* Tid;
     unsigned* status;
     int* ovf;  // [0]: count of tiles left to the overflow kernel, then their indices
     int* scan_part;
@@ -214,6 +309,10 @@ struct dpd_handle {
     int* flags;
     double* red;
     long long* binacc;
+    DevParams* reps_dev;  // parameters of every replica (batch)
+    int* tile_rep;        // replica of every tile (batch)
+    unsigned* stepb;      // step before a replayed chunk
+    int tile_order;       // 0: bands of tiles per XCD; 1: launch order
     int64_t step;
     bool have_state;
     // the last dpd_step also made the next step's half kick and drift (and its
@@ -228,6 +327,10 @@ struct dpd_handle {
     double prof_ms;
     int64_t prof_n;
     uint64_t prof_seq;
+    // steps replayed from captured graphs, in chunks of graph_chunk steps
+    int graph_chunk;
+    hipStream_t cap_stream;
+    std::vector<Graph> graphs;
 };
 
 namespace {
@@ -252,6 +355,33 @@ int fail(dpd_handle* h, int code, const std::string& msg) {
             return fail((h), DPD_EHIP, fmt("kernel launch: %s", hipGetErrorString(e_)));  \
     } while (0)
 
+const DevParams& P0(const dpd_handle* h) { return h->d.reps[0].P; }
+
+void drop_graphs(dpd_handle* h) {
+    if (h->graphs.empty()) return;
+    (void)hipStreamSynchronize(h->stream);  // no replay may still be in flight
+    for (Graph& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+}
+
+// Upload the replica table and the tile -> replica map (batches only).
+int upload_tables(dpd_handle* h) {
+    if (h->R == 1) return DPD_OK;
+    std::vector<DevParams> P(h->R);
+    std::vector<int> tr((size_t)h->d.tiles);
+    for (int r = 0; r < h->R; ++r) {
+        P[r] = h->d.reps[r].P;
+        const long long t0 = P[r].tbase, nt = (long long)P[r].ntx * P[r].nty;
+        for (long long t = 0; t < nt; ++t) tr[(size_t)(t0 + t)] = r;
+    }
+    HIPCHK(h, hipMemcpyAsync(h->reps_dev, P.data(), P.size() * sizeof(DevParams),
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->tile_rep, tr.data(), tr.size() * 4, hipMemcpyHostToDevice,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));  // the host vectors go out of scope
+    return DPD_OK;
+}
+
 // cell_start from count (count cleared) and the slot -> input map.  Within a
 // cell the slots are in arrival order; the pair kernel places each cell's
 // members by id itself.  With id_of_input != NULL every cell is also ordered by
@@ -259,18 +389,18 @@ int fail(dpd_handle* h, int code, const std::string& msg) {
 // passes through before it is stored).
 int bin_from_counts(dpd_handle* h, int* count, const int* rebuild, int* moved_clear,
                     const int* id_of_input) {
-    const DevParams& P = h->d.P;
     const int G = h->d.n_scan_blocks;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(G), dim3(kBlock), 0, h->stream, (const int*)count,
-                       P.n_cells, h->scan_part, rebuild, moved_clear, h->flags + 2);
-    hipLaunchKernelGGL(k_scan_final, dim3(G), dim3(kBlock), 0, h->stream, count, P.n_cells,
+    const int C = (int)h->d.cells, N = (int)h->d.N;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(G), dim3(kBlock), 0, h->stream, (const int*)count, C,
+                       h->scan_part, rebuild, moved_clear, h->flags + 2);
+    hipLaunchKernelGGL(k_scan_final, dim3(G), dim3(kBlock), 0, h->stream, count, C,
                        (const int*)h->scan_part, h->cs, h->ovf, rebuild);
-    hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(P.N), 4096)), dim3(kBlock), 0, h->stream,
-                       P.N, (const int*)h->key, (const int*)h->rank, (const int*)h->cs, h->src,
+    hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(N), 4096)), dim3(kBlock), 0, h->stream,
+                       N, (const int*)h->key, (const int*)h->rank, (const int*)h->cs, h->src,
                        rebuild);
     if (id_of_input)
-        hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(P.n_cells)), dim3(kBlock), 0, h->stream,
-                           P.n_cells, (const int*)h->cs, h->src, id_of_input);
+        hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, C,
+                           (const int*)h->cs, h->src, id_of_input);
     LAUNCHCHK(h);
     return DPD_OK;
 }
@@ -282,9 +412,22 @@ int* counter_of(dpd_handle* h, int64_t s) {
     return (h->count2 && (s & 1)) ? h->count2 : h->count;
 }
 
+template <int MODE, bool SKIN, bool BATCH>
+void launch_pair_kernel(dpd_handle* h, const PairArgs& b, int reduce) {
+    const int G = (int)h->d.tiles;
+    hipLaunchKernelGGL((k_pair<MODE, SKIN, BATCH>), dim3(G), dim3(kWave), 0, h->stream, P0(h), b,
+                       reduce);
+}
+
+template <int MODE, bool BATCH>
+void launch_overflow(dpd_handle* h, const PairArgs& b, int reduce) {
+    // tiles over an LDS capacity (dense clusters), if any
+    const int Go = (int)std::min<long long>(h->d.tiles, 64);
+    hipLaunchKernelGGL((k_pair_overflow<MODE, BATCH>), dim3(Go), dim3(kWave), 0, h->stream, P0(h),
+                       b, reduce);
+}
+
 int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
-    const DevParams& P = h->d.P;
-    const int G = h->d.n_tiles;
     size_t ev = 0;
     // with profiling on, every kProfEvery-th launch is bracketed by events (an
     // event record between two kernels costs a few microseconds of GPU time)
@@ -303,19 +446,30 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
     PairArgs b = a;
     b.ovf_count = h->ovf;
     b.ovf_list = h->ovf + 1;
+    b.reps = h->reps_dev;
+    b.tile_rep = h->tile_rep;
+    b.nt_total = (int)h->d.tiles;
+    b.tile_order = h->tile_order;
+    const int red = reduce ? 1 : 0;
+    const bool batch = h->R > 1;
     // the Verlet-skin variant of the kernel only where a skin is set (a force
     // evaluation alone keeps no record)
-    const bool skin = P.skin_on && mode != MODE_FORCES;
-    if (mode == MODE_STEP && skin)
-        hipLaunchKernelGGL((k_pair<MODE_STEP, true>), dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
-    else if (mode == MODE_STEP)
-        hipLaunchKernelGGL((k_pair<MODE_STEP, false>), dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
-    else if (mode == MODE_FINAL && skin)
-        hipLaunchKernelGGL((k_pair<MODE_FINAL, true>), dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
-    else if (mode == MODE_FINAL)
-        hipLaunchKernelGGL((k_pair<MODE_FINAL, false>), dim3(G), dim3(kWave), 0, h->stream, P, b, (int)reduce);
-    else
-        hipLaunchKernelGGL((k_pair<MODE_FORCES, false>), dim3(G), dim3(kWave), 0, h->stream, P, b, 0);
+    const bool skin = h->d.skin && mode != MODE_FORCES;
+    if (batch) {
+        if (mode == MODE_STEP) launch_pair_kernel<MODE_STEP, false, true>(h, b, red);
+        else if (mode == MODE_FINAL) launch_pair_kernel<MODE_FINAL, false, true>(h, b, red);
+        else launch_pair_kernel<MODE_FORCES, false, true>(h, b, 0);
+    } else if (mode == MODE_STEP && skin) {
+        launch_pair_kernel<MODE_STEP, true, false>(h, b, red);
+    } else if (mode == MODE_STEP) {
+        launch_pair_kernel<MODE_STEP, false, false>(h, b, red);
+    } else if (mode == MODE_FINAL && skin) {
+        launch_pair_kernel<MODE_FINAL, true, false>(h, b, red);
+    } else if (mode == MODE_FINAL) {
+        launch_pair_kernel<MODE_FINAL, false, false>(h, b, red);
+    } else {
+        launch_pair_kernel<MODE_FORCES, false, false>(h, b, 0);
+    }
     LAUNCHCHK(h);
     if (timed) {
         HIPCHK(h, hipEventRecord(h->ev_stop[ev], h->stream));
@@ -330,14 +484,33 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
             h->ev_used = 0;
         }
     }
-    // tiles over an LDS capacity (dense clusters), if any
-    const int Go = std::min(G, 64);
-    if (mode == MODE_STEP)
-        hipLaunchKernelGGL(k_pair_overflow<MODE_STEP>, dim3(Go), dim3(kWave), 0, h->stream, P, b, (int)reduce);
-    else if (mode == MODE_FINAL)
-        hipLaunchKernelGGL(k_pair_overflow<MODE_FINAL>, dim3(Go), dim3(kWave), 0, h->stream, P, b, (int)reduce);
-    else
-        hipLaunchKernelGGL(k_pair_overflow<MODE_FORCES>, dim3(Go), dim3(kWave), 0, h->stream, P, b, 0);
+    if (batch) {
+        if (mode == MODE_STEP) launch_overflow<MODE_STEP, true>(h, b, red);
+        else if (mode == MODE_FINAL) launch_overflow<MODE_FINAL, true>(h, b, red);
+        else launch_overflow<MODE_FORCES, true>(h, b, 0);
+    } else {
+        if (mode == MODE_STEP) launch_overflow<MODE_STEP, false>(h, b, red);
+        else if (mode == MODE_FINAL) launch_overflow<MODE_FINAL, false>(h, b, red);
+        else launch_overflow<MODE_FORCES, false>(h, b, 0);
+    }
+    LAUNCHCHK(h);
+    return DPD_OK;
+}
+
+// FP64 (P_x, P_y, KE) of every replica from the per-tile partials of the last
+// pair launch, into out[3 r .. 3 r + 2].
+int launch_reduce(dpd_handle* h, double* out) {
+    if (h->R == 1) {
+        const int parts = (int)std::min<long long>(kRedParts, h->d.tiles);
+        double* part = h->red + 3 * (size_t)h->d.tiles_alloc;
+        hipLaunchKernelGGL(k_reduce_part, dim3(parts), dim3(kBlock), 0, h->stream,
+                           (const double*)h->red, (int)h->d.tiles, part);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, h->stream, (const double*)part,
+                           parts, h->d.reps[0].p.mass, out);
+    } else {
+        hipLaunchKernelGGL(k_reduce_reps, dim3(h->R), dim3(kBlock), 0, h->stream,
+                           (const double*)h->red, (const DevParams*)h->reps_dev, out);
+    }
     LAUNCHCHK(h);
     return DPD_OK;
 }
@@ -365,25 +538,201 @@ int read_status(dpd_handle* h) {
 // binning starts from zero).
 int unprepare(dpd_handle* h) {
     if (!h->prepared) return DPD_OK;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(h->d.P.n_cells)), dim3(kBlock), 0, h->stream,
-                       h->count, 0, (long long)h->d.P.n_cells);
+    const long long C = h->d.cells;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, h->count, 0, C);
     if (h->count2)
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(h->d.P.n_cells)), dim3(kBlock), 0, h->stream,
-                           h->count2, 0, (long long)h->d.P.n_cells);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, h->count2, 0, C);
     LAUNCHCHK(h);
     h->prepared = false;
     return DPD_OK;
+}
+
+// First half kick and drift of a dpd_step call from the stored state, into the
+// A buffers (with a skin this step rebuilds).
+int kick_drift(dpd_handle* h) {
+    int* count = counter_of(h, h->step);
+    for (const Rep& r : h->d.reps) {
+        const DevParams& P = r.P;
+        const size_t pb = (size_t)P.pbase;
+        hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
+                           (const float2*)(h->Sx + pb), (const float2*)(h->Sv + pb),
+                           (const float2*)(h->SF + pb), (const int*)(h->Sid + pb), h->Ax + pb,
+                           h->Au + pb, h->Aid + pb, h->key + pb, h->rank + pb, count, h->status);
+    }
+    if (h->d.skin)
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, h->flags + (h->step & 1),
+                           1, 1LL);
+    LAUNCHCHK(h);
+    h->prepared = true;
+    h->prep_x = h->Ax;
+    h->prep_u = h->Au;
+    h->prep_id = h->Aid;
+    return DPD_OK;
+}
+
+// The arguments of the pair launch of step s = h->step + k of a run that
+// starts from the prepared buffers (in, out alternate; the last step stores
+// the state and prepares the next one).
+PairArgs step_args(dpd_handle* h, int64_t k, bool last, float2* inx, float2* inu, int* inid,
+                   float2* outx, float2* outu, int* outid) {
+    const int64_t s = h->step + k;
+    PairArgs a = {};
+    a.cs = h->cs;
+    a.src = h->src;
+    a.xin = inx;
+    a.uin = inu;
+    a.idin = inid;
+    a.status = h->status;
+    a.red = h->red;
+    a.step = (uint32_t)((uint64_t)s & 0xffffffffu);
+    a.keyout = h->key;
+    a.rankout = h->rank;
+    a.count = counter_of(h, s);
+    if (h->d.skin) {
+        a.rebuild = h->flags + ((s - 1) & 1);
+        a.rec = h->rec;
+        a.xref = h->xref;
+        a.moved = h->flags + (s & 1);
+        a.count_clear = counter_of(h, s - 1);
+    }
+    if (last) {
+        a.xout = h->Sx;
+        a.uout = h->Sv;
+        a.idout = h->Sid;
+        a.Fout = h->SF;
+        a.pxout = outx;
+        a.puout = outu;
+        a.pidout = outid;
+    } else {
+        a.xout = outx;
+        a.uout = outu;
+        a.idout = outid;
+    }
+    return a;
+}
+
+// n >= 1 steps from the prepared buffers, launched one by one.  Records of
+// (P_x, P_y, KE) per replica are taken at the steps k0 + k that are multiples
+// of reduce_every, into pk_out + 3 R *rec.
+int run_steps(dpd_handle* h, int64_t n, int reduce_every, double* pk_out, int64_t k0, int64_t* rec) {
+    float2 *inx = h->prep_x, *inu = h->prep_u;
+    int* inid = h->prep_id;
+    const bool in_a = (inx == h->Ax);
+    float2* outx = in_a ? h->Bx : h->Ax;
+    float2* outu = in_a ? h->Bu : h->Au;
+    int* outid = in_a ? h->Bid : h->Aid;
+    for (int64_t k = 1; k <= n; ++k) {
+        // forces of step s = step + k: the binning consumes the keys of x_s
+        // (counters of step s - 1) if this step rebuilds
+        const int64_t s = h->step + k;
+        const int* rebuild = h->d.skin ? h->flags + ((s - 1) & 1) : nullptr;
+        int* moved = h->d.skin ? h->flags + (s & 1) : nullptr;
+        int rc = bin_from_counts(h, counter_of(h, s - 1), rebuild, moved, nullptr);
+        if (rc) return rc;
+        const bool last = (k == n);
+        const bool red = pk_out && reduce_every > 0 && ((k0 + k) % reduce_every == 0);
+        const PairArgs a = step_args(h, k, last, inx, inu, inid, outx, outu, outid);
+        rc = launch_pair(h, last ? MODE_FINAL : MODE_STEP, a, red);
+        if (rc) return rc;
+        if (red) {
+            rc = launch_reduce(h, pk_out + 3 * (size_t)h->R * (size_t)(*rec));
+            if (rc) return rc;
+            ++*rec;
+        }
+        std::swap(inx, outx);
+        std::swap(inu, outu);
+        std::swap(inid, outid);
+    }
+    // the last launch left the next step's start in what is now `in`
+    h->prep_x = inx;
+    h->prep_u = inu;
+    h->prep_id = inid;
+    h->step += n;
+    return DPD_OK;
+}
+
+// Capture K steps (K even, prepared buffers in A, step numbers read from
+// *stepb) into a graph; with reduce_last the last pair launch also writes the
+// per-tile partials of the FP64 sums.  The chunk ends with the next step
+// prepared in A again and *stepb advanced by K.
+int capture_chunk(dpd_handle* h, int K, bool reduce_last, hipGraphExec_t* out) {
+    if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = h->stream;
+    h->stream = h->cap_stream;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        h->stream = user;
+        return fail(h, DPD_EHIP, fmt("hipStreamBeginCapture: %s", hipGetErrorString(e)));
+    }
+    int rc = DPD_OK;
+    float2 *inx = h->Ax, *inu = h->Au, *outx = h->Bx, *outu = h->Bu;
+    int *inid = h->Aid, *outid = h->Bid;
+    for (int k = 1; k <= K && rc == DPD_OK; ++k) {
+        rc = bin_from_counts(h, h->count, nullptr, nullptr, nullptr);
+        if (rc) break;
+        const bool last = (k == K);
+        PairArgs a = step_args(h, k, last, inx, inu, inid, outx, outu, outid);
+        a.step = (uint32_t)k;
+        a.step_base = h->stepb;
+        rc = launch_pair(h, last ? MODE_FINAL : MODE_STEP, a, last && reduce_last);
+        std::swap(inx, outx);
+        std::swap(inu, outu);
+        std::swap(inid, outid);
+    }
+    if (rc == DPD_OK) {
+        hipLaunchKernelGGL(k_add_u32, dim3(1), dim3(64), 0, h->cap_stream, h->stepb, (unsigned)K);
+        e = hipGetLastError();
+        if (e != hipSuccess) rc = fail(h, DPD_EHIP, fmt("kernel launch: %s", hipGetErrorString(e)));
+    }
+    e = hipStreamEndCapture(h->cap_stream, &graph);
+    h->stream = user;
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(h, DPD_EHIP, fmt("hipStreamEndCapture: %s", hipGetErrorString(e)));
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(h, DPD_EHIP, fmt("hipGraphInstantiate: %s", hipGetErrorString(e)));
+    return DPD_OK;
+}
+
+// Copy the stored state (S) to the tuner's save area, or back.
+int copy_state(dpd_handle* h, bool save) {
+    const size_t N = (size_t)h->d.N;
+    void* S[4] = {h->Sx, h->Sv, h->SF, h->Sid};
+    void* T[4] = {h->Tx, h->Tv, h->TF, h->Tid};
+    const size_t bytes[4] = {N * 8, N * 8, N * 8, N * 4};
+    for (int k = 0; k < 4; ++k)
+        HIPCHK(h, hipMemcpyAsync(save ? T[k] : S[k], save ? S[k] : T[k], bytes[k],
+                                 hipMemcpyDeviceToDevice, h->stream));
+    return DPD_OK;
+}
+
+// Apply a tile schedule to every replica (tile sides clamped per replica).
+int apply_schedule(dpd_handle* h, int tx, int ty, int order) {
+    Derived nd = h->d;
+    for (Rep& r : nd.reps) set_tiling(r.P, tx, ty);
+    assign_offsets(&nd);
+    if (nd.tiles > h->d.tiles_alloc)
+        return fail(h, DPD_EINVAL, fmt("tile %d x %d needs %lld tiles, the workspace holds %lld", tx,
+                                       ty, nd.tiles, h->d.tiles_alloc));
+    drop_graphs(h);
+    h->d = nd;
+    h->tile_order = order;
+    return upload_tables(h);
 }
 
 }  // namespace
 
 extern "C" {
 
-int dpd_workspace_bytes(const dpd_params* p, size_t* bytes) {
+int dpd_batch_workspace_bytes(const dpd_params* p, int32_t n_rep, size_t* bytes) {
     try {
         Derived d;
         std::string err;
-        int rc = derive(p, &d, &err);
+        int rc = derive(p, n_rep, &d, &err);
         if (rc) return fail(nullptr, rc, err);
         if (!bytes) return fail(nullptr, DPD_EINVAL, "bytes is NULL");
         *bytes = d.lay.total;
@@ -393,22 +742,26 @@ int dpd_workspace_bytes(const dpd_params* p, size_t* bytes) {
     }
 }
 
-int64_t dpd_cells_per_side(const dpd_params* p) {
-    Derived d;
-    std::string err;
-    int rc = derive(p, &d, &err);
-    if (rc) return fail(nullptr, rc, err);
-    return d.P.nc;
+int dpd_workspace_bytes(const dpd_params* p, size_t* bytes) {
+    return dpd_batch_workspace_bytes(p, 1, bytes);
 }
 
-int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
-               dpd_handle** out) {
+int64_t dpd_cells_per_side(const dpd_params* p) {
+    DevParams P;
+    std::string err;
+    int rc = derive_one(p, P, &err);
+    if (rc) return fail(nullptr, rc, err);
+    return P.nc;
+}
+
+int dpd_create_batch(const dpd_params* p, int32_t n_rep, void* workspace, size_t bytes,
+                     void* stream, dpd_handle** out) {
     try {
         if (!out) return fail(nullptr, DPD_EINVAL, "out is NULL");
         *out = nullptr;
         Derived d;
         std::string err;
-        int rc = derive(p, &d, &err);
+        int rc = derive(p, n_rep, &d, &err);
         if (rc) return fail(nullptr, rc, err);
         if (!workspace || ((uintptr_t)workspace & 255u))
             return fail(nullptr, DPD_EWORKSPACE, "workspace is NULL or not 256-byte aligned");
@@ -417,8 +770,8 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
                         fmt("workspace has %zu bytes, needs %zu", bytes, d.lay.total));
         dpd_handle* h = new (std::nothrow) dpd_handle();
         if (!h) return fail(nullptr, DPD_EINVAL, "out of host memory");
-        h->p = *p;
         h->d = d;
+        h->R = n_rep;
         h->stream = (hipStream_t)stream;
         h->ws = (char*)workspace;
         const Layout& L = d.lay;
@@ -445,9 +798,17 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
         h->ovf = (int*)(w + L.off_ovf);
         h->scan_part = (int*)(w + L.off_scan_part);
         h->flags = (int*)(w + L.off_flags);
-        h->count2 = d.P.skin_on ? (int*)(w + L.off_count2) : nullptr;
-        h->xref = d.P.skin_on ? (float2*)(w + L.off_xref) : nullptr;
-        h->rec = d.P.skin_on ? (unsigned char*)(w + L.off_rec) : nullptr;
+        h->stepb = (unsigned*)(w + L.off_stepb);
+        h->reps_dev = (DevParams*)(w + L.off_reps);
+        h->tile_rep = (int*)(w + L.off_tile_rep);
+        h->count2 = d.skin ? (int*)(w + L.off_count2) : nullptr;
+        h->xref = d.skin ? (float2*)(w + L.off_xref) : nullptr;
+        h->rec = d.skin ? (unsigned char*)(w + L.off_rec) : nullptr;
+        h->Tx = d.skin ? nullptr : (float2*)(w + L.off_Tx);
+        h->Tv = d.skin ? nullptr : (float2*)(w + L.off_Tv);
+        h->TF = d.skin ? nullptr : (float2*)(w + L.off_TF);
+        h->Tid = d.skin ? nullptr : (int*)(w + L.off_Tid);
+        h->tile_order = 0;
         h->step = 0;
         h->have_state = false;
         h->prepared = false;
@@ -459,17 +820,18 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
         h->prof_ms = 0.0;
         h->prof_n = 0;
         h->prof_seq = 0;
+        h->graph_chunk = 0;
+        h->cap_stream = nullptr;
         // clear the counters the kernels rely on
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(d.P.n_cells)), dim3(kBlock), 0, h->stream,
-                           h->count, 0, (long long)d.P.n_cells);
+        const long long C = d.cells;
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, h->count, 0, C);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, (int*)h->status, 0, 4LL);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, h->ovf, 0, 1LL);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, h->flags, 0, 16LL);
-        if (d.P.skin_on) {
-            hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(d.P.n_cells)), dim3(kBlock), 0, h->stream,
-                               h->count2, 0, (long long)d.P.n_cells);
+        if (d.skin) {
+            hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, h->count2, 0, C);
             // no tile record is valid before the first rebuild
-            const long long words = (long long)d.n_tiles * (long long)(kRecStride / 4);
+            const long long words = d.tiles_alloc * (long long)(kRecStride / 4);
             hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(words)), dim3(kBlock), 0, h->stream,
                                (int*)h->rec, 0, words);
         }
@@ -479,6 +841,12 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
             delete h;
             return fail(nullptr, DPD_EHIP, m);
         }
+        rc = upload_tables(h);
+        if (rc) {
+            std::string m = h->err;
+            delete h;
+            return fail(nullptr, rc, m);
+        }
         *out = h;
         return DPD_OK;
     } catch (...) {
@@ -486,8 +854,15 @@ int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
     }
 }
 
+int dpd_create(const dpd_params* p, void* workspace, size_t bytes, void* stream,
+               dpd_handle** out) {
+    return dpd_create_batch(p, 1, workspace, bytes, stream, out);
+}
+
 void dpd_destroy(dpd_handle* h) {
     if (!h) return;
+    drop_graphs(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (auto e : h->ev_start) (void)hipEventDestroy(e);
     for (auto e : h->ev_stop) (void)hipEventDestroy(e);
     delete h;
@@ -501,20 +876,26 @@ int dpd_set_state(dpd_handle* h, const float* x, const float* v, int64_t step, c
     if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
     if (!x || !v) return fail(h, DPD_EINVAL, "x and v must not be NULL");
     try {
-        const DevParams& P = h->d.P;
         int rc0 = unprepare(h);
         if (rc0) return rc0;
-        hipLaunchKernelGGL(k_load_input, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
-                           (const float2*)x, (const float2*)v, h->Ax, h->Au, h->Aid, h->key,
-                           h->rank, h->count, h->status);
+        for (const Rep& r : h->d.reps) {
+            const DevParams& P = r.P;
+            const size_t pb = (size_t)P.pbase;
+            hipLaunchKernelGGL(k_load_input, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
+                               (const float2*)x + pb, (const float2*)v + pb, h->Ax + pb, h->Au + pb,
+                               h->Aid + pb, h->key + pb, h->rank + pb, h->count, h->status);
+        }
         LAUNCHCHK(h);
         int rc = bin_from_counts(h, h->count, nullptr, nullptr, F ? h->Aid : nullptr);
         if (rc) return rc;
         if (F) {
-            hipLaunchKernelGGL(k_gather_state, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
-                               (const int*)h->src, (const float2*)h->Ax, (const float2*)h->Au,
-                               (const int*)h->Aid, (const float2*)F, h->Sx, h->Sv, h->Sid, h->SF,
-                               h->status);
+            for (const Rep& r : h->d.reps) {
+                const size_t pb = (size_t)r.P.pbase;
+                hipLaunchKernelGGL(k_gather_state, dim3(grid_for(r.P.N)), dim3(kBlock), 0, h->stream,
+                                   r.P.N, (const int*)h->src + pb, (const float2*)h->Ax,
+                                   (const float2*)h->Au, (const int*)h->Aid, (const float2*)F + pb,
+                                   h->Sx + pb, h->Sv + pb, h->Sid + pb, h->SF + pb, h->status);
+            }
             LAUNCHCHK(h);
         } else {
             PairArgs a = {};
@@ -547,102 +928,56 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
     if (reduce_every < 0) return fail(h, DPD_EINVAL, "reduce_every < 0");
     if (n_steps == 0) return DPD_OK;
     try {
-        const DevParams& P = h->d.P;
-        const bool want_pk = reduce_every > 0 && pk_out != nullptr;
-        float2 *inx, *inu, *outx, *outu;
-        int *inid, *outid;
-        if (h->prepared) {
-            // the previous call already made this step's half kick, drift and keys
-            inx = h->prep_x;
-            inu = h->prep_u;
-            inid = h->prep_id;
-        } else {
-            // first half kick + drift from the stored state; with a skin the first
-            // step rebuilds
-            hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
-                               (const float2*)h->Sx, (const float2*)h->Sv, (const float2*)h->SF,
-                               (const int*)h->Sid, h->Ax, h->Au, h->Aid, h->key, h->rank,
-                               counter_of(h, h->step), h->status);
-            if (P.skin_on)
-                hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream,
-                                   h->flags + (h->step & 1), 1, 1LL);
+        double* pk = reduce_every > 0 ? pk_out : nullptr;
+        int rc;
+        if (!h->prepared) {
+            // first half kick + drift from the stored state
+            rc = kick_drift(h);
+            if (rc) return rc;
+        }
+        int64_t done = 0, rec = 0;
+        const int K = h->graph_chunk;
+        const bool graphs = K > 0 && !h->d.skin && !h->profiling &&
+                            (pk == nullptr || reduce_every % K == 0);
+        if (graphs && n_steps > K && h->prep_x != h->Ax && pk == nullptr) {
+            // a captured chunk starts from the A buffers
+            rc = run_steps(h, 1, 0, nullptr, 0, &rec);
+            if (rc) return rc;
+            done = 1;
+        }
+        if (graphs && h->prep_x == h->Ax && n_steps - done >= K) {
+            const int64_t chunks = (n_steps - done) / K;
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, h->stream, (int*)h->stepb,
+                               (int)(uint32_t)((uint64_t)h->step & 0xffffffffu), 1LL);
             LAUNCHCHK(h);
-            inx = h->Ax;
-            inu = h->Au;
-            inid = h->Aid;
+            for (int64_t c = 0; c < chunks; ++c) {
+                const bool red = pk && ((done + K) % reduce_every == 0);
+                hipGraphExec_t exec = nullptr;
+                for (const Graph& g : h->graphs)
+                    if (g.K == K && g.reduce_last == red) exec = g.exec;
+                if (!exec) {
+                    rc = capture_chunk(h, K, red, &exec);
+                    if (rc) return rc;
+                    h->graphs.push_back(Graph{K, red, exec});
+                }
+                HIPCHK(h, hipGraphLaunch(exec, h->stream));
+                h->step += K;
+                done += K;
+                if (red) {
+                    rc = launch_reduce(h, pk + 3 * (size_t)h->R * (size_t)rec);
+                    if (rc) return rc;
+                    ++rec;
+                }
+            }
+            // every chunk leaves the next step prepared in A
+            h->prep_x = h->Ax;
+            h->prep_u = h->Au;
+            h->prep_id = h->Aid;
         }
-        h->prepared = false;
-        const bool in_a = (inx == h->Ax);
-        outx = in_a ? h->Bx : h->Ax;
-        outu = in_a ? h->Bu : h->Au;
-        outid = in_a ? h->Bid : h->Aid;
-        int rec = 0;
-        for (int k = 1; k <= n_steps; ++k) {
-            // forces of step s = step + k: the binning consumes the keys of x_s
-            // (counters of step s - 1) if this step rebuilds
-            const int64_t s = h->step + k;
-            int* consumed = counter_of(h, s - 1);
-            const int* rebuild = P.skin_on ? h->flags + ((s - 1) & 1) : nullptr;
-            int* moved = P.skin_on ? h->flags + (s & 1) : nullptr;
-            int rc = bin_from_counts(h, consumed, rebuild, moved, nullptr);
+        if (done < n_steps) {
+            rc = run_steps(h, n_steps - done, reduce_every, pk, done, &rec);
             if (rc) return rc;
-            const bool last = (k == n_steps);
-            const bool red = want_pk && (k % reduce_every == 0);
-            PairArgs a = {};
-            a.cs = h->cs;
-            a.src = h->src;
-            a.xin = inx;
-            a.uin = inu;
-            a.idin = inid;
-            a.status = h->status;
-            a.red = h->red;
-            a.step = (uint32_t)((uint64_t)(h->step + k) & 0xffffffffu);
-            a.keyout = h->key;
-            a.rankout = h->rank;
-            a.count = counter_of(h, s);
-            if (P.skin_on) {
-                a.rebuild = rebuild;
-                a.rec = h->rec;
-                a.xref = h->xref;
-                a.moved = moved;
-                a.count_clear = consumed;
-            }
-            if (last) {
-                a.xout = h->Sx;
-                a.uout = h->Sv;
-                a.idout = h->Sid;
-                a.Fout = h->SF;
-                a.pxout = outx;
-                a.puout = outu;
-                a.pidout = outid;
-                rc = launch_pair(h, MODE_FINAL, a, red);
-            } else {
-                a.xout = outx;
-                a.uout = outu;
-                a.idout = outid;
-                rc = launch_pair(h, MODE_STEP, a, red);
-            }
-            if (rc) return rc;
-            if (red) {
-                const int parts = std::min(kRedParts, h->d.n_tiles);
-                double* part = h->red + 3 * (size_t)h->d.n_tiles;
-                hipLaunchKernelGGL(k_reduce_part, dim3(parts), dim3(kBlock), 0, h->stream,
-                                   (const double*)h->red, h->d.n_tiles, part);
-                hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, h->stream,
-                                   (const double*)part, parts, h->p.mass, pk_out + 3 * rec);
-                LAUNCHCHK(h);
-                ++rec;
-            }
-            std::swap(inx, outx);
-            std::swap(inu, outu);
-            std::swap(inid, outid);
         }
-        // the last launch left the next step's start in what is now `in`
-        h->prepared = true;
-        h->prep_x = inx;
-        h->prep_u = inu;
-        h->prep_id = inid;
-        h->step += n_steps;
         return DPD_OK;
     } catch (...) {
         return fail(h, DPD_EINVAL, "internal error");
@@ -654,11 +989,13 @@ int dpd_forces(dpd_handle* h, float* F_out) {
     if (!h->have_state) return fail(h, DPD_ESTATE, "dpd_forces before dpd_set_state");
     if (!F_out) return fail(h, DPD_EINVAL, "F_out is NULL");
     try {
-        const DevParams& P = h->d.P;
         int rc0 = unprepare(h);
         if (rc0) return rc0;
-        hipLaunchKernelGGL(k_key_rank, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
-                           (const float2*)h->Sx, h->key, h->rank, h->count);
+        for (const Rep& r : h->d.reps) {
+            const size_t pb = (size_t)r.P.pbase;
+            hipLaunchKernelGGL(k_key_rank, dim3(grid_for(r.P.N)), dim3(kBlock), 0, h->stream, r.P,
+                               (const float2*)h->Sx + pb, h->key + pb, h->rank + pb, h->count);
+        }
         LAUNCHCHK(h);
         int rc = bin_from_counts(h, h->count, nullptr, nullptr, nullptr);
         if (rc) return rc;
@@ -676,8 +1013,12 @@ int dpd_forces(dpd_handle* h, float* F_out) {
         a.step = (uint32_t)((uint64_t)h->step & 0xffffffffu);
         rc = launch_pair(h, MODE_FORCES, a, false);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_unpermute, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
-                           (const int*)h->Bid, (const float2*)h->Fs, (float2*)F_out);
+        for (const Rep& r : h->d.reps) {
+            const size_t pb = (size_t)r.P.pbase;
+            hipLaunchKernelGGL(k_unpermute, dim3(grid_for(r.P.N)), dim3(kBlock), 0, h->stream, r.P.N,
+                               (const int*)h->Bid + pb, (const float2*)h->Fs + pb,
+                               (float2*)F_out + pb);
+        }
         LAUNCHCHK(h);
         return read_status(h);
     } catch (...) {
@@ -688,13 +1029,15 @@ int dpd_forces(dpd_handle* h, float* F_out) {
 int dpd_get_state(dpd_handle* h, float* x, float* v, float* F, int64_t* step) {
     if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
     if (!h->have_state) return fail(h, DPD_ESTATE, "dpd_get_state before dpd_set_state");
-    const DevParams& P = h->d.P;
     const float2* srcs[3] = {h->Sx, h->Sv, h->SF};
     float* dsts[3] = {x, v, F};
     for (int k = 0; k < 3; ++k) {
         if (!dsts[k]) continue;
-        hipLaunchKernelGGL(k_unpermute, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
-                           (const int*)h->Sid, srcs[k], (float2*)dsts[k]);
+        for (const Rep& r : h->d.reps) {
+            const size_t pb = (size_t)r.P.pbase;
+            hipLaunchKernelGGL(k_unpermute, dim3(grid_for(r.P.N)), dim3(kBlock), 0, h->stream, r.P.N,
+                               (const int*)h->Sid + pb, srcs[k] + pb, (float2*)dsts[k] + pb);
+        }
         LAUNCHCHK(h);
     }
     if (step) *step = h->step;
@@ -704,12 +1047,11 @@ int dpd_get_state(dpd_handle* h, float* x, float* v, float* F, int64_t* step) {
 int dpd_get_cells(dpd_handle* h, int32_t* cell_start_out, int32_t* ids_out) {
     if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
     if (!h->have_state) return fail(h, DPD_ESTATE, "dpd_get_cells before dpd_set_state");
-    const DevParams& P = h->d.P;
     if (cell_start_out)
-        HIPCHK(h, hipMemcpyAsync(cell_start_out, h->cs, ((size_t)P.n_cells + 1) * 4,
+        HIPCHK(h, hipMemcpyAsync(cell_start_out, h->cs, ((size_t)h->d.cells + 1) * 4,
                                  hipMemcpyDeviceToDevice, h->stream));
     if (ids_out)
-        HIPCHK(h, hipMemcpyAsync(ids_out, h->Sid, (size_t)P.N * 4, hipMemcpyDeviceToDevice,
+        HIPCHK(h, hipMemcpyAsync(ids_out, h->Sid, (size_t)h->d.N * 4, hipMemcpyDeviceToDevice,
                                  h->stream));
     return read_status(h);
 }
@@ -723,66 +1065,74 @@ int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode, float* 
     if (!u_out || !n_out) return fail(h, DPD_EINVAL, "u_out and n_out must not be NULL");
     if (!std::isfinite(eps)) return fail(h, DPD_EINVAL, "eps must be finite");
     try {
-        const DevParams& P = h->d.P;
-        // 64-bit fixed point: |v| <= 2^16 and <= 2^ceil(log2 n) contributors per bin
-        const long long n_src = mode == 0 ? P.N : P.N / 2;
-        int lg = 0;
-        while ((1LL << lg) < n_src + 1) ++lg;
-        const int S = std::min(32, 46 - lg);
-        const double qscale = std::ldexp(1.0, S);
-        if (mode == 0 && eps <= 0.0 && M <= 2048) {
-            // plain bins of particle velocities: one block per grid row, read
-            // straight from the canonical state
-            BinRowArgs r;
-            r.Q = std::max(1, std::min(8, M / 32));
-            r.x = h->Sx;
-            r.v = h->Sv;
-            r.cs = h->cs;
-            r.u = (float2*)u_out;
-            r.n = (int*)n_out;
-            r.status = h->status;
-            r.M = M;
-            r.nc = P.nc;
-            r.L = h->p.L;
-            r.inv_dx = (double)M / h->p.L;
-            r.qscale = qscale;
-            r.vmax = 65536.0;
-            const size_t lds = (size_t)((M + r.Q - 1) / r.Q) * 24;
-            hipLaunchKernelGGL(k_bin_rows, dim3(r.Q, M), dim3(kBinRowBlock), lds, h->stream, r);
-            LAUNCHCHK(h);
-            return DPD_OK;
+        const bool rows = mode == 0 && eps <= 0.0 && M <= 2048;
+        if (!rows) {
+            // id-order copies of x and v go to the scratch buffers (which may hold
+            // the prepared next step)
+            int rc0 = unprepare(h);
+            if (rc0) return rc0;
         }
-        // id-order copies of x and v into the scratch buffers (which may hold the
-        // prepared next step)
-        int rc0 = unprepare(h);
-        if (rc0) return rc0;
-        hipLaunchKernelGGL(k_unpermute, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
-                           (const int*)h->Sid, (const float2*)h->Sx, h->Bx);
-        hipLaunchKernelGGL(k_unpermute, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
-                           (const int*)h->Sid, (const float2*)h->Sv, h->Bu);
         const long long nbin = (long long)M * M;
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nbin * 6)), dim3(kBlock), 0, h->stream,
-                           (int*)h->binacc, 0, nbin * 6);
-        LAUNCHCHK(h);
-        BinArgs b;
-        b.x = h->Bx;
-        b.v = h->Bu;
-        b.acc = h->binacc;
-        b.status = h->status;
-        b.n_src = mode == 0 ? P.N : P.N / 2;
-        b.mode = mode;
-        b.M = M;
-        b.L = h->p.L;
-        b.inv_dx = (double)M / h->p.L;
-        b.dx = h->p.L / (double)M;
-        b.eps = eps;
-        b.qscale = qscale;
-        b.vmax = 65536.0;
-        hipLaunchKernelGGL(k_bin_accum, dim3(grid_for(b.n_src)), dim3(kBlock), 0, h->stream, b);
-        hipLaunchKernelGGL(k_bin_finalize, dim3(grid_for(nbin)), dim3(kBlock), 0, h->stream,
-                           (int)nbin, (const long long*)h->binacc, b.qscale, (float2*)u_out,
-                           (int*)n_out);
-        LAUNCHCHK(h);
+        for (int ri = 0; ri < h->R; ++ri) {
+            const Rep& rp = h->d.reps[ri];
+            const DevParams& P = rp.P;
+            const size_t pb = (size_t)P.pbase;
+            float2* u = (float2*)u_out + (size_t)ri * nbin;
+            int* n = (int*)n_out + (size_t)ri * nbin;
+            // 64-bit fixed point: |v| <= 2^16 and <= 2^ceil(log2 n) contributors per bin
+            const long long n_src = mode == 0 ? P.N : P.N / 2;
+            int lg = 0;
+            while ((1LL << lg) < n_src + 1) ++lg;
+            const int S = std::min(32, 46 - lg);
+            const double qscale = std::ldexp(1.0, S);
+            if (rows) {
+                // plain bins of particle velocities: one block per grid row, read
+                // straight from the canonical state
+                BinRowArgs r;
+                r.Q = std::max(1, std::min(8, M / 32));
+                r.x = h->Sx;
+                r.v = h->Sv;
+                r.cs = h->cs + P.cbase;
+                r.u = u;
+                r.n = n;
+                r.status = h->status;
+                r.M = M;
+                r.nc = P.nc;
+                r.L = rp.p.L;
+                r.inv_dx = (double)M / rp.p.L;
+                r.qscale = qscale;
+                r.vmax = 65536.0;
+                const size_t lds = (size_t)((M + r.Q - 1) / r.Q) * 24;
+                hipLaunchKernelGGL(k_bin_rows, dim3(r.Q, M), dim3(kBinRowBlock), lds, h->stream, r);
+                LAUNCHCHK(h);
+                continue;
+            }
+            hipLaunchKernelGGL(k_unpermute, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
+                               (const int*)h->Sid + pb, (const float2*)h->Sx + pb, h->Bx + pb);
+            hipLaunchKernelGGL(k_unpermute, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P.N,
+                               (const int*)h->Sid + pb, (const float2*)h->Sv + pb, h->Bu + pb);
+            hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nbin * 6)), dim3(kBlock), 0, h->stream,
+                               (int*)h->binacc, 0, nbin * 6);
+            LAUNCHCHK(h);
+            BinArgs b;
+            b.x = h->Bx + pb;
+            b.v = h->Bu + pb;
+            b.acc = h->binacc;
+            b.status = h->status;
+            b.n_src = n_src;
+            b.mode = mode;
+            b.M = M;
+            b.L = rp.p.L;
+            b.inv_dx = (double)M / rp.p.L;
+            b.dx = rp.p.L / (double)M;
+            b.eps = eps;
+            b.qscale = qscale;
+            b.vmax = 65536.0;
+            hipLaunchKernelGGL(k_bin_accum, dim3(grid_for(b.n_src)), dim3(kBlock), 0, h->stream, b);
+            hipLaunchKernelGGL(k_bin_finalize, dim3(grid_for(nbin)), dim3(kBlock), 0, h->stream,
+                               (int)nbin, (const long long*)h->binacc, b.qscale, u, n);
+            LAUNCHCHK(h);
+        }
         return DPD_OK;
     } catch (...) {
         return fail(h, DPD_EINVAL, "internal error");
@@ -796,14 +1146,14 @@ int dpd_sync(dpd_handle* h) {
 
 int dpd_rng_words(const dpd_params* p, const int32_t* i, const int32_t* j, int64_t step,
                   int32_t n, uint32_t* words_out, float* alpha_out, void* stream) {
-    Derived d;
+    DevParams P;
     std::string err;
-    int rc = derive(p, &d, &err);
+    int rc = derive_one(p, P, &err);
     if (rc) return fail(nullptr, rc, err);
     if (n < 0 || !i || !j || !words_out) return fail(nullptr, DPD_EINVAL, "bad arguments");
     if (n == 0) return DPD_OK;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_rng_words, dim3(grid_for(n)), dim3(kBlock), 0, s, d.P, (const int*)i,
+    hipLaunchKernelGGL(k_rng_words, dim3(grid_for(n)), dim3(kBlock), 0, s, P, (const int*)i,
                        (const int*)j, (uint32_t)((uint64_t)step & 0xffffffffu), (int)n,
                        (uint4*)words_out, alpha_out);
     hipError_t e = hipGetLastError();
@@ -848,6 +1198,112 @@ int dpd_cell_list_rebuilds(dpd_handle* h, int64_t* rebuilds) {
     HIPCHK(h, hipMemcpy(&n, h->flags + 2, sizeof n, hipMemcpyDeviceToHost));
     *rebuilds = n;
     return DPD_OK;
+}
+
+int dpd_set_graph_chunk(dpd_handle* h, int32_t steps) {
+    if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
+    if (steps < 0 || (steps & 1) || steps > 4096)
+        return fail(h, DPD_EINVAL, "graph chunk must be 0 or an even number of steps <= 4096");
+    if (steps != h->graph_chunk) drop_graphs(h);
+    h->graph_chunk = steps;
+    return DPD_OK;
+}
+
+int dpd_set_schedule(dpd_handle* h, int32_t tile_x, int32_t tile_y, int32_t tile_order) {
+    if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
+    if (h->d.skin) return fail(h, DPD_EINVAL, "the schedule of a Verlet-skin handle is fixed");
+    if (tile_x < 1 || tile_x > kTileMax || tile_y < 1 || tile_y > kTileMax)
+        return fail(h, DPD_EINVAL, fmt("tile sides must be in [1, %d]", kTileMax));
+    if (tile_order != 0 && tile_order != 1) return fail(h, DPD_EINVAL, "tile_order must be 0 or 1");
+    try {
+        return apply_schedule(h, tile_x, tile_y, tile_order);
+    } catch (...) {
+        return fail(h, DPD_EINVAL, "internal error");
+    }
+}
+
+int dpd_get_schedule(dpd_handle* h, int32_t* tile_x, int32_t* tile_y, int32_t* tile_order) {
+    if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
+    if (tile_x) *tile_x = P0(h).tile_x;
+    if (tile_y) *tile_y = P0(h).tile_y;
+    if (tile_order) *tile_order = h->tile_order;
+    return DPD_OK;
+}
+
+int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* tile_y,
+                 int32_t* tile_order, double* best_ms) {
+    if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
+    if (!h->have_state) return fail(h, DPD_ESTATE, "dpd_autotune before dpd_set_state");
+    if (h->d.skin) return fail(h, DPD_EINVAL, "the schedule of a Verlet-skin handle is fixed");
+    if (trial_steps < 1 || trial_steps > 100000) return fail(h, DPD_EINVAL, "trial_steps must be in [1, 100000]");
+    try {
+        static const int cand[][2] = {{8, 7}, {8, 8}, {7, 7}, {7, 6}, {6, 6}, {8, 5}, {6, 5}, {5, 5}, {4, 4}};
+        const bool prof = h->profiling;
+        h->profiling = false;
+        const int64_t step0 = h->step;
+        int rc = unprepare(h);
+        if (!rc) rc = copy_state(h, true);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (!rc && hipEventCreate(&e0) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventCreate failed");
+        if (!rc && hipEventCreate(&e1) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventCreate failed");
+        double best = 1e300;
+        int bx = P0(h).tile_x, by = P0(h).tile_y, bo = h->tile_order;
+        std::vector<long long> seen;
+        for (const auto& c : cand) {
+            for (int order = 0; order < 2 && !rc; ++order) {
+                // skip tilings that clamp to one already timed, and those that do
+                // not fit the per-tile arrays
+                Derived nd = h->d;
+                for (Rep& r : nd.reps) set_tiling(r.P, c[0], c[1]);
+                assign_offsets(&nd);
+                if (nd.tiles > h->d.tiles_alloc) continue;
+                long long sig = order;
+                for (const Rep& r : nd.reps) sig = sig * 1000003LL + r.P.tile_x * 16 + r.P.tile_y;
+                if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+                seen.push_back(sig);
+                rc = apply_schedule(h, c[0], c[1], order);
+                if (!rc) rc = copy_state(h, false);
+                if (rc) break;
+                h->step = step0;
+                h->prepared = false;
+                rc = kick_drift(h);
+                int64_t rec = 0;
+                if (!rc) rc = run_steps(h, 2, 0, nullptr, 0, &rec);  // untimed
+                if (!rc && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventRecord failed");
+                if (!rc) rc = run_steps(h, trial_steps, 0, nullptr, 0, &rec);
+                if (!rc && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventRecord failed");
+                if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventSynchronize failed");
+                float ms = 0.f;
+                if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventElapsedTime failed");
+                if (rc) break;
+                rc = unprepare(h);
+                if (!rc && ms < best) {
+                    best = ms;
+                    bx = c[0];
+                    by = c[1];
+                    bo = order;
+                }
+            }
+            if (rc) break;
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        h->profiling = prof;
+        if (rc) return rc;
+        // the chosen schedule, and the state as it was
+        rc = apply_schedule(h, bx, by, bo);
+        if (!rc) rc = copy_state(h, false);
+        if (rc) return rc;
+        h->step = step0;
+        h->prepared = false;
+        if (tile_x) *tile_x = P0(h).tile_x;
+        if (tile_y) *tile_y = P0(h).tile_y;
+        if (tile_order) *tile_order = bo;
+        if (best_ms) *best_ms = best / trial_steps;
+        return read_status(h);
+    } catch (...) {
+        return fail(h, DPD_EINVAL, "internal error");
+    }
 }
 
 int dpd_copy_kernel(const void* src, void* dst, size_t bytes, void* stream) {

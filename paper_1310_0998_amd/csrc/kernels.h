@@ -55,7 +55,7 @@ struct PairArgs {
     float2* xout;       // STEP: next position; FINAL/FORCES: position
     float2* uout;       // STEP: next half-step velocity; FINAL: v; FORCES: input velocity
     int* idout;
-    int* keyout;        // STEP: new cell key
+    int* keyout;        // STEP: new cell key (index into the cells of the whole batch)
     int* rankout;       // STEP: rank of the particle within its new cell
     int* count;         // STEP: per-cell counters (atomically incremented)
     float2* Fout;       // FINAL/FORCES: total force
@@ -72,7 +72,15 @@ struct PairArgs {
     float2* xref;       // position of every slot at the last rebuild
     int* moved;         // set when a particle has moved more than skin / 2 since then
     int* count_clear;   // the other per-cell counter array, cleared cell by cell
-    uint32_t step;      // step number of the force evaluation (mod 2^32)
+    uint32_t step;      // step number of the force evaluation (mod 2^32), or its
+                        // offset from *step_base when that is set
+    const uint32_t* step_base;  // null, or the step before a replayed graph chunk
+    // a batch of replicas: the parameters of each, the replica of each tile of
+    // the concatenated tile list, and the number of tiles
+    const DevParams* reps;
+    const int* tile_rep;
+    int nt_total;
+    int tile_order;     // 0: bands of consecutive tiles per XCD; 1: launch order
 };
 
 // ---- small helpers ----------------------------------------------------------
@@ -261,7 +269,7 @@ __device__ __forceinline__ void finish_particle(const DevParams& P, const PairAr
         if (a.pxout) {  // start the next call's first step: half kick, drift, key, rank
             const float2 un = make_float2(fmaf(P.h, fx, v.x), fmaf(P.h, fy, v.y));
             const float2 xn = make_float2(drift_wrap(xi.x, un.x, P), drift_wrap(xi.y, un.y, P));
-            const int key = cell_key(xn, P);
+            const int key = cell_key(xn, P) + P.cbase;
             a.pxout[g] = xn;
             a.puout[g] = un;
             a.pidout[g] = idi;
@@ -275,7 +283,7 @@ __device__ __forceinline__ void finish_particle(const DevParams& P, const PairAr
     }
     const float2 un = make_float2(fmaf(P.h, fx, v.x), fmaf(P.h, fy, v.y));
     const float2 xn = make_float2(drift_wrap(xi.x, un.x, P), drift_wrap(xi.y, un.y, P));
-    const int key = cell_key(xn, P);
+    const int key = cell_key(xn, P) + P.cbase;
     const int rank = atomicAdd(&a.count[key], 1);
     a.xout[g] = xn;
     a.uout[g] = un;
@@ -311,9 +319,9 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
             int g = b, idi = 0x7FFFFFFF, p = 0;
             for (int g1 = b; g1 < e; ++g1) {
                 int p1 = REBUILT ? a.src[g1] : g1;
-                if ((unsigned)p1 >= (unsigned)P.N) {
+                if ((unsigned)(p1 - P.pbase) >= (unsigned)P.N) {  // outside this system
                     atomicOr(a.status, kStatusBinning);
-                    p1 = 0;
+                    p1 = P.pbase;
                 }
                 const int id1 = a.idin[p1];
                 if (id1 > last && id1 < idi) {
@@ -335,7 +343,7 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
                     for (int g2 = b2; g2 < e2; ++g2) {
                         if (g2 == g) continue;
                         int q = REBUILT ? a.src[g2] : g2;
-                        if ((unsigned)q >= (unsigned)P.N) q = 0;
+                        if ((unsigned)(q - P.pbase) >= (unsigned)P.N) q = P.pbase;
                         const int idj = a.idin[q];
                         const float2 xj = a.xin[q];
                         if (idj == pid) {
@@ -449,8 +457,10 @@ __device__ __forceinline__ void tile_reduce(const PairArgs& a, int t, double rv[
 //   C  every tile particle adds its agent forces and finishes the step.
 // A tile that overflows an LDS capacity is left to k_pair_overflow.
 // SKIN compiles the Verlet-skin code (records, list steps, displacement test)
-// in; without it the kernel carries none of it.
-template <int MODE, bool SKIN>
+// in; without it the kernel carries none of it.  BATCH: the tiles of all
+// replicas of a batch form one launch; each wavefront reads its replica's
+// parameters from a.reps (the kernel argument P is then unused).
+template <int MODE, bool SKIN, bool BATCH>
 __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int reduce) {
     __shared__ int s_ofs[kLocMax + 1];       // first staged index of each local cell
     __shared__ int s_gbeg[kLocMax];          // first global slot of each local cell
@@ -472,11 +482,20 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
 
     // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs, so give
     // each XCD a contiguous band of tiles (neighbouring halos share its L2).
-    const int nt = P.ntx * P.nty;
+    const int nt = BATCH ? a.nt_total : P.ntx * P.nty;
     const int bid = blockIdx.x;
-    const int xcd = bid & 7, kk = bid >> 3;
-    const int per = nt >> 3, rem = nt & 7;
-    const int tile = xcd * per + min(xcd, rem) + kk;
+    int gtile = bid;
+    if (a.tile_order == 0) {
+        const int xcd = bid & 7, kk = bid >> 3;
+        const int per = nt >> 3, rem = nt & 7;
+        gtile = xcd * per + min(xcd, rem) + kk;
+    }
+    if constexpr (BATCH) {
+        P = a.reps[a.tile_rep[gtile]];
+        a.cs += P.cbase;
+    }
+    if (a.step_base) a.step += *a.step_base;
+    const int tile = BATCH ? gtile - P.tbase : gtile;
     const TileGeom G = tile_geom(P, tile);
     const int cx0 = G.cx0, cy0 = G.cy0, tw = G.tw, th = G.th;
     const int W = tw + 2, nloc = W * (th + 2);
@@ -557,9 +576,9 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 if (q < total) {
                     const int lc = s_lcell[q];
                     int p = a.src[s_gbeg[lc] + (q - s_ofs[lc])];
-                    if ((unsigned)p >= (unsigned)P.N) {
+                    if ((unsigned)(p - P.pbase) >= (unsigned)P.N) {  // outside this system
                         atomicOr(a.status, kStatusBinning);
-                        p = 0;
+                        p = P.pbase;
                     }
                     lcq[r] = lc;
                     idq[r] = a.idin[p];
@@ -702,9 +721,9 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
             const int total = min(R->total, kCap), nlist = min(R->nlist, kLcap);
             for (int q = lane; q < total; q += kWave) {
                 int g = R->slot[q];
-                if ((unsigned)g >= (unsigned)P.N) {
+                if ((unsigned)(g - P.pbase) >= (unsigned)P.N) {
                     atomicOr(a.status, kStatusBinning);
-                    g = 0;
+                    g = P.pbase;
                 }
                 const float2 xg = a.xin[g];
                 s_rec[q] = make_float4(xg.x, xg.y, __int_as_float(a.idin[g]), __int_as_float((int)R->tix[q]));
@@ -742,7 +761,7 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
     double rv[3] = {0.0, 0.0, 0.0};
     if (!ok) {
         // over an LDS capacity: leave the tile to k_pair_overflow
-        if (lane == 0) a.ovf_list[atomicAdd(a.ovf_count, 1)] = tile;
+        if (lane == 0) a.ovf_list[atomicAdd(a.ovf_count, 1)] = gtile;
         return;
     }
     for (int k = lane; k < ntile; k += kWave) {
@@ -801,33 +820,45 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
             const int lc = s_lcell[si];
             g = s_gbeg[lc] + (si - s_ofs[lc]);
         }
+        // inconsistent cell data (flagged above) must not turn into a stray store
+        if ((unsigned)(g - P.pbase) >= (unsigned)P.N) {
+            atomicOr(a.status, kStatusBinning);
+            continue;
+        }
         finish_particle<MODE, SKIN>(P, a, g, xi, ui, idi, fx, fy, rv, reduce != 0, rebuild);
     }
-    if (reduce) tile_reduce(a, tile, rv);
+    if (reduce) tile_reduce(a, gtile, rv);
 }
 
 // The tiles k_pair left over, one 64-lane wavefront per listed tile, through
 // the global-memory path (same results bit for bit).  Launched right after
 // k_pair with a fixed grid; with an empty list every wavefront exits at once.
-template <int MODE, bool REBUILT>
-__device__ __forceinline__ void overflow_tiles(const DevParams& P, const PairArgs& a, int n,
+template <int MODE, bool REBUILT, bool BATCH>
+__device__ __forceinline__ void overflow_tiles(const DevParams& P0, const PairArgs& a0, int n,
                                                int reduce) {
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
-        const int tile = a.ovf_list[i];
-        const TileGeom G = tile_geom(P, tile);
+        const int gtile = a0.ovf_list[i];
+        DevParams P = P0;
+        PairArgs a = a0;
+        if constexpr (BATCH) {
+            P = a.reps[a.tile_rep[gtile]];
+            a.cs += P.cbase;
+        }
+        const TileGeom G = tile_geom(P, BATCH ? gtile - P.tbase : gtile);
         double rv[3] = {0.0, 0.0, 0.0};
         tile_global<MODE, REBUILT>(P, a, G.cx0, G.cy0, G.tw, G.th, rv);
-        if (reduce) tile_reduce(a, tile, rv);
+        if (reduce) tile_reduce(a, gtile, rv);
     }
 }
 
-template <int MODE>
+template <int MODE, bool BATCH>
 __global__ __launch_bounds__(kWave) void k_pair_overflow(DevParams P, PairArgs a, int reduce) {
     const int n = *a.ovf_count;
+    if (a.step_base) a.step += *a.step_base;
     if (MODE == MODE_FORCES || a.rebuild == nullptr || *a.rebuild != 0)
-        overflow_tiles<MODE, true>(P, a, n, reduce);
+        overflow_tiles<MODE, true, BATCH>(P, a, n, reduce);
     else
-        overflow_tiles<MODE, false>(P, a, n, reduce);
+        overflow_tiles<MODE, false, BATCH>(P, a, n, reduce);
 }
 
 // ---- binning ------------------------------------------------------------------
@@ -842,7 +873,7 @@ __global__ void k_load_input(DevParams P, const float2* __restrict__ x, const fl
     const float2 xi = x[i], vi = v[i];
     if (!finite2(xi) || !finite2(vi)) atomicOr(status, kStatusNonFinite);
     const float2 xw = make_float2(drift_wrap(xi.x, 0.f, P), drift_wrap(xi.y, 0.f, P));
-    const int k = cell_key(xw, P);
+    const int k = cell_key(xw, P) + P.cbase;
     xo[i] = xw;
     uo[i] = vi;
     ido[i] = i;
@@ -855,7 +886,7 @@ __global__ void k_key_rank(DevParams P, const float2* __restrict__ x, int* key, 
                            int* count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.N) return;
-    const int k = cell_key(x[i], P);
+    const int k = cell_key(x[i], P) + P.cbase;
     key[i] = k;
     rank[i] = atomicAdd(&count[k], 1);
 }
@@ -1035,7 +1066,7 @@ __global__ void k_kick_drift(DevParams P, const float2* __restrict__ x, const fl
     const float2 f = F[g], vv = v[g], xx = x[g];
     const float2 u = make_float2(fmaf(P.h, f.x, vv.x), fmaf(P.h, f.y, vv.y));
     const float2 xn = make_float2(drift_wrap(xx.x, u.x, P), drift_wrap(xx.y, u.y, P));
-    const int k = cell_key(xn, P);
+    const int k = cell_key(xn, P) + P.cbase;
     xo[g] = xn;
     uo[g] = u;
     ido[g] = id[g];
@@ -1082,6 +1113,28 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restric
         out[0] = mass * v[0];
         out[1] = mass * v[1];
         out[2] = 0.5 * mass * v[2];
+    }
+}
+
+// Per replica of a batch: (P_x, P_y, KE) of its tiles, summed in a fixed order
+// by one block per replica.
+__global__ __launch_bounds__(kBlock) void k_reduce_reps(const double* __restrict__ red,
+                                                        const DevParams* __restrict__ reps,
+                                                        double* out) {
+    __shared__ double s_red[kBlock / kWave][3];
+    const DevParams& P = reps[blockIdx.x];
+    const int t0 = P.tbase, t1 = P.tbase + P.ntx * P.nty;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = t0 + threadIdx.x; t < t1; t += kBlock) {
+        v[0] += red[3 * t + 0];
+        v[1] += red[3 * t + 1];
+        v[2] += red[3 * t + 2];
+    }
+    block_sum3(v, s_red);
+    if (threadIdx.x == 0) {
+        out[3 * blockIdx.x + 0] = P.mass_d * v[0];
+        out[3 * blockIdx.x + 1] = P.mass_d * v[1];
+        out[3 * blockIdx.x + 2] = 0.5 * P.mass_d * v[2];
     }
 }
 
@@ -1329,6 +1382,11 @@ __global__ void k_rng_words(DevParams P, const int* __restrict__ i, const int* _
 __global__ void k_fill_i32(int* p, int v, long long n) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Advance the step before the next replay of a captured chunk of steps.
+__global__ void k_add_u32(unsigned* p, unsigned v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) p[0] += v;
 }
 
 __global__ void k_copy16(const uint4* __restrict__ a, uint4* __restrict__ b, long long n) {

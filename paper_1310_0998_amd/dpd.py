@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Mapping, Optional
+from typing import Mapping, Optional, Sequence, Union
 
 import torch  # loaded first so that the engine binds to torch's HIP runtime
 
@@ -100,6 +100,14 @@ def lib() -> ctypes.CDLL:
             "dpd_pair_kernel_time": (ctypes.c_int, [vp, ctypes.POINTER(f64), ctypes.POINTER(i64)]),
             "dpd_cell_list_rebuilds": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
             "dpd_copy_kernel": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+            "dpd_batch_workspace_bytes": (ctypes.c_int, [P, i32, ctypes.POINTER(ctypes.c_size_t)]),
+            "dpd_create_batch": (ctypes.c_int, [P, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+            "dpd_set_graph_chunk": (ctypes.c_int, [vp, i32]),
+            "dpd_set_schedule": (ctypes.c_int, [vp, i32, i32, i32]),
+            "dpd_get_schedule": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                                ctypes.POINTER(i32)]),
+            "dpd_autotune": (ctypes.c_int, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                            ctypes.POINTER(i32), ctypes.POINTER(f64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -136,31 +144,50 @@ def cells_per_side(cfg: Mapping) -> int:
     return int(r)
 
 
-def workspace_bytes(cfg: Mapping) -> int:
+def _param_array(cfgs: Sequence[Mapping]):
+    arr = (Params * len(cfgs))()
+    for k, c in enumerate(cfgs):
+        arr[k] = make_params(c)
+    return arr
+
+
+def workspace_bytes(cfg: Union[Mapping, Sequence[Mapping]]) -> int:
+    cfgs = [cfg] if isinstance(cfg, Mapping) else list(cfg)
     n = ctypes.c_size_t(0)
-    _check(lib().dpd_workspace_bytes(ctypes.byref(make_params(cfg)), ctypes.byref(n)))
+    _check(lib().dpd_batch_workspace_bytes(_param_array(cfgs), len(cfgs), ctypes.byref(n)))
     return int(n.value)
 
 
 class Sim:
-    """One simulation bound to the current torch stream of `device`."""
+    """One simulation, or a batch of independent replicas (cfg a list of
+    configurations), bound to the current torch stream of `device`.  For a
+    batch every state tensor is the replicas' (N_q, 2) blocks concatenated in
+    replica order."""
 
-    def __init__(self, cfg: Mapping, device="cuda"):
-        self.cfg = dict(cfg)
+    def __init__(self, cfg: Union[Mapping, Sequence[Mapping]], device="cuda"):
+        self.batch = not isinstance(cfg, Mapping)
+        cfgs = [dict(cfg)] if not self.batch else [dict(c) for c in cfg]
+        self.cfgs = cfgs
+        self.cfg = cfgs[0]
+        self.R = len(cfgs)
         self.device = torch.device(device)
-        self.params = make_params(cfg)
-        self.N = 2 * int(cfg["n_agents"])
-        nbytes = workspace_bytes(cfg)
+        self._params = _param_array(cfgs)
+        self.params = self._params[0]
+        self.sizes = [2 * int(c["n_agents"]) for c in cfgs]
+        self.N = sum(self.sizes)
+        nbytes = workspace_bytes(cfgs)
         # the allocator returns 512-byte aligned blocks; keep 256 spare anyway
         self._ws_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws_raw.data_ptr()
         self._ws_ptr = (base + 255) & ~255
         self._stream = _stream_handle(self.device)
         h = ctypes.c_void_p()
-        _check(lib().dpd_create(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr),
-                                ctypes.c_size_t(nbytes), self._stream, ctypes.byref(h)))
+        _check(lib().dpd_create_batch(self._params, self.R, ctypes.c_void_p(self._ws_ptr),
+                                      ctypes.c_size_t(nbytes), self._stream, ctypes.byref(h)))
         self._h = h
-        self.n_c = cells_per_side(cfg)
+        ncs = [cells_per_side(c) for c in cfgs]
+        self.n_c = ncs if self.batch else ncs[0]
+        self.n_cells = sum(n * n for n in ncs)
 
     # -- lifecycle
     def close(self):
@@ -202,10 +229,12 @@ class Sim:
 
     def step(self, n: int, reduce_every: int = 0, pk: Optional[torch.Tensor] = None):
         """Advance n steps.  With reduce_every > 0 returns a (n // reduce_every, 3)
-        float64 device tensor of (P_x, P_y, KE) records."""
+        float64 device tensor of (P_x, P_y, KE) records ((n // reduce_every, R, 3)
+        for a batch)."""
         if reduce_every > 0 and pk is None:
             nrec = n // reduce_every
-            pk = torch.zeros((max(nrec, 1), 3), dtype=torch.float64, device=self.device)
+            shape = (max(nrec, 1), self.R, 3) if self.batch else (max(nrec, 1), 3)
+            pk = torch.zeros(shape, dtype=torch.float64, device=self.device)
         self._c(lib().dpd_step(self._h, int(n), int(reduce_every), _ptr(pk)))
         if reduce_every > 0:
             return pk[: n // reduce_every]
@@ -216,17 +245,19 @@ class Sim:
 
     def bin_velocity(self, M: int, eps: float = 0.0, mode: int = 0, out=None):
         """Mean velocity (M, M, 2) [row j, column i] and counts (M, M) per grid
-        window; asynchronous on the stream (reading the tensors waits for it)."""
+        window ((R, M, M, 2) and (R, M, M) for a batch); asynchronous on the
+        stream (reading the tensors waits for it)."""
         if out is None:
-            u = torch.empty((M, M, 2), dtype=torch.float32, device=self.device)
-            n = torch.empty((M, M), dtype=torch.int32, device=self.device)
+            lead = (self.R,) if self.batch else ()
+            u = torch.empty(lead + (M, M, 2), dtype=torch.float32, device=self.device)
+            n = torch.empty(lead + (M, M), dtype=torch.int32, device=self.device)
         else:
             u, n = out
         self._c(lib().dpd_bin_velocity(self._h, int(M), float(eps), int(mode), _ptr(u), _ptr(n)))
         return u, n
 
     def cells(self):
-        cs = torch.empty(self.n_c * self.n_c + 1, dtype=torch.int32, device=self.device)
+        cs = torch.empty(self.n_cells + 1, dtype=torch.int32, device=self.device)
         ids = torch.empty(self.N, dtype=torch.int32, device=self.device)
         self._c(lib().dpd_get_cells(self._h, _ptr(cs), _ptr(ids)))
         return cs, ids
@@ -246,6 +277,28 @@ class Sim:
         n = ctypes.c_int64(0)
         self._c(lib().dpd_cell_list_rebuilds(self._h, ctypes.byref(n)))
         return int(n.value)
+
+    # -- captured chunks and schedules
+    def set_graph_chunk(self, steps: int):
+        """Replay dpd_step in captured chunks of `steps` launches (0: off)."""
+        self._c(lib().dpd_set_graph_chunk(self._h, int(steps)))
+
+    def set_schedule(self, tile_x: int, tile_y: int, tile_order: int = 0):
+        self._c(lib().dpd_set_schedule(self._h, int(tile_x), int(tile_y), int(tile_order)))
+
+    def schedule(self):
+        tx, ty, o = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        self._c(lib().dpd_get_schedule(self._h, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(o)))
+        return int(tx.value), int(ty.value), int(o.value)
+
+    def autotune(self, trial_steps: int = 20):
+        """Time the candidate schedules on the current state, keep the fastest
+        (the state is left as it was).  Returns (tile_x, tile_y, order, ms/step)."""
+        tx, ty, o = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        ms = ctypes.c_double(0.0)
+        self._c(lib().dpd_autotune(self._h, int(trial_steps), ctypes.byref(tx), ctypes.byref(ty),
+                                   ctypes.byref(o), ctypes.byref(ms)))
+        return int(tx.value), int(ty.value), int(o.value), float(ms.value)
 
 
 def rng_words(cfg: Mapping, i: torch.Tensor, j: torch.Tensor, step: int):

@@ -41,6 +41,34 @@ PAPER_SET = dict(
 )
 
 
+# Batched sweep: replicas over area fraction phi and the friction ratio
+# gamma / zeta (the paper varies phi, Gamma and Gamma_s, Sec. 5 and 5.1).
+SWEEP_PHI = (0.2, 0.4, 0.6, 0.8)
+SWEEP_RATIO = (0.1, 1.0, 10.0, 100.0)
+
+
+def sweep_replicas(n_rep: int = 64, seed: int = 401, n_min: int = 2000, n_max: int = 64000,
+                   base: dict | None = None) -> list:
+    """Workload mappings of a seeded sweep: agent counts log-uniform on
+    [n_min, n_max]; replica r takes grid point r mod 16 of phi x (gamma/zeta)
+    with gamma = 4.5 and zeta = 4.5 / ratio; box side L = r_c sqrt(N_a / phi)
+    rounded to a multiple of 2^-8 (areal density 2 phi / r_c^2); noise seed
+    4000 + r."""
+    b = dict(_BASE if base is None else base)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    na = np.exp(rng.uniform(math.log(n_min), math.log(n_max), size=n_rep))
+    grid = [(phi, ratio) for phi in SWEEP_PHI for ratio in SWEEP_RATIO]
+    out = []
+    for r in range(n_rep):
+        phi, ratio = grid[r % len(grid)]
+        n_agents = int(round(float(na[r])))
+        L = b["r_c"] * math.sqrt(n_agents / phi)
+        L = math.floor(L * 256.0) / 256.0
+        out.append(dict(b, n_agents=n_agents, L=L, gamma=4.5, gamma_s=4.5 / ratio,
+                        seed=4000 + r, phi=phi, ratio=ratio))
+    return out
+
+
 def physics(cfg: dict) -> dict:
     """The model parameters of a workload (drops run-length keys)."""
     keep = ("n_agents", "L", "r_c", "A", "gamma", "kT", "kappa", "bond_l", "f_sp",

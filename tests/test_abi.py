@@ -94,3 +94,49 @@ def test_null_handle_calls_fail_cleanly(dpd):
     assert lib.dpd_set_state(None, None, None, 0, None) == -1
     assert lib.dpd_sync(None) == -1
     lib.dpd_destroy(None)
+
+
+def test_batch_workspace_and_validation(dpd):
+    c1 = inputs.physics(inputs.WORKLOADS["dimers_1600"])
+    one = dpd.workspace_bytes(c1)
+    assert dpd.workspace_bytes([c1]) == one
+    two = dpd.workspace_bytes([c1, dict(c1, n_agents=300, L=23.0)])
+    assert two > one
+    sweep = [inputs.physics(c) for c in inputs.sweep_replicas()]
+    assert len(sweep) == 64
+    assert dpd.workspace_bytes(sweep) < 2 * 1024 ** 3
+    with pytest.raises(dpd.DPDError) as ei:
+        dpd.workspace_bytes([c1, dict(c1, skin=0.3)])  # no skin in a batch
+    assert ei.value.code == -1
+    with pytest.raises(dpd.DPDError) as ei:
+        dpd.workspace_bytes([c1, dict(c1, L=2.5)])     # a bad replica names itself
+    assert b"replica 1" in dpd.lib().dpd_last_error(None)
+    lib = dpd.lib()
+    n = ctypes.c_size_t(0)
+    assert lib.dpd_batch_workspace_bytes(ctypes.byref(dpd.make_params(c1)), 0, ctypes.byref(n)) == -1
+
+
+def test_null_handle_batch_calls_fail_cleanly(dpd):
+    lib = dpd.lib()
+    i = ctypes.c_int32(0)
+    assert lib.dpd_set_graph_chunk(None, 8) == -1
+    assert lib.dpd_set_schedule(None, 8, 7, 0) == -1
+    assert lib.dpd_get_schedule(None, ctypes.byref(i), ctypes.byref(i), ctypes.byref(i)) == -1
+    assert lib.dpd_autotune(None, 4, None, None, None, None) == -1
+
+
+def test_sweep_replicas_recipe():
+    # seeded, log-uniform sizes in range, the 16-point grid four times over,
+    # boxes exactly representable in FP32 at areal density 2 phi
+    import numpy as np
+    a = inputs.sweep_replicas()
+    assert a == inputs.sweep_replicas()
+    na = np.array([c["n_agents"] for c in a])
+    assert na.min() >= 2000 and na.max() <= 64000
+    grid = {(c["phi"], c["ratio"]) for c in a}
+    assert len(grid) == 16
+    for c in a:
+        assert float(np.float32(c["L"])) == c["L"]
+        rho = 2 * c["n_agents"] / c["L"] ** 2
+        assert abs(rho / (2 * c["phi"]) - 1) < 1e-3
+        assert c["gamma"] == 4.5 and abs(c["gamma"] / c["gamma_s"] - c["ratio"]) < 1e-12
