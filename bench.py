@@ -7,6 +7,10 @@ steps, on the 4M-particle system (2M dimers in a 2000 x 2000 periodic box,
 synthetic random initial state).  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-steps S]
+
+With --workload sweep64 it instead times the batched parameter sweep: 64
+replicas of uneven size advanced together, against the same systems run one
+after another (prints one JSON line of its own).
 """
 from __future__ import annotations
 
@@ -86,6 +90,134 @@ def cpu_baseline(cfg, x, v, steps: int):
     }
 
 
+def run_sweep(args):
+    """The batched parameter sweep: 64 replicas of uneven size (2k-64k dimers,
+    log-uniform) over area fraction x (gamma / zeta), all advanced by one launch
+    per step kernel, against the same 64 systems run one after another."""
+    import numpy as np
+    import torch
+
+    from paper_1310_0998_amd import dpd, inputs
+
+    dev = torch.device("cuda:0")
+    cfgs = [inputs.physics(c) for c in inputs.sweep_replicas()]
+    states = [inputs.initial_state(c) for c in cfgs]
+    x = np.concatenate([s[0] for s in states])
+    v = np.concatenate([s[1] for s in states])
+    N = len(x)
+    steps = args.sweep_steps
+    K = args.graph_chunk
+    red_every = 100 if steps % 100 == 0 and 100 % K == 0 else 0
+    log(f"sweep: {len(cfgs)} replicas, N={N} particles, {steps} steps, graph chunk {K}")
+
+    def to_dev(a):
+        return torch.from_numpy(a).to(dev)
+
+    # batched: tuned schedule, captured chunks, one call
+    b = dpd.Sim(cfgs, device=dev)
+    b.set_state(to_dev(x), to_dev(v), 0)
+    tune = None
+    if not args.no_tune:
+        tune = b.autotune(10)
+        log(f"autotune: tile {tune[0]} x {tune[1]}, order {tune[2]}, {tune[3]:.4f} ms/step")
+    b.set_graph_chunk(K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pk = b.step(steps, reduce_every=red_every) if red_every else b.step(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.sync()
+    xb, vb, _, _ = b.get_state()
+    xb, vb = xb.cpu().numpy(), vb.cpu().numpy()
+    # pair-kernel time of the batch from a short eager run with events
+    b.set_graph_chunk(0)
+    b.set_profiling(True)
+    b.step(200)
+    pair_ms, launches = b.pair_kernel_time()
+    b.set_profiling(False)
+    n_cells = b.n_cells
+    b.close()
+    log(f"batched: {t_batch:.3f} s, {1e3 * t_batch / steps:.4f} ms/step")
+
+    # the same systems one after another (step loops only are timed)
+    seq = {}
+    equal = True
+    for mode in (() if args.no_sequential else ("eager", "graph")):
+        total = 0.0
+        for q, (c, (xs, vs)) in enumerate(zip(cfgs, states)):
+            s = dpd.Sim(c, device=dev)
+            s.set_state(to_dev(xs), to_dev(vs), 0)
+            if mode == "graph":
+                s.set_graph_chunk(K)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if red_every:
+                s.step(steps, reduce_every=red_every)
+            else:
+                s.step(steps)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+            if mode == "eager":
+                xq, vq, _, _ = s.get_state()
+                o = sum(len(t[0]) for t in states[:q])
+                equal &= bool((xq.cpu().numpy() == xb[o:o + len(xs)]).all()
+                              and (vq.cpu().numpy() == vb[o:o + len(xs)]).all())
+            s.close()
+        seq[mode] = total
+        log(f"sequential ({mode}): {total:.3f} s")
+
+    avg_us = 1e3 * pair_ms / max(launches, 1)
+    alg = pair_kernel_bytes(N, n_cells)
+    achieved = alg / (avg_us * 1e-6) / 1e9
+    rate = N * steps / t_batch
+    line = {
+        "metric": "batched sweep: particle-steps/s over 64 replicas in one launch per step kernel",
+        "value": rate,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": 1e3 * t_batch / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "sweep64: 64 replicas, dimer counts log-uniform in [2000, 64000] (seed 401), "
+                        "area fraction {0.2,0.4,0.6,0.8} x gamma/zeta {0.1,1,10,100} (4 replicas "
+                        "per point), gamma=4.5, L=sqrt(N_a/phi) r_c, a=25, kT=1, F_p=1, dt=0.005, "
+                        f"{steps} steps each from random positions at rest",
+            "n_particles": N,
+            "cells": n_cells,
+            "graph_chunk": K,
+            "schedule": None if tune is None else {"tile": [tune[0], tune[1]], "order": tune[2]},
+            "fp64_reduction_every": red_every,
+            "parallelism": "single-gpu",
+        },
+        "sequential": None if not seq else {
+            "eager_s": seq["eager"], "graph_s": seq["graph"],
+            "value_eager": N * steps / seq["eager"], "value_graph": N * steps / seq["graph"],
+        },
+        "speedup_vs_sequential": None if not seq else {
+            "eager": seq["eager"] / t_batch, "graph": seq["graph"] / t_batch},
+        "bitwise_equal_to_sequential": equal if seq else None,
+        "roofline": {
+            "kernel": "k_pair (batched)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": alg,
+            "avg_launch_us": avg_us,
+        },
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,11 +232,21 @@ def main():
                     help="Verlet skin (0: cell list rebuilt every step)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run a plain copy kernel of this many MiB (counter calibration)")
+    ap.add_argument("--sweep-steps", type=int, default=5000,
+                    help="steps of each replica (workload sweep64)")
+    ap.add_argument("--graph-chunk", type=int, default=50,
+                    help="steps per captured graph chunk (workload sweep64)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile schedule")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the one-after-another runs (workload sweep64)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the engine has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "sweep64":
+        run_sweep(args)
+        return
 
     import numpy as np
     import torch

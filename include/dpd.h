@@ -75,7 +75,9 @@ typedef struct dpd_params {
                             1: Philox2x32-10 on (min id, max id), key folds seed and step */
     int32_t  sp_split;   /* 0: f_sp/2 on head and tail; 1: f_sp on the head only      */
     int32_t  bin_M_max;  /* largest grid side dpd_bin_velocity will be asked for (0: 256) */
-    int32_t  tile;       /* pair-kernel tile side in cells, 1..8 (0: about 56 cells)   */
+    int32_t  tile;       /* pair-kernel tile side in cells, 1..8 (0: 8 x 7 cells at one
+                            particle per cell, the sides scaled by 1 / (particles per
+                            cell), or by its square root with a skin)                */
     float    skin;       /* Verlet skin (>= 0, in units of length).  0: the cell list
                             is rebuilt every step with cells of width >= r_c.  > 0:
                             cells are >= r_c + skin wide and a rebuild also stores,
@@ -189,17 +191,21 @@ int dpd_create_batch(const dpd_params* p, int32_t n_rep, void* workspace, size_t
 int dpd_set_graph_chunk(dpd_handle* h, int32_t steps);
 
 /* Pair-kernel schedule: tiles of tile_x x tile_y cells (1..8, clamped per
- * replica to n_c - 2; the workspace holds the tiles of any sides >= 4, or of
- * the sides the handle was made with if smaller) and the tile order (0: each
- * of the 8 XCDs takes a band of consecutive tiles; 1: launch order).  The
- * results do not depend on the schedule.  Not with a Verlet skin.
+ * replica to n_c - 2), or tile_x = tile_y = 0 for every replica's default
+ * tile (see dpd_params.tile), and the tile order (0: each of the 8 XCDs takes a
+ * band of consecutive tiles; 1: launch order).  The workspace holds the tiles
+ * of the schedules dpd_autotune tries and of the one the handle was made with;
+ * smaller tiles are refused.  The results do not depend on the schedule.
+ * dpd_get_schedule reports replica 0's tile.  Not with a Verlet skin.
  * Errors: DPD_EINVAL. */
 int dpd_set_schedule(dpd_handle* h, int32_t tile_x, int32_t tile_y, int32_t tile_order);
 int dpd_get_schedule(dpd_handle* h, int32_t* tile_x, int32_t* tile_y, int32_t* tile_order);
 
 /* Time trial_steps steps of the current state under each candidate schedule
- * (tile sides from 8 x 7 down to 4 x 4, both tile orders), keep the fastest
- * and restore the state exactly as it was (state, step, no prepared step).
+ * (every replica's default tile scaled by 1, 0.85, 0.7 and 0.55; the same
+ * 8 x 7, 8 x 8, 6 x 6 and 4 x 4 tiles for all; both tile orders), keep the
+ * fastest and restore the state exactly as it was (state, step, no prepared
+ * step).
  * Outputs (host, any may be NULL): the chosen schedule and its time per step
  * in ms.  Synchronises the stream.  Not with a Verlet skin.
  * Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP, device flags. */

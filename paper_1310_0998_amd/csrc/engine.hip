@@ -57,7 +57,6 @@ struct Derived {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr uint64_t kProfEvery = 8;  // pair launches per profiled launch
-constexpr int kTuneMinTile = 4;     // smallest tile side the tuner tries
 
 std::string fmt(const char* f, ...) {
     char buf[512];
@@ -83,10 +82,42 @@ void set_tiling(DevParams& P, int tx, int ty) {
     P.inv_ntx = 1.0 / (double)P.ntx;
 }
 
-long long tiles_of(const DevParams& P, int tx, int ty) {
-    DevParams Q = P;
-    set_tiling(Q, tx, ty);
-    return (long long)Q.ntx * Q.nty;
+// A tile schedule: the same tile sides for every replica (tx, ty >= 1), or
+// each replica's own default tile scaled by f (tx == 0); and the tile order.
+struct Sched {
+    int tx, ty;
+    double f;
+    int order;
+};
+
+// The schedules the tuner times.
+const Sched kCandidates[] = {
+    {0, 0, 1.0, 0}, {0, 0, 0.85, 0}, {0, 0, 0.7, 0}, {0, 0, 0.55, 0},
+    {8, 7, 0.0, 0}, {8, 8, 0.0, 0}, {6, 6, 0.0, 0}, {4, 4, 0.0, 0},
+};
+
+// Default tile of a system, scaled by f.  Without a skin the sides shrink as
+// 1 / (particles per cell): a tile then keeps about as many pairs as 8 x 7
+// cells at one particle per cell (the kept pairs of a tile grow as its
+// particles times the density, and must fit the pair list in LDS).  With a
+// skin they shrink as 1 / sqrt(particles per cell), which keeps the staged
+// particles (the records hold the pairs to r_c + skin).
+void default_tile(const dpd_params& p, const DevParams& P, double f, int* tx, int* ty) {
+    const double cell_n = std::max((double)P.N / ((double)P.nc * P.nc), 1.0 / 16.0);
+    const double sc = p.skin > 0.0f ? std::sqrt(cell_n) : cell_n;
+    *tx = std::max(1, std::min(kTileMax, (int)std::lround(kTileX * f / sc)));
+    *ty = std::max(1, std::min(kTileMax, (int)std::lround(kTileY * f / sc)));
+}
+
+void apply_tiling(Rep& r, const Sched& s) {
+    int tx = s.tx, ty = s.ty;
+    if (tx <= 0) default_tile(r.p, r.P, s.f, &tx, &ty);
+    set_tiling(r.P, tx, ty);
+}
+
+long long tiles_with(Rep r, const Sched& s) {
+    apply_tiling(r, s);
+    return (long long)r.P.ntx * r.P.nty;
 }
 
 // Validate the parameters of one system and derive its launch constants.
@@ -134,15 +165,9 @@ int derive_one(const dpd_params* p, DevParams& P, std::string* err) {
     P.N = (int)(2 * p->n_agents);
     P.nc = (int)ncd;
     P.n_cells = P.nc * P.nc;
-    // the default tile holds about 56 particles; with a skin the cells are wider
-    int tx = kTileX, ty = kTileY;
-    if (p->skin > 0.0f) {
-        const double cell_n = (2.0 * (double)p->n_agents) / ((double)ncd * ncd);  // particles per cell
-        const double sc = std::sqrt(std::max(cell_n, 1e-9));
-        tx = std::max(1, std::min(kTileMax, (int)std::lround(kTileX / sc)));
-        ty = std::max(1, std::min(kTileMax, (int)std::lround(kTileY / sc)));
-    }
-    set_tiling(P, p->tile ? p->tile : tx, p->tile ? p->tile : ty);
+    int tx = p->tile, ty = p->tile;
+    if (!p->tile) default_tile(*p, P, 1.0, &tx, &ty);
+    set_tiling(P, tx, ty);
     P.noise_kind = p->noise_kind;
     P.rng_kind = p->rng_kind;
     P.L = (float)p->L;
@@ -226,9 +251,11 @@ int derive(const dpd_params* p, int n_rep, Derived* d, std::string* err) {
     }
     // the per-tile arrays hold the tiles of any schedule the tuner may choose
     long long ta = 0;
-    for (const Rep& r : d->reps)
-        ta += std::max((long long)r.P.ntx * r.P.nty,
-                       tiles_of(r.P, std::min(r.P.tile_x, kTuneMinTile), std::min(r.P.tile_y, kTuneMinTile)));
+    for (const Rep& r : d->reps) {
+        long long t = (long long)r.P.ntx * r.P.nty;
+        for (const Sched& c : kCandidates) t = std::max(t, tiles_with(r, c));
+        ta += t;
+    }
     if (d->skin) ta = d->tiles;  // the skin keeps the tiling it was created with
     d->tiles_alloc = ta;
     d->n_scan_blocks = (int)((d->cells + kScanTile - 1) / kScanTile);
@@ -710,17 +737,23 @@ int copy_state(dpd_handle* h, bool save) {
     return DPD_OK;
 }
 
-// Apply a tile schedule to every replica (tile sides clamped per replica).
-int apply_schedule(dpd_handle* h, int tx, int ty, int order) {
-    Derived nd = h->d;
-    for (Rep& r : nd.reps) set_tiling(r.P, tx, ty);
+// The handle's replicas under schedule s (tile sides clamped per replica).
+Derived with_schedule(const Derived& d, const Sched& s) {
+    Derived nd = d;
+    for (Rep& r : nd.reps) apply_tiling(r, s);
     assign_offsets(&nd);
+    return nd;
+}
+
+// Apply a tile schedule to every replica.
+int apply_schedule(dpd_handle* h, const Sched& s) {
+    Derived nd = with_schedule(h->d, s);
     if (nd.tiles > h->d.tiles_alloc)
-        return fail(h, DPD_EINVAL, fmt("tile %d x %d needs %lld tiles, the workspace holds %lld", tx,
-                                       ty, nd.tiles, h->d.tiles_alloc));
+        return fail(h, DPD_EINVAL, fmt("tile %d x %d needs %lld tiles, the workspace holds %lld", s.tx,
+                                       s.ty, nd.tiles, h->d.tiles_alloc));
     drop_graphs(h);
     h->d = nd;
-    h->tile_order = order;
+    h->tile_order = s.order;
     return upload_tables(h);
 }
 
@@ -1212,11 +1245,12 @@ int dpd_set_graph_chunk(dpd_handle* h, int32_t steps) {
 int dpd_set_schedule(dpd_handle* h, int32_t tile_x, int32_t tile_y, int32_t tile_order) {
     if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
     if (h->d.skin) return fail(h, DPD_EINVAL, "the schedule of a Verlet-skin handle is fixed");
-    if (tile_x < 1 || tile_x > kTileMax || tile_y < 1 || tile_y > kTileMax)
-        return fail(h, DPD_EINVAL, fmt("tile sides must be in [1, %d]", kTileMax));
+    const bool dflt = tile_x == 0 && tile_y == 0;
+    if (!dflt && (tile_x < 1 || tile_x > kTileMax || tile_y < 1 || tile_y > kTileMax))
+        return fail(h, DPD_EINVAL, fmt("tile sides must be in [1, %d] (or both 0)", kTileMax));
     if (tile_order != 0 && tile_order != 1) return fail(h, DPD_EINVAL, "tile_order must be 0 or 1");
     try {
-        return apply_schedule(h, tile_x, tile_y, tile_order);
+        return apply_schedule(h, Sched{tile_x, tile_y, 1.0, tile_order});
     } catch (...) {
         return fail(h, DPD_EINVAL, "internal error");
     }
@@ -1237,7 +1271,6 @@ int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* t
     if (h->d.skin) return fail(h, DPD_EINVAL, "the schedule of a Verlet-skin handle is fixed");
     if (trial_steps < 1 || trial_steps > 100000) return fail(h, DPD_EINVAL, "trial_steps must be in [1, 100000]");
     try {
-        static const int cand[][2] = {{8, 7}, {8, 8}, {7, 7}, {7, 6}, {6, 6}, {8, 5}, {6, 5}, {5, 5}, {4, 4}};
         const bool prof = h->profiling;
         h->profiling = false;
         const int64_t step0 = h->step;
@@ -1247,21 +1280,22 @@ int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* t
         if (!rc && hipEventCreate(&e0) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventCreate failed");
         if (!rc && hipEventCreate(&e1) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventCreate failed");
         double best = 1e300;
-        int bx = P0(h).tile_x, by = P0(h).tile_y, bo = h->tile_order;
-        std::vector<long long> seen;
-        for (const auto& c : cand) {
+        Derived best_d = h->d;
+        int best_order = h->tile_order;
+        std::vector<std::vector<int>> seen;
+        for (const Sched& c0 : kCandidates) {
             for (int order = 0; order < 2 && !rc; ++order) {
-                // skip tilings that clamp to one already timed, and those that do
-                // not fit the per-tile arrays
-                Derived nd = h->d;
-                for (Rep& r : nd.reps) set_tiling(r.P, c[0], c[1]);
-                assign_offsets(&nd);
+                Sched c = c0;
+                c.order = order;
+                // skip schedules that give tilings already timed, and those that
+                // do not fit the per-tile arrays
+                Derived nd = with_schedule(h->d, c);
                 if (nd.tiles > h->d.tiles_alloc) continue;
-                long long sig = order;
-                for (const Rep& r : nd.reps) sig = sig * 1000003LL + r.P.tile_x * 16 + r.P.tile_y;
+                std::vector<int> sig{order};
+                for (const Rep& r : nd.reps) sig.push_back(r.P.tile_x * 16 + r.P.tile_y);
                 if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
                 seen.push_back(sig);
-                rc = apply_schedule(h, c[0], c[1], order);
+                rc = apply_schedule(h, c);
                 if (!rc) rc = copy_state(h, false);
                 if (rc) break;
                 h->step = step0;
@@ -1279,9 +1313,8 @@ int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* t
                 rc = unprepare(h);
                 if (!rc && ms < best) {
                     best = ms;
-                    bx = c[0];
-                    by = c[1];
-                    bo = order;
+                    best_d = h->d;
+                    best_order = order;
                 }
             }
             if (rc) break;
@@ -1291,14 +1324,17 @@ int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* t
         h->profiling = prof;
         if (rc) return rc;
         // the chosen schedule, and the state as it was
-        rc = apply_schedule(h, bx, by, bo);
+        drop_graphs(h);
+        h->d = best_d;
+        h->tile_order = best_order;
+        rc = upload_tables(h);
         if (!rc) rc = copy_state(h, false);
         if (rc) return rc;
         h->step = step0;
         h->prepared = false;
         if (tile_x) *tile_x = P0(h).tile_x;
         if (tile_y) *tile_y = P0(h).tile_y;
-        if (tile_order) *tile_order = bo;
+        if (tile_order) *tile_order = best_order;
         if (best_ms) *best_ms = best / trial_steps;
         return read_status(h);
     } catch (...) {

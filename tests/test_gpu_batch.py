@@ -37,13 +37,13 @@ def host(t):
 def replicas():
     """Five systems of uneven size, box, friction, seed and layout; the last
     one, at areal density 3 (softer repulsion, so that the random start does not
-    tear bonds), sends every tile to the overflow kernel."""
+    tear bonds) with 8 x 8 tiles, sends every tile to the overflow kernel."""
     cfgs = [
         dict(C1, n_agents=300, L=23.0, gamma_s=0.0, seed=11),
         dict(C1, n_agents=800, L=40.0, seed=12),
         dict(C1, n_agents=137, L=16.5, gamma=1.0, gamma_s=5.0, seed=13),
         dict(C1, n_agents=1500, L=47.0, gamma=20.0, gamma_s=0.5, seed=14, sp_split=1),
-        dict(C1, n_agents=800, L=23.0, A=5.0, seed=15),
+        dict(C1, n_agents=800, L=23.0, A=5.0, seed=15, tile=8),
     ]
     kinds = ["random", "edge", "random", "random", "random"]
     states = [inputs.initial_state(c, kind=k, thermal=True) for c, k in zip(cfgs, kinds)]
