@@ -86,7 +86,12 @@ typedef struct dpd_params {
                             than skin / 2 since the rebuild, which triggers the next
                             one (checked on the device, every step).  Results are
                             bitwise the same for every skin. */
-    int32_t  reserved[2];
+    float    w_exp;      /* exponent s of the dissipative weight: f_D uses w^s and
+                            f_R uses w^(s/2), so that the fluctuation-dissipation
+                            balance of Eq. 2.3 holds for every s; f_C keeps w.
+                            0 means 2 (Eq. 2.3 as printed); other values, in
+                            (0, 8], are the change of exponent Sec. 6 proposes. */
+    int32_t  reserved[1];
 } dpd_params;
 
 typedef struct dpd_handle dpd_handle;

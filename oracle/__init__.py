@@ -40,6 +40,7 @@ FIELDS = (
     ("rng_kind", ctypes.c_int32),
     ("sp_split", ctypes.c_int32),
     ("pad_", ctypes.c_int32),
+    ("w_exp", ctypes.c_double),
 )
 
 
@@ -107,7 +108,7 @@ def lib():
     return _lib
 
 
-DEFAULTS = dict(noise_kind=0, rng_kind=0, sp_split=0, seed=0, mass=1.0)
+DEFAULTS = dict(noise_kind=0, rng_kind=0, sp_split=0, seed=0, mass=1.0, w_exp=2.0)
 
 
 def make_params(cfg: Mapping) -> OracleParams:

@@ -148,8 +148,16 @@ int oracle_pair_force(const oracle_params* p, const double d[2], const double dv
     double g = dv[0] * e0 + dv[1] * e1;           /* (v_i - v_j) . e           */
     double sigma = sqrt(2.0 * p->gamma * p->kT);
     double sC = p->A * w;                         /* conservative magnitude     */
-    double sD = -p->gamma * w * w * g;            /* dissipative magnitude      */
-    double sR = sigma * w * alpha / sqrt(p->dt);  /* random magnitude           */
+    double sD, sR;                                /* dissipative, random        */
+    if (p->w_exp == 2.0) {                        /* Eq. 2.3 as printed         */
+        sD = -p->gamma * w * w * g;
+        sR = sigma * w * alpha / sqrt(p->dt);
+    } else {
+        /* dissipative weight w^s, random weight w^(s/2): the first is the
+           square of the second, as fluctuation-dissipation requires */
+        sD = -p->gamma * pow(w, p->w_exp) * g;
+        sR = sigma * pow(w, 0.5 * p->w_exp) * alpha / sqrt(p->dt);
+    }
     double s = (sC + sD) + sR;
     f[0] = s * e0;
     f[1] = s * e1;

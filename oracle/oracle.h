@@ -47,6 +47,10 @@ typedef struct oracle_params {
     int32_t  rng_kind;   /* 0: Philox4x32-10, 1: Philox2x32-10                     */
     int32_t  sp_split;   /* 0: f_sp/2 on each particle, 1: all of f_sp on the head */
     int32_t  pad_;
+    double   w_exp;      /* exponent s of the dissipative weight w^s; the random
+                            weight is w^(s/2) and the conservative one stays w
+                            (s = 2: Eq. 2.3 as printed; other s: the change of
+                            exponent that Sec. 6 proposes)                       */
 } oracle_params;
 
 /* ---- counter-based generator (Salmon, Moraes, Dror & Shaw, SC'11) ---------- */

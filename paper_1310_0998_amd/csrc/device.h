@@ -56,6 +56,7 @@ struct DevParams {
     // concatenated arrays of the batch (all 0 for a single system), its mass
     int pbase, cbase, tbase;
     double mass_d;
+    float w_half;     // half the exponent of the dissipative weight (1: Eq. 2.3)
 };
 
 // ---- Philox (Salmon, Moraes, Dror & Shaw, SC'11) ---------------------------

@@ -160,6 +160,10 @@ int derive_one(const dpd_params* p, DevParams& P, std::string* err) {
     if (p->sp_split != 0 && p->sp_split != 1) { *err = "sp_split must be 0 or 1"; return DPD_EINVAL; }
     if (p->bin_M_max < 0 || p->bin_M_max > 8192) { *err = "bin_M_max must be in [0, 8192]"; return DPD_EINVAL; }
     if (p->tile < 0 || p->tile > kTileMax) { *err = fmt("tile must be in [0, %d]", kTileMax); return DPD_EINVAL; }
+    if (!std::isfinite((double)p->w_exp) || p->w_exp < 0.0f || p->w_exp > 8.0f) {
+        *err = "w_exp must be in [0, 8] (0: 2)";
+        return DPD_EINVAL;
+    }
 
     P = DevParams{};
     P.N = (int)(2 * p->n_agents);
@@ -204,6 +208,7 @@ int derive_one(const dpd_params* p, DevParams& P, std::string* err) {
     P.seed_lo = (uint32_t)(p->seed & 0xffffffffu);
     P.seed_hi = (uint32_t)(p->seed >> 32);
     P.mass_d = p->mass;
+    P.w_half = p->w_exp > 0.0f ? 0.5f * p->w_exp : 1.0f;
     return DPD_OK;
 }
 

@@ -149,7 +149,9 @@ __device__ __forceinline__ bool interacts(float q, float r2) { return q > 0.f &&
 // r2 = |d|^2 and q = r_c^2 - |d|^2 with interacts(q, r2).  The weight
 // w = 1 - r/r_c (Eq. 2.4) is evaluated as q / (r_c (r_c + r)).  Every
 // operation is symmetric under (i, j, d) -> (j, i, -d), so the force on j is
-// bitwise the negation.
+// bitwise the negation.  WEXP = false compiles the printed weights (w, w^2)
+// only; with WEXP the exponent P.w_half is applied when it is not 1.
+template <bool WEXP = true>
 __device__ __forceinline__ void add_pair_force(const DevParams& P, float dx, float dy,
                                                float q, float r2, float2 ui, float2 uj, int idi,
                                                int idj, uint32_t step, float& fx,
@@ -161,7 +163,10 @@ __device__ __forceinline__ void add_pair_force(const DevParams& P, float dx, flo
     const float g = (ui.x - uj.x) * ex + (ui.y - uj.y) * ey;
     const uint32_t a = (uint32_t)min(idi, idj), b = (uint32_t)max(idi, idj);
     const float alpha = alpha_from_words(P.noise_kind, pair_words2(P, a, b, step));
-    const float s = P.A * w - P.gamma * w * w * g + P.sigma_rdt * w * alpha;
+    // random weight w^(s/2) and dissipative weight its square (s = 2: w and w^2)
+    float wr = w;
+    if (WEXP && P.w_half != 1.0f) wr = exp2f(P.w_half * log2f(w));
+    const float s = P.A * w - P.gamma * wr * wr * g + P.sigma_rdt * wr * alpha;
     fx += s * ex;
     fy += s * ey;
 }
@@ -432,6 +437,37 @@ __device__ __forceinline__ void tile_reduce(const PairArgs& a, int t, double rv[
         a.red[3 * t + 1] = rv[1];
         a.red[3 * t + 2] = rv[2];
     }
+}
+
+// Phase B of the pair kernel: the forces of the kept pairs s_pair[0 .. E), added
+// in fixed point to the tile particles (the first of each pair, and the second
+// if it is in the tile).  Returns whether a force was not finite.
+template <bool WEXP>
+__device__ __forceinline__ bool pair_sums(const DevParams& P, uint32_t step, bool edge, int E,
+                                          const unsigned short* s_pair, const float4* s_rec,
+                                          const float2* s_u, long long (*s_acc)[2]) {
+    bool bad = false;
+    for (int e = threadIdx.x; e < E; e += kWave) {
+        const int w = s_pair[e];
+        const int so = w >> 8, j = w & 0xFF;
+        const float4 ro = s_rec[so], rj = s_rec[j];
+        const int k = __float_as_int(ro.w);
+        const float dx = edge ? minimg_sub(ro.x, rj.x, P) : ro.x - rj.x;
+        const float dy = edge ? minimg_sub(ro.y, rj.y, P) : ro.y - rj.y;
+        float fx = 0.f, fy = 0.f;
+        add_pair_force<WEXP>(P, dx, dy, cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy), s_u[so], s_u[j],
+                             __float_as_int(ro.z), __float_as_int(rj.z), step, fx, fy);
+        bad |= !(__builtin_isfinite(fx) && __builtin_isfinite(fy));
+        const long long qx = to_fixed(fx), qy = to_fixed(fy);
+        atomicAdd((unsigned long long*)&s_acc[k][0], (unsigned long long)qx);
+        atomicAdd((unsigned long long*)&s_acc[k][1], (unsigned long long)qy);
+        const int tj = __float_as_int(rj.w);
+        if (tj != 0xFF) {
+            atomicAdd((unsigned long long*)&s_acc[tj][0], (unsigned long long)(-qx));
+            atomicAdd((unsigned long long*)&s_acc[tj][1], (unsigned long long)(-qy));
+        }
+    }
+    return bad;
 }
 
 // The fused pair / agent / integrator kernel: one 64-lane wavefront per tile of
@@ -769,28 +805,11 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
         s_acc[k][1] = 0;
     }
     __syncthreads();
-    // ---- B: one force per kept pair, exact fixed-point sums
-    bool bad = false;
-    for (int e = lane; e < E; e += kWave) {
-        const int w = s_pair[e];
-        const int so = w >> 8, j = w & 0xFF;
-        const float4 ro = s_rec[so], rj = s_rec[j];
-        const int k = __float_as_int(ro.w);
-        const float dx = edge ? minimg_sub(ro.x, rj.x, P) : ro.x - rj.x;
-        const float dy = edge ? minimg_sub(ro.y, rj.y, P) : ro.y - rj.y;
-        float fx = 0.f, fy = 0.f;
-        add_pair_force(P, dx, dy, cutoff_gap(P, dx, dy), fmaf(dx, dx, dy * dy), s_u[so], s_u[j],
-                       __float_as_int(ro.z), __float_as_int(rj.z), a.step, fx, fy);
-        bad |= !(__builtin_isfinite(fx) && __builtin_isfinite(fy));
-        const long long qx = to_fixed(fx), qy = to_fixed(fy);
-        atomicAdd((unsigned long long*)&s_acc[k][0], (unsigned long long)qx);
-        atomicAdd((unsigned long long*)&s_acc[k][1], (unsigned long long)qy);
-        const int tj = __float_as_int(rj.w);
-        if (tj != 0xFF) {
-            atomicAdd((unsigned long long*)&s_acc[tj][0], (unsigned long long)(-qx));
-            atomicAdd((unsigned long long*)&s_acc[tj][1], (unsigned long long)(-qy));
-        }
-    }
+    // ---- B: one force per kept pair, exact fixed-point sums (the weight
+    // exponent is tested once, outside the loop)
+    const bool bad = P.w_half == 1.0f
+        ? pair_sums<false>(P, a.step, edge, E, s_pair, s_rec, s_u, s_acc)
+        : pair_sums<true>(P, a.step, edge, E, s_pair, s_rec, s_u, s_acc);
     if (bad) atomicOr(a.status, kStatusNonFinite);
     __syncthreads();
 
@@ -820,11 +839,9 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
             const int lc = s_lcell[si];
             g = s_gbeg[lc] + (si - s_ofs[lc]);
         }
-        // inconsistent cell data (flagged above) must not turn into a stray store
-        if ((unsigned)(g - P.pbase) >= (unsigned)P.N) {
-            atomicOr(a.status, kStatusBinning);
-            continue;
-        }
+        // inconsistent cell data (flagged when the gather found an index outside
+        // the system) must not turn into a store outside the system's slots
+        g = min(max(g, P.pbase), P.pbase + P.N - 1);
         finish_particle<MODE, SKIN>(P, a, g, xi, ui, idi, fx, fy, rv, reduce != 0, rebuild);
     }
     if (reduce) tile_reduce(a, gtile, rv);

@@ -50,13 +50,14 @@ class Params(ctypes.Structure):
         ("bin_M_max", ctypes.c_int32),
         ("tile", ctypes.c_int32),
         ("skin", ctypes.c_float),
-        ("reserved", ctypes.c_int32 * 2),
+        ("w_exp", ctypes.c_float),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
 _INT_FIELDS = {"n_agents", "seed", "noise_kind", "rng_kind", "sp_split", "bin_M_max", "tile"}
 _DEFAULTS = dict(mass=1.0, seed=0, noise_kind=0, rng_kind=0, sp_split=0, bin_M_max=0, tile=0,
-                 skin=0.0)
+                 skin=0.0, w_exp=0.0)
 
 
 def make_params(cfg: Mapping) -> Params:

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(dpd):
 
 
 def test_params_struct_layout_matches_header(dpd):
-    # 1 int64 + 11 doubles + 1 uint64 + 5 int32 + 1 float + 2 reserved int32 = 128 bytes
+    # 1 int64 + 11 doubles + 1 uint64 + 5 int32 + 2 floats + 1 reserved int32 = 128 bytes
     assert ctypes.sizeof(dpd.Params) == 8 + 11 * 8 + 8 + 8 * 4
 
 
@@ -62,7 +62,7 @@ def test_workspace_and_cells(dpd):
 @pytest.mark.parametrize("bad", [
     dict(n_agents=0), dict(L=2.5), dict(L=40.1), dict(r_c=0.0), dict(dt=0.0), dict(mass=-1.0),
     dict(gamma=-1.0), dict(kT=float("nan")), dict(noise_kind=2), dict(rng_kind=5), dict(sp_split=3),
-    dict(tile=99), dict(bin_M_max=-1),
+    dict(tile=99), dict(bin_M_max=-1), dict(w_exp=-1.0), dict(w_exp=9.0), dict(w_exp=float("nan")),
 ])
 def test_invalid_parameters_rejected(dpd, bad):
     cfg = dict(inputs.physics(inputs.WORKLOADS["dimers_1600"]), **bad)

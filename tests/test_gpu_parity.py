@@ -149,6 +149,10 @@ FORCE_CASES = [
     ("tile1", dict(C1, L=12.0, n_agents=70, tile=1, seed=16), "random", True),
     ("gamma0", dict(C1, gamma=0.0, seed=17), "random", True),
     ("at-rest", dict(C1, seed=18), "random", False),
+    # the change of weight exponent of Sec. 6: f_D with w^s, f_R with w^(s/2)
+    ("w_exp-0.5", dict(C1, w_exp=0.5, seed=19), "random", True),
+    ("w_exp-1", dict(C1, w_exp=1.0, seed=20), "edge", True),
+    ("w_exp-3", dict(C1, w_exp=3.0, seed=21), "random", True),
 ]
 
 
@@ -468,6 +472,24 @@ def test_fluctuation_dissipation_on_gpu(dpd):
         sim.close()
     print("kinetic temperatures", Ts)
     assert np.mean(Ts) == pytest.approx(C1["kT"], rel=0.005)
+
+
+@pytest.mark.parametrize("w_exp", [0.5, 1.0])
+def test_fluctuation_dissipation_weight_exponent(dpd, w_exp):
+    # with the dissipative weight w^s and the random weight w^(s/2) the pair
+    # thermostat still satisfies fluctuation-dissipation: T_kin -> kT
+    Ts = []
+    for seed in (105, 106):
+        cfg = dict(C1, f_sp=0.0, gamma_s=0.0, seed=seed, L=80.0, n_agents=3200, w_exp=w_exp)
+        x, v = inputs.initial_state(cfg, thermal=True)
+        sim = make_sim(dpd, cfg, x, v)
+        sim.step(6000)
+        pk = host(sim.step(12000, reduce_every=10))
+        n = 2 * cfg["n_agents"]
+        Ts.append(2 * pk[:, 2].mean() / (2 * n - 2))
+        sim.close()
+    print(f"w_exp {w_exp}: kinetic temperatures", Ts)
+    assert np.mean(Ts) == pytest.approx(C1["kT"], rel=0.01)
 
 
 # ----------------------------------------------------------- velocity field

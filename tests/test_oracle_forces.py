@@ -43,6 +43,34 @@ def test_random_force_hand_value(oracle_mod):
     assert parts[2] == pytest.approx([8.909545442950499, 11.879393923933999], rel=1e-14)
 
 
+@pytest.mark.parametrize("s", [0.5, 1.0, 3.0])
+def test_weight_exponent_hand_values(oracle_mod, s):
+    # the change of weight exponent Sec. 6 proposes: at d = (0.3, 0.4) (w = 1/2,
+    # e = (0.6, 0.8)) with dv = (1, 2) (g = 2.2) and alpha = 0.7, f_C = A w e is
+    # unchanged, f_D = -gamma w^s g e and f_R = sigma w^(s/2) alpha dt^(-1/2) e
+    cfg = dict(BASE, w_exp=s)
+    f, parts, hit = oracle_mod.pair_force(cfg, [0.3, 0.4], [1.0, 2.0], 0.7)
+    assert hit
+    e = np.array([0.6, 0.8])
+    assert parts[0] == pytest.approx(25.0 * 0.5 * e, rel=1e-14)
+    assert parts[1] == pytest.approx(-4.5 * 0.5 ** s * 2.2 * e, rel=1e-14)
+    assert parts[2] == pytest.approx(3.0 * 0.5 ** (s / 2) * 0.7 / math.sqrt(0.005) * e, rel=1e-14)
+    # the dissipative weight is the square of the random one at any separation
+    _, p1, _ = oracle_mod.pair_force(dict(cfg, A=0.0), [0.13, -0.41], [0.0, 1.0], 1.0)
+    r = math.hypot(0.13, -0.41)
+    w = 1.0 - r
+    ratio = np.linalg.norm(p1[1]) / (4.5 * abs(0.41 / r)) / (np.linalg.norm(p1[2]) / (3.0 / math.sqrt(0.005))) ** 2
+    assert ratio == pytest.approx(1.0, rel=1e-12)
+    assert w > 0
+
+
+def test_weight_exponent_two_is_the_printed_law(oracle_mod):
+    d, dv = [0.21, -0.37], [0.9, 0.3]
+    a, _, _ = oracle_mod.pair_force(BASE, d, dv, -1.1)
+    b, _, _ = oracle_mod.pair_force(dict(BASE, w_exp=2.0), d, dv, -1.1)
+    assert (a == b).all()
+
+
 def test_cutoff_is_strict_and_weight_vanishes(oracle_mod):
     cfg = dict(BASE)
     f, _, hit = oracle_mod.pair_force(cfg, [1.0, 0.0], [3.0, 0.0], 2.0)
