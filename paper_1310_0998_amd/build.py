@@ -9,9 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpd.so")
-SOURCES = [os.path.join(CSRC, "engine.hip")]
+SOURCES = [os.path.join(CSRC, "engine.hip"), os.path.join(CSRC, "closure.hip")]
 DEPENDS = SOURCES + [os.path.join(CSRC, f) for f in ("device.h", "kernels.h")] + [
-    os.path.join(ROOT, "include", "dpd.h")]
+    os.path.join(ROOT, "include", "dpd.h"), os.path.join(ROOT, "include", "closure.h")]
 
 
 def hipcc() -> str:

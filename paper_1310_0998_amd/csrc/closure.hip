@@ -1,0 +1,744 @@
+// closure.hip -- the learned closure of include/closure.h: a periodic
+// convolutional network on the binned velocity field (Sec. 5.4), its training
+// kernels (forward, loss, input and weight gradients, Adam) and its rollout.
+//
+// Layout: every field is NHWC ([pixel][channel], pixel = (b M + j) M + i).
+// Convolution l maps c_in(l) channels to c_out(l): 3 x 3 taps with periodic
+// wrap, weights W_l[tap][c][o] (FP32 master), bias b_l[o].
+//
+// Forward and input-gradient convolutions are implicit GEMMs on the matrix
+// cores: one 64-lane wavefront computes 16 pixels x 16 output channels per
+// v_mfma_f32_16x16x16_bf16 accumulator, running over K = 9 c_in in chunks of
+// 16 (4 per lane: 4 consecutive channels of one tap, one 8-byte load).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/closure.h"
+#include "../../include/dpd.h"
+#include "device.h"
+
+namespace nn {
+
+constexpr int kWaveN = 64;
+constexpr int kThreads = 256;      // 4 wavefronts per block
+constexpr int kWgPix = 256;        // pixels per block of the weight-gradient sums
+constexpr int kWgStage = 8;        // pixels staged in LDS at a time
+constexpr int kMaxC = 32;          // largest channel count
+constexpr int kWgOutMax = 9 * kMaxC * kMaxC + kMaxC;  // weights + biases of one layer
+constexpr int kWgPerThread = (kWgOutMax + kThreads - 1) / kThreads;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(unsigned short h) {
+    return __uint_as_float((unsigned)h << 16);
+}
+
+// One convolution's shapes.
+struct Conv {
+    int cin, cout;      // channels in, out
+    int K, Kpad;        // 9 cin, rounded up to 16
+    int cout16;         // cout rounded up to 16 (output-channel tiles)
+    int cout4;          // cout rounded up to 4 (channels of the BF16 output gradient)
+    int Kb, Kbpad;      // 9 cout4, rounded up to 16
+    int cin16;          // cin rounded up to 16
+};
+
+// ---- parameters -----------------------------------------------------------------
+
+// Master W[tap][c][o] -> Wf[o][tap cin + c] (forward B operand, rows padded to
+// cout16 and Kpad) and Wb[c][tap cout4 + o] (input-gradient B operand).
+__global__ void k_cast_weights(Conv cv, const float* __restrict__ W, unsigned short* Wf,
+                               unsigned short* Wb) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nf = cv.cout16 * cv.Kpad;
+    if (t < nf) {
+        const int o = t / cv.Kpad, k = t % cv.Kpad;
+        float w = 0.f;
+        if (o < cv.cout && k < cv.K) w = W[k * cv.cout + o];  // k = tap cin + c
+        Wf[t] = to_bf16(w);
+    }
+    const int nb = cv.cin16 * cv.Kbpad;
+    if (Wb && t < nb) {
+        const int c = t / cv.Kbpad, k = t % cv.Kbpad;
+        float w = 0.f;
+        if (c < cv.cin && k < cv.Kb) {
+            const int tap = k / cv.cout4, o = k % cv.cout4;
+            if (o < cv.cout) w = W[(tap * cv.cin + c) * cv.cout + o];
+        }
+        Wb[t] = to_bf16(w);
+    }
+}
+
+// ---- forward ---------------------------------------------------------------------
+
+// First activation: (u_x, u_y, conditions...) rounded to BF16.
+__global__ void k_input(int npix, int M2, int cin, const float* __restrict__ u,
+                        const float* __restrict__ cond, unsigned short* X) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const int b = p / M2;
+    X[(size_t)p * cin + 0] = to_bf16(u[2 * (size_t)p + 0]);
+    X[(size_t)p * cin + 1] = to_bf16(u[2 * (size_t)p + 1]);
+    for (int c = 2; c < cin; ++c) X[(size_t)p * cin + c] = to_bf16(cond[(size_t)b * (cin - 2) + c - 2]);
+}
+
+// Pixel index of (pixel p, tap) shifted by +(dx, dy) (sign = 1) or -(dx, dy)
+// (sign = -1) with periodic wrap.
+__device__ __forceinline__ int shifted(int p, int tap, int sign, int M) {
+    const int M2 = M * M;
+    const int b = p / M2, r = p - b * M2;
+    const int y = r / M, x = r - y * M;
+    const int dy = sign * (tap / 3 - 1), dx = sign * (tap % 3 - 1);
+    int ny = y + dy, nx = x + dx;
+    ny += (ny < 0) ? M : 0;
+    ny -= (ny >= M) ? M : 0;
+    nx += (nx < 0) ? M : 0;
+    nx -= (nx >= M) ? M : 0;
+    return b * M2 + ny * M + nx;
+}
+
+// Z = conv(X, W) + b on 16-pixel tiles, one wavefront each.  Hidden layers
+// write relu(Z) in BF16 (the next activation); the last writes pred = u + Z.
+template <bool LAST>
+__global__ __launch_bounds__(kThreads) void k_conv_fwd(Conv cv, int M, int npix,
+                                                        const unsigned short* __restrict__ X,
+                                                        const unsigned short* __restrict__ Wf,
+                                                        const float* __restrict__ bias,
+                                                        unsigned short* Xnext,
+                                                        const float* __restrict__ u, float* pred) {
+    const int tile = blockIdx.x * (kThreads / kWaveN) + threadIdx.x / kWaveN;
+    if (tile * 16 >= npix) return;
+    const int lane = threadIdx.x & (kWaveN - 1), r16 = lane & 15, g = lane >> 4;
+    const int pa = tile * 16 + r16;  // pixel of this lane's A row
+    const int nct = cv.cout16 / 16;  // 1 or 2
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < cv.Kpad; k0 += 16) {
+        const int k = k0 + 4 * g;
+        bf16x4 a = {0, 0, 0, 0};
+        if (k < cv.K) {
+            const int tap = k / cv.cin, c = k - tap * cv.cin;
+            const int q = shifted(pa, tap, 1, M);
+            a = *reinterpret_cast<const bf16x4*>(X + (size_t)q * cv.cin + c);
+        }
+        const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(Wf + (size_t)r16 * cv.Kpad + k);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b0, acc0, 0, 0, 0);
+        if (nct > 1) {
+            const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(Wf + (size_t)(16 + r16) * cv.Kpad + k);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b1, acc1, 0, 0, 0);
+        }
+    }
+    // D[row 4 g + i][column r16]: pixel tile 16 + 4 g + i, channel ct 16 + r16
+    for (int ct = 0; ct < nct; ++ct) {
+        const int o = ct * 16 + r16;
+        if (o >= cv.cout) continue;
+        const f32x4 acc = ct == 0 ? acc0 : acc1;
+        const float bo = bias[o];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = tile * 16 + 4 * g + i;
+            const float z = acc[i] + bo;
+            if (LAST)
+                pred[2 * (size_t)p + o] = u[2 * (size_t)p + o] + z;
+            else
+                Xnext[(size_t)p * cv.cout + o] = to_bf16(fmaxf(z, 0.f));
+        }
+    }
+}
+
+// ---- loss --------------------------------------------------------------------------
+
+// d = pred - target; loss partials sum d^2 (FP64, per block); the gradient of
+// the mean, 2 d / n, in FP32 ([p][2]) and BF16 ([p][4], channels 2, 3 zero).
+__global__ __launch_bounds__(kThreads) void k_loss(int npix, const float* __restrict__ pred,
+                                                    const float* __restrict__ target, float inv_n2,
+                                                    float* dZ, unsigned short* dZb, double* part) {
+    __shared__ double s[kThreads / kWaveN];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (p < npix) {
+        const float d0 = pred[2 * (size_t)p] - target[2 * (size_t)p];
+        const float d1 = pred[2 * (size_t)p + 1] - target[2 * (size_t)p + 1];
+        e = (double)d0 * d0 + (double)d1 * d1;
+        const float g0 = inv_n2 * d0, g1 = inv_n2 * d1;
+        dZ[2 * (size_t)p] = g0;
+        dZ[2 * (size_t)p + 1] = g1;
+        dZb[4 * (size_t)p + 0] = to_bf16(g0);
+        dZb[4 * (size_t)p + 1] = to_bf16(g1);
+        dZb[4 * (size_t)p + 2] = 0;
+        dZb[4 * (size_t)p + 3] = 0;
+    }
+    for (int o = kWaveN / 2; o > 0; o >>= 1) e += __shfl_down(e, o, kWaveN);
+    if ((threadIdx.x & (kWaveN - 1)) == 0) s[threadIdx.x / kWaveN] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((s[0] + s[1]) + s[2]) + s[3];
+}
+
+__global__ __launch_bounds__(kThreads) void k_loss_final(int nparts, const double* __restrict__ part,
+                                                          double inv_n, double* loss) {
+    __shared__ double s[kThreads];
+    double e = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kThreads) e += part[k];
+    s[threadIdx.x] = e;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss) *loss = s[0] * inv_n;
+}
+
+// ---- input gradient ------------------------------------------------------------
+
+// dX[q][c] = sum_{tap, o} dZ[q - off(tap)][o] W[tap][c][o] on the matrix cores,
+// then through the ReLU of the layer below: dZ_below = dX where X[q][c] > 0
+// (X is this layer's input, the ReLU output below), in FP32 and BF16.
+__global__ __launch_bounds__(kThreads) void k_conv_bwd(Conv cv, int M, int npix,
+                                                        const unsigned short* __restrict__ dZb,
+                                                        const unsigned short* __restrict__ Wb,
+                                                        const unsigned short* __restrict__ X,
+                                                        float* dZprev, unsigned short* dZprevb) {
+    const int tile = blockIdx.x * (kThreads / kWaveN) + threadIdx.x / kWaveN;
+    if (tile * 16 >= npix) return;
+    const int lane = threadIdx.x & (kWaveN - 1), r16 = lane & 15, g = lane >> 4;
+    const int qa = tile * 16 + r16;
+    const int nct = cv.cin16 / 16;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < cv.Kbpad; k0 += 16) {
+        const int k = k0 + 4 * g;
+        bf16x4 a = {0, 0, 0, 0};
+        if (k < cv.Kb) {
+            const int tap = k / cv.cout4, o = k - tap * cv.cout4;
+            const int p = shifted(qa, tap, -1, M);
+            a = *reinterpret_cast<const bf16x4*>(dZb + (size_t)p * cv.cout4 + o);
+        }
+        const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(Wb + (size_t)r16 * cv.Kbpad + k);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b0, acc0, 0, 0, 0);
+        if (nct > 1) {
+            const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(Wb + (size_t)(16 + r16) * cv.Kbpad + k);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b1, acc1, 0, 0, 0);
+        }
+    }
+    for (int ct = 0; ct < nct; ++ct) {
+        const int c = ct * 16 + r16;
+        if (c >= cv.cin) continue;
+        const f32x4 acc = ct == 0 ? acc0 : acc1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = tile * 16 + 4 * g + i;
+            const bool on = from_bf16(X[(size_t)q * cv.cin + c]) > 0.f;
+            const float d = on ? acc[i] : 0.f;
+            dZprev[(size_t)q * cv.cin + c] = d;
+            dZprevb[(size_t)q * cv.cin + c] = to_bf16(d);
+        }
+    }
+}
+
+// ---- weight gradient -----------------------------------------------------------
+
+// Per block of kWgPix pixels: part[block][o] = sum_p X[p + off(tap)][c] dZ[p][o']
+// for o = (tap cin + c) cout + o' (the layout of W), then the bias sums
+// sum_p dZ[p][o'] at o = 9 cin cout + o'.  Pixels are taken in order, so the
+// sums are reproducible.
+__global__ __launch_bounds__(kThreads) void k_wgrad_part(Conv cv, int M, int npix,
+                                                          const unsigned short* __restrict__ X,
+                                                          const float* __restrict__ dZ,
+                                                          float* part) {
+    __shared__ float xs[kWgStage][9 * kMaxC];
+    __shared__ float zs[kWgStage][kMaxC];
+    const int nW = cv.K * cv.cout, nO = nW + cv.cout;
+    float acc[kWgPerThread];
+#pragma unroll
+    for (int j = 0; j < kWgPerThread; ++j) acc[j] = 0.f;
+    const int p0 = blockIdx.x * kWgPix;
+    const int p1 = min(npix, p0 + kWgPix);
+    for (int pb = p0; pb < p1; pb += kWgStage) {
+        const int np = min(kWgStage, p1 - pb);
+        for (int t = threadIdx.x; t < np * cv.K; t += kThreads) {
+            const int pp = t / cv.K, k = t - pp * cv.K;
+            const int tap = k / cv.cin, c = k - tap * cv.cin;
+            xs[pp][k] = from_bf16(X[(size_t)shifted(pb + pp, tap, 1, M) * cv.cin + c]);
+        }
+        for (int t = threadIdx.x; t < np * cv.cout; t += kThreads) {
+            const int pp = t / cv.cout, o = t - pp * cv.cout;
+            zs[pp][o] = dZ[(size_t)(pb + pp) * cv.cout + o];
+        }
+        __syncthreads();
+        for (int pp = 0; pp < np; ++pp) {
+#pragma unroll
+            for (int j = 0; j < kWgPerThread; ++j) {
+                const int o = threadIdx.x + j * kThreads;
+                if (o < nW) {
+                    const int k = o / cv.cout, oo = o - k * cv.cout;
+                    acc[j] = fmaf(xs[pp][k], zs[pp][oo], acc[j]);
+                } else if (o < nO) {
+                    acc[j] += zs[pp][o - nW];
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < kWgPerThread; ++j) {
+        const int o = threadIdx.x + j * kThreads;
+        if (o < nO) part[(size_t)blockIdx.x * nO + o] = acc[j];
+    }
+}
+
+// grad[o] = sum over the blocks in order of part[block][o].
+__global__ void k_wgrad_reduce(int nO, int nblocks, const float* __restrict__ part, float* grad) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nO) return;
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * nO + o];
+    grad[o] = s;
+}
+
+// ---- optimiser and rollout -----------------------------------------------------
+
+__global__ void k_adam(int n, float* w, float* m, float* v, const float* __restrict__ g, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// u_next = pred + sigma_c alpha, alpha Gaussian by Box-Muller from
+// Philox4x32-10 with counter (point, component, step, 0) and the seed as key.
+__global__ void k_noise(int n, const float* __restrict__ pred, float s0, float s1, uint32_t step,
+                        uint32_t k0, uint32_t k1, float* unext) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;  // t = 2 point + component
+    if (t >= n) return;
+    const uint4 w = dpd::philox4x32_10(make_uint4((uint32_t)(t >> 1), (uint32_t)(t & 1), step, 0u), k0, k1);
+    const float alpha = dpd::alpha_from_words(0, make_uint2(w.x, w.y));
+    unext[t] = pred[t] + ((t & 1) ? s1 : s0) * alpha;
+}
+
+__global__ void k_zero(float* p, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+}  // namespace nn
+
+// ======================================================================= host
+
+namespace {
+
+using namespace nn;
+
+thread_local std::string g_nn_error = "no error";
+
+std::string nfmt(const char* f, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, f);
+    vsnprintf(buf, sizeof buf, f, ap);
+    va_end(ap);
+    return buf;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+int up(int x, int m) { return (x + m - 1) / m * m; }
+int blocks(long long n, int b = kThreads) { return (int)((n + b - 1) / b); }
+
+struct Net {
+    dpd_nn_params p;
+    std::vector<Conv> conv;
+    std::vector<size_t> woff, boff;  // parameter offsets of W_l and b_l
+    long long nparam = 0;
+    size_t total = 0;
+    // workspace offsets
+    size_t o_w, o_m, o_v, o_g, o_pred, o_dz[2], o_dzb[2], o_part, o_lpart, o_loss, o_u, o_cond;
+    std::vector<size_t> o_x, o_wf, o_wb;
+};
+
+int plan(const dpd_nn_params* p, Net* n, std::string* err) {
+    if (!p) { *err = "params is NULL"; return DPD_EINVAL; }
+    if (p->M < 4 || p->M > 256 || p->M % 4) { *err = "M must be a multiple of 4 in [4, 256]"; return DPD_EINVAL; }
+    if (p->c_in < 4 || p->c_in > kMaxC || p->c_in % 4) { *err = "c_in must be a multiple of 4 in [4, 32]"; return DPD_EINVAL; }
+    if (p->width != 16 && p->width != 32) { *err = "width must be 16 or 32"; return DPD_EINVAL; }
+    if (p->layers < 1 || p->layers > 8) { *err = "layers must be in [1, 8]"; return DPD_EINVAL; }
+    if (p->max_batch < 1 || (long long)p->max_batch * p->M * p->M > (1LL << 26)) {
+        *err = "max_batch must be >= 1 with max_batch M^2 <= 2^26";
+        return DPD_EINVAL;
+    }
+    n->p = *p;
+    n->conv.clear();
+    n->woff.clear();
+    n->boff.clear();
+    long long off = 0;
+    for (int l = 0; l < p->layers; ++l) {
+        Conv c;
+        c.cin = l == 0 ? p->c_in : p->width;
+        c.cout = l == p->layers - 1 ? 2 : p->width;
+        c.K = 9 * c.cin;
+        c.Kpad = up(c.K, 16);
+        c.cout16 = up(c.cout, 16);
+        c.cout4 = up(c.cout, 4);
+        c.Kb = 9 * c.cout4;
+        c.Kbpad = up(c.Kb, 16);
+        c.cin16 = up(c.cin, 16);
+        n->conv.push_back(c);
+        n->woff.push_back((size_t)off);
+        off += (long long)c.K * c.cout;
+        n->boff.push_back((size_t)off);
+        off += c.cout;
+    }
+    n->nparam = off;
+    const size_t npix = (size_t)p->max_batch * p->M * p->M;
+    const size_t P = (size_t)off;
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o = al256(o + b); return r; };
+    n->o_w = take(P * 4);
+    n->o_m = take(P * 4);
+    n->o_v = take(P * 4);
+    n->o_g = take(P * 4);
+    n->o_pred = take(npix * 2 * 4);
+    const int cmax = std::max(p->width, 4);
+    for (int k = 0; k < 2; ++k) {
+        n->o_dz[k] = take(npix * cmax * 4);
+        n->o_dzb[k] = take(npix * cmax * 2);
+    }
+    const size_t nwb = (npix + kWgPix - 1) / kWgPix;
+    n->o_part = take(nwb * kWgOutMax * 4);
+    n->o_lpart = take(((npix + kThreads - 1) / kThreads) * 8);
+    n->o_loss = take(8);
+    n->o_u = take((size_t)p->M * p->M * 2 * 4 * 2);  // rollout field and its prediction
+    n->o_cond = take(kMaxC * 4);
+    n->o_x.clear();
+    n->o_wf.clear();
+    n->o_wb.clear();
+    for (const Conv& c : n->conv) {
+        n->o_x.push_back(take(npix * c.cin * 2));
+        n->o_wf.push_back(take((size_t)c.cout16 * c.Kpad * 2));
+        n->o_wb.push_back(take((size_t)c.cin16 * c.Kbpad * 2));
+    }
+    n->total = o;
+    return DPD_OK;
+}
+
+}  // namespace
+
+struct dpd_nn {
+    Net net;
+    hipStream_t stream;
+    char* ws;
+    int adam_t;
+    std::string err;
+};
+
+namespace {
+
+int nfail(dpd_nn* h, int code, const std::string& m) {
+    if (h) h->err = m;
+    g_nn_error = m;
+    return code;
+}
+
+#define NCHK(h, expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return nfail((h), DPD_EHIP, nfmt("%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+
+#define NLAUNCH(h)                                                                        \
+    do {                                                                                  \
+        hipError_t e_ = hipGetLastError();                                                \
+        if (e_ != hipSuccess)                                                             \
+            return nfail((h), DPD_EHIP, nfmt("kernel launch: %s", hipGetErrorString(e_))); \
+    } while (0)
+
+template <class T>
+T* at(dpd_nn* h, size_t off) { return reinterpret_cast<T*>(h->ws + off); }
+
+// BF16 weight layouts from the master weights.
+int cast_weights(dpd_nn* h) {
+    const Net& n = h->net;
+    for (size_t l = 0; l < n.conv.size(); ++l) {
+        const Conv& c = n.conv[l];
+        const int nt = std::max(c.cout16 * c.Kpad, c.cin16 * c.Kbpad);
+        hipLaunchKernelGGL(k_cast_weights, dim3(blocks(nt)), dim3(kThreads), 0, h->stream, c,
+                           (const float*)at<float>(h, n.o_w + 4 * n.woff[l]),
+                           at<unsigned short>(h, n.o_wf[l]), at<unsigned short>(h, n.o_wb[l]));
+    }
+    NLAUNCH(h);
+    return DPD_OK;
+}
+
+// Forward pass of B fields: activations stay in the workspace, pred -> out.
+int forward(dpd_nn* h, const float* u, const float* cond, int B, float* pred) {
+    const Net& n = h->net;
+    const int M = n.p.M, M2 = M * M, npix = B * M2;
+    int rc = cast_weights(h);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_input, dim3(blocks(npix)), dim3(kThreads), 0, h->stream, npix, M2,
+                       n.p.c_in, u, cond, at<unsigned short>(h, n.o_x[0]));
+    const int ntile = npix / 16;
+    const int grid = (ntile + 3) / 4;
+    for (size_t l = 0; l < n.conv.size(); ++l) {
+        const Conv& c = n.conv[l];
+        const unsigned short* X = at<unsigned short>(h, n.o_x[l]);
+        const unsigned short* Wf = at<unsigned short>(h, n.o_wf[l]);
+        const float* b = at<float>(h, n.o_w + 4 * n.boff[l]);
+        if (l + 1 == n.conv.size())
+            hipLaunchKernelGGL(k_conv_fwd<true>, dim3(grid), dim3(kThreads), 0, h->stream, c, M, npix,
+                               X, Wf, b, (unsigned short*)nullptr, u, pred);
+        else
+            hipLaunchKernelGGL(k_conv_fwd<false>, dim3(grid), dim3(kThreads), 0, h->stream, c, M,
+                               npix, X, Wf, b, at<unsigned short>(h, n.o_x[l + 1]),
+                               (const float*)nullptr, (float*)nullptr);
+    }
+    NLAUNCH(h);
+    return DPD_OK;
+}
+
+int gradient(dpd_nn* h, const float* u, const float* cond, const float* target, int B,
+             float* grad, double* loss) {
+    const Net& n = h->net;
+    const int M = n.p.M, M2 = M * M, npix = B * M2;
+    float* pred = at<float>(h, n.o_pred);
+    int rc = forward(h, u, cond, B, pred);
+    if (rc) return rc;
+    const int nlb = blocks(npix);
+    double* lpart = at<double>(h, n.o_lpart);
+    hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(kThreads), 0, h->stream, npix, (const float*)pred,
+                       target, (float)(2.0 / (2.0 * npix)), at<float>(h, n.o_dz[0]),
+                       at<unsigned short>(h, n.o_dzb[0]), lpart);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kThreads), 0, h->stream, nlb,
+                       (const double*)lpart, 1.0 / (2.0 * npix), loss);
+    NLAUNCH(h);
+    const int ntile = npix / 16;
+    const int grid = (ntile + 3) / 4;
+    const int nwb = (npix + kWgPix - 1) / kWgPix;
+    float* part = at<float>(h, n.o_part);
+    int cur = 0;  // dZ of layer l sits in buffer cur
+    for (int l = (int)n.conv.size() - 1; l >= 0; --l) {
+        const Conv& c = n.conv[l];
+        const int nO = c.K * c.cout + c.cout;
+        hipLaunchKernelGGL(k_wgrad_part, dim3(nwb), dim3(kThreads), 0, h->stream, c, M, npix,
+                           (const unsigned short*)at<unsigned short>(h, n.o_x[l]),
+                           (const float*)at<float>(h, n.o_dz[cur]), part);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(nO)), dim3(kThreads), 0, h->stream, nO, nwb,
+                           (const float*)part, grad + n.woff[l]);
+        if (l > 0) {
+            hipLaunchKernelGGL(k_conv_bwd, dim3(grid), dim3(kThreads), 0, h->stream, c, M, npix,
+                               (const unsigned short*)at<unsigned short>(h, n.o_dzb[cur]),
+                               (const unsigned short*)at<unsigned short>(h, n.o_wb[l]),
+                               (const unsigned short*)at<unsigned short>(h, n.o_x[l]),
+                               at<float>(h, n.o_dz[1 - cur]), at<unsigned short>(h, n.o_dzb[1 - cur]));
+            cur = 1 - cur;
+        }
+        NLAUNCH(h);
+    }
+    return DPD_OK;
+}
+
+int adam(dpd_nn* h, const float* grad, float lr, float b1, float b2, float eps) {
+    const Net& n = h->net;
+    h->adam_t += 1;
+    const float c1 = (float)(1.0 - std::pow((double)b1, h->adam_t));
+    const float c2 = (float)(1.0 - std::pow((double)b2, h->adam_t));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(n.nparam)), dim3(kThreads), 0, h->stream, (int)n.nparam,
+                       at<float>(h, n.o_w), at<float>(h, n.o_m), at<float>(h, n.o_v), grad, lr, b1,
+                       b2, eps, c1, c2);
+    NLAUNCH(h);
+    return DPD_OK;
+}
+
+int check_batch(dpd_nn* h, int B) {
+    if (B < 1 || B > h->net.p.max_batch)
+        return nfail(h, DPD_EINVAL, nfmt("B = %d outside [1, %d]", B, h->net.p.max_batch));
+    return DPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpd_nn_param_count(const dpd_nn_params* p, int64_t* count) {
+    Net n;
+    std::string e;
+    int rc = plan(p, &n, &e);
+    if (rc) return nfail(nullptr, rc, e);
+    if (!count) return nfail(nullptr, DPD_EINVAL, "count is NULL");
+    *count = n.nparam;
+    return DPD_OK;
+}
+
+int dpd_nn_workspace_bytes(const dpd_nn_params* p, size_t* bytes) {
+    Net n;
+    std::string e;
+    int rc = plan(p, &n, &e);
+    if (rc) return nfail(nullptr, rc, e);
+    if (!bytes) return nfail(nullptr, DPD_EINVAL, "bytes is NULL");
+    *bytes = n.total;
+    return DPD_OK;
+}
+
+int dpd_nn_create(const dpd_nn_params* p, void* workspace, size_t bytes, void* stream,
+                  dpd_nn** out) {
+    try {
+        if (!out) return nfail(nullptr, DPD_EINVAL, "out is NULL");
+        *out = nullptr;
+        Net n;
+        std::string e;
+        int rc = plan(p, &n, &e);
+        if (rc) return nfail(nullptr, rc, e);
+        if (!workspace || ((uintptr_t)workspace & 255u))
+            return nfail(nullptr, DPD_EWORKSPACE, "workspace is NULL or not 256-byte aligned");
+        if (bytes < n.total)
+            return nfail(nullptr, DPD_EWORKSPACE, nfmt("workspace has %zu bytes, needs %zu", bytes, n.total));
+        dpd_nn* h = new (std::nothrow) dpd_nn();
+        if (!h) return nfail(nullptr, DPD_EINVAL, "out of host memory");
+        h->net = n;
+        h->stream = (hipStream_t)stream;
+        h->ws = (char*)workspace;
+        h->adam_t = 0;
+        h->err = "no error";
+        for (size_t off : {n.o_w, n.o_m, n.o_v, n.o_g})
+            hipLaunchKernelGGL(k_zero, dim3(blocks(n.nparam)), dim3(kThreads), 0, h->stream,
+                               at<float>(h, off), (long long)n.nparam);
+        hipError_t le = hipGetLastError();
+        if (le != hipSuccess) {
+            delete h;
+            return nfail(nullptr, DPD_EHIP, nfmt("kernel launch: %s", hipGetErrorString(le)));
+        }
+        *out = h;
+        return DPD_OK;
+    } catch (...) {
+        return nfail(nullptr, DPD_EINVAL, "internal error");
+    }
+}
+
+void dpd_nn_destroy(dpd_nn* nn) { delete nn; }
+
+const char* dpd_nn_last_error(const dpd_nn* nn) { return nn ? nn->err.c_str() : g_nn_error.c_str(); }
+
+int dpd_nn_set_weights(dpd_nn* nn, const float* w) {
+    if (!nn) return nfail(nullptr, DPD_EINVAL, "handle is NULL");
+    if (!w) return nfail(nn, DPD_EINVAL, "w is NULL");
+    const Net& n = nn->net;
+    NCHK(nn, hipMemcpyAsync(at<float>(nn, n.o_w), w, 4 * (size_t)n.nparam, hipMemcpyDeviceToDevice,
+                            nn->stream));
+    for (size_t off : {n.o_m, n.o_v})
+        hipLaunchKernelGGL(k_zero, dim3(blocks(n.nparam)), dim3(kThreads), 0, nn->stream,
+                           at<float>(nn, off), (long long)n.nparam);
+    NLAUNCH(nn);
+    nn->adam_t = 0;
+    return DPD_OK;
+}
+
+int dpd_nn_get_weights(dpd_nn* nn, float* w) {
+    if (!nn) return nfail(nullptr, DPD_EINVAL, "handle is NULL");
+    if (!w) return nfail(nn, DPD_EINVAL, "w is NULL");
+    NCHK(nn, hipMemcpyAsync(w, at<float>(nn, nn->net.o_w), 4 * (size_t)nn->net.nparam,
+                            hipMemcpyDeviceToDevice, nn->stream));
+    return DPD_OK;
+}
+
+int dpd_nn_forward(dpd_nn* nn, const float* u, const float* cond, int32_t B, float* pred) {
+    if (!nn) return nfail(nullptr, DPD_EINVAL, "handle is NULL");
+    int rc = check_batch(nn, B);
+    if (rc) return rc;
+    if (!u || !pred || (!cond && nn->net.p.c_in > 2)) return nfail(nn, DPD_EINVAL, "NULL field");
+    try {
+        return forward(nn, u, cond, B, pred);
+    } catch (...) {
+        return nfail(nn, DPD_EINVAL, "internal error");
+    }
+}
+
+int dpd_nn_gradient(dpd_nn* nn, const float* u, const float* cond, const float* target,
+                    int32_t B, float* grad, double* loss) {
+    if (!nn) return nfail(nullptr, DPD_EINVAL, "handle is NULL");
+    int rc = check_batch(nn, B);
+    if (rc) return rc;
+    if (!u || !target || !grad || (!cond && nn->net.p.c_in > 2)) return nfail(nn, DPD_EINVAL, "NULL argument");
+    try {
+        return gradient(nn, u, cond, target, B, grad, loss);
+    } catch (...) {
+        return nfail(nn, DPD_EINVAL, "internal error");
+    }
+}
+
+int dpd_nn_adam(dpd_nn* nn, const float* grad, float lr, float beta1, float beta2, float eps) {
+    if (!nn) return nfail(nullptr, DPD_EINVAL, "handle is NULL");
+    if (!grad) return nfail(nn, DPD_EINVAL, "grad is NULL");
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return nfail(nn, DPD_EINVAL, "need lr >= 0, 0 <= beta < 1, eps > 0");
+    return adam(nn, grad, lr, beta1, beta2, eps);
+}
+
+int dpd_nn_train_step(dpd_nn* nn, const float* u, const float* cond, const float* target,
+                      int32_t B, float lr, float beta1, float beta2, float eps, double* loss) {
+    if (!nn) return nfail(nullptr, DPD_EINVAL, "handle is NULL");
+    float* g = at<float>(nn, nn->net.o_g);
+    int rc = dpd_nn_gradient(nn, u, cond, target, B, g, loss);
+    if (rc) return rc;
+    return dpd_nn_adam(nn, g, lr, beta1, beta2, eps);
+}
+
+int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t steps,
+                   const float* noise_std, uint64_t seed, int32_t save_every, float* traj) {
+    if (!nn) return nfail(nullptr, DPD_EINVAL, "handle is NULL");
+    if (!u0 || !noise_std || (!cond && nn->net.p.c_in > 2)) return nfail(nn, DPD_EINVAL, "NULL argument");
+    if (steps < 0 || save_every < 1) return nfail(nn, DPD_EINVAL, "need steps >= 0, save_every >= 1");
+    if (steps / save_every > 0 && !traj) return nfail(nn, DPD_EINVAL, "traj is NULL");
+    if (!std::isfinite(noise_std[0]) || !std::isfinite(noise_std[1]) || noise_std[0] < 0.f || noise_std[1] < 0.f)
+        return nfail(nn, DPD_EINVAL, "noise_std must be finite and >= 0");
+    try {
+        const Net& n = nn->net;
+        const int M2 = n.p.M * n.p.M, nf = 2 * M2;
+        float* ucur = at<float>(nn, n.o_u);
+        float* pred = ucur + nf;
+        float* cnd = at<float>(nn, n.o_cond);
+        NCHK(nn, hipMemcpyAsync(ucur, u0, 4 * (size_t)nf, hipMemcpyDeviceToDevice, nn->stream));
+        if (n.p.c_in > 2)
+            NCHK(nn, hipMemcpyAsync(cnd, cond, 4 * (size_t)(n.p.c_in - 2), hipMemcpyDeviceToDevice, nn->stream));
+        const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+        for (int s = 1; s <= steps; ++s) {
+            int rc = forward(nn, ucur, cnd, 1, pred);
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_noise, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream, nf,
+                               (const float*)pred, noise_std[0], noise_std[1], (uint32_t)s, k0, k1, ucur);
+            NLAUNCH(nn);
+            if (s % save_every == 0)
+                NCHK(nn, hipMemcpyAsync(traj + (size_t)(s / save_every - 1) * nf, ucur, 4 * (size_t)nf,
+                                        hipMemcpyDeviceToDevice, nn->stream));
+        }
+        return DPD_OK;
+    } catch (...) {
+        return nfail(nn, DPD_EINVAL, "internal error");
+    }
+}
+
+int dpd_nn_sync(dpd_nn* nn) {
+    if (!nn) return nfail(nullptr, DPD_EINVAL, "handle is NULL");
+    NCHK(nn, hipStreamSynchronize(nn->stream));
+    return DPD_OK;
+}
+
+}  // extern "C"

@@ -161,3 +161,24 @@ def initial_state(cfg: dict, kind: str = "random", thermal: bool = False):
     else:
         v = np.zeros_like(x)
     return x, v
+
+
+# ---- learned closure -------------------------------------------------------------
+
+def closure_shapes(c_in: int, width: int, layers: int):
+    """(c_in, c_out) of every convolution of the closure network."""
+    return [(c_in if l == 0 else width, 2 if l == layers - 1 else width) for l in range(layers)]
+
+
+def closure_init(seed: int, c_in: int, width: int, layers: int, out_scale: float = 0.1):
+    """Seeded initial parameters of the closure network in its flat layout
+    (per layer W[9][c_in][c_out], then b[c_out]): He-normal weights, the last
+    layer scaled by out_scale, zero biases.  FP32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    shp = closure_shapes(c_in, width, layers)
+    for l, (ci, co) in enumerate(shp):
+        std = math.sqrt(2.0 / (9 * ci)) * (out_scale if l == len(shp) - 1 else 1.0)
+        parts.append(rng.normal(0.0, std, size=9 * ci * co))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)

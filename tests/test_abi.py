@@ -23,15 +23,19 @@ def dpd():
     return d
 
 
-def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+\**\s*(dpd_\w+)\s*\(", text, flags=re.M)
+def declared_functions(path=None):
+    names = []
+    paths = [path] if path else sorted(
+        os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    for hp in paths:
+        text = open(hp).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+\**\s*(dpd_\w+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
 def test_header_declares_the_boundary():
-    names = declared_functions()
+    names = declared_functions(HEADER)
     for required in ("dpd_create", "dpd_set_state", "dpd_forces", "dpd_step", "dpd_bin_velocity",
                      "dpd_get_state", "dpd_destroy", "dpd_last_error", "dpd_workspace_bytes"):
         assert required in names
@@ -140,3 +144,24 @@ def test_sweep_replicas_recipe():
         rho = 2 * c["n_agents"] / c["L"] ** 2
         assert abs(rho / (2 * c["phi"]) - 1) < 1e-3
         assert c["gamma"] == 4.5 and abs(c["gamma"] / c["gamma_s"] - c["ratio"]) < 1e-12
+
+
+def test_closure_header_and_validation(dpd):
+    names = declared_functions(os.path.join(ROOT, "include", "closure.h"))
+    for required in ("dpd_nn_create", "dpd_nn_forward", "dpd_nn_gradient", "dpd_nn_adam",
+                     "dpd_nn_train_step", "dpd_nn_rollout", "dpd_nn_destroy"):
+        assert required in names
+    from paper_1310_0998_amd import closure as cl
+    from oracle import closure as oc
+    assert cl.param_count(64, 4, 32, 4) == oc.param_count(4, 32, 4) == 20258
+    lib = cl.lib()
+    n = ctypes.c_size_t(0)
+    for bad in (dict(M=6), dict(M=0), dict(c_in=3), dict(c_in=36), dict(width=24), dict(layers=0),
+                dict(layers=9), dict(max_batch=0)):
+        kw = dict(M=64, c_in=4, width=32, layers=4, max_batch=8)
+        kw.update(bad)
+        assert lib.dpd_nn_workspace_bytes(ctypes.byref(cl.make_params(**kw)), ctypes.byref(n)) == -1
+        assert len(lib.dpd_nn_last_error(None)) > 0
+    assert lib.dpd_nn_workspace_bytes(ctypes.byref(cl.make_params(64, 4, 32, 4, 8)), ctypes.byref(n)) == 0
+    assert lib.dpd_nn_forward(None, None, None, 1, None) == -1
+    assert lib.dpd_nn_rollout(None, None, None, 1, None, 0, 1, None) == -1

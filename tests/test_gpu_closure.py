@@ -1,0 +1,170 @@
+"""The learned closure's kernels against the FP64 closure oracle, through the
+C ABI.  Needs an MI355X.
+
+With BF16-exact inputs and weights a single convolution has no rounding before
+its FP32 sums, so the GPU must agree with the oracle to FP32 summation
+accuracy.  Deeper networks round activations to BF16 between layers on both
+sides; a few activations can then round the other way (where the FP32 and FP64
+sums straddle a BF16 rounding boundary); measured, the outputs and gradients
+still agree to about 2e-6, against 4e-3 to 9e-3 between the BF16 and the FP64
+network."""
+import numpy as np
+import pytest
+
+from oracle import closure as oc
+from paper_1310_0998_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def cl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1310_0998_amd import closure as c
+    c.lib()
+    return c
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def bf16_exact(a):
+    return oc.bf16(a).astype(np.float32)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_single_layer_forward_and_gradient_exact_inputs(cl):
+    rng = np.random.default_rng(10)
+    M, B, c_in = 16, 3, 4
+    net = cl.Closure(M, c_in=c_in, width=16, layers=1, max_batch=4, device=DEV)
+    w = bf16_exact(rng.normal(0.0, 0.5, net.n_params))
+    u = bf16_exact(rng.normal(size=(B, M, M, 2)))
+    cond = bf16_exact(rng.normal(size=(B, c_in - 2)))
+    tgt = rng.normal(size=(B, M, M, 2)).astype(np.float32)
+    net.set_weights(dev(w))
+    pred = host(net.forward(dev(u), dev(cond)))
+    ref, _ = oc.forward(w, u, cond, c_in, 16, 1)
+    assert np.abs(pred - ref).max() <= 1e-5 * np.abs(ref).max()
+    loss, g = net.gradient(dev(u), dev(cond), dev(tgt))
+    lref, gref = oc.loss_and_gradient(w, u, cond, tgt, c_in, 16, 1)
+    assert loss == pytest.approx(lref, rel=1e-6)
+    assert rel_l2(host(g), gref) < 1e-5
+    net.close()
+
+
+@pytest.mark.parametrize("width,layers,M,B", [(32, 4, 32, 3), (16, 3, 16, 2), (32, 2, 64, 1)])
+def test_network_forward_and_gradient(cl, width, layers, M, B):
+    rng = np.random.default_rng(11 + layers)
+    c_in = 4
+    net = cl.Closure(M, c_in=c_in, width=width, layers=layers, max_batch=B, device=DEV)
+    w = inputs.closure_init(20 + layers, c_in, width, layers, out_scale=1.0)
+    u = rng.normal(size=(B, M, M, 2)).astype(np.float32)
+    cond = rng.normal(size=(B, c_in - 2)).astype(np.float32)
+    tgt = rng.normal(size=(B, M, M, 2)).astype(np.float32)
+    net.set_weights(dev(w))
+    pred = host(net.forward(dev(u), dev(cond)))
+    ref, _ = oc.forward(w, u, cond, c_in, width, layers)
+    e_f = rel_l2(pred - u, ref - u)
+    loss, g = net.gradient(dev(u), dev(cond), dev(tgt))
+    lref, gref = oc.loss_and_gradient(w, u, cond, tgt, c_in, width, layers)
+    e_g = rel_l2(host(g), gref)
+    # without the BF16 rounding the network differs by much more: the oracle's
+    # rounding points are the GPU's
+    plain, _ = oc.forward(w, u, cond, c_in, width, layers, bf16_ops=False)
+    e_plain = rel_l2(ref - u, plain - u)
+    print(f"width {width} layers {layers}: forward rel err {e_f:.2e}, gradient rel err {e_g:.2e}, "
+          f"BF16 vs FP64 network {e_plain:.2e}")
+    assert e_f < 2e-5 and e_g < 2e-5
+    assert loss == pytest.approx(lref, rel=1e-5)
+    if layers > 1:
+        assert e_plain > 10 * e_f
+    net.close()
+
+
+def test_adam_matches_oracle(cl):
+    rng = np.random.default_rng(12)
+    net = cl.Closure(8, c_in=4, width=16, layers=2, max_batch=1, device=DEV)
+    n = net.n_params
+    w = rng.normal(size=n)
+    net.set_weights(dev(w))
+    m = np.zeros(n)
+    v = np.zeros(n)
+    for t in range(1, 4):
+        g = rng.normal(size=n).astype(np.float32)
+        net.adam(dev(g), 0.01, 0.9, 0.999, 1e-8)
+        w, m, v = oc.adam(w, m, v, g.astype(np.float64), t, 0.01, 0.9, 0.999, 1e-8)
+    got = host(net.get_weights())
+    assert np.abs(got - w).max() <= 1e-6 * (1 + np.abs(w).max())
+    net.close()
+
+
+def test_rollout_zero_network(cl):
+    # zero parameters: without noise the field stays the start exactly; with
+    # noise each step adds independent N(0, s_c^2) per point and component
+    M = 64
+    net = cl.Closure(M, c_in=4, width=16, layers=2, max_batch=1, device=DEV)
+    rng = np.random.default_rng(13)
+    u0 = rng.normal(size=(M, M, 2)).astype(np.float32)
+    cond = np.array([0.5, 1.0], np.float32)
+    tr = host(net.rollout(dev(u0), dev(cond), 7, (0.0, 0.0), seed=1, save_every=1))
+    assert tr.shape == (7, M, M, 2) and (tr == u0).all()
+    s = (0.3, 0.1)
+    tr = host(net.rollout(dev(u0), dev(cond), 100, s, seed=2, save_every=50))
+    d = tr[-1] - u0
+    for c in range(2):
+        var = d[..., c].var()
+        assert var == pytest.approx(100 * s[c] ** 2, rel=0.08)
+        assert abs(d[..., c].mean()) < 4 * np.sqrt(100 * s[c] ** 2 / (M * M))
+    # the same seed repeats the same path
+    tr2 = host(net.rollout(dev(u0), dev(cond), 100, s, seed=2, save_every=50))
+    assert (tr2 == tr).all()
+    net.close()
+
+
+def test_training_learns_a_periodic_stencil(cl):
+    # target = u + 0.4 (mean of the four neighbours - u): a linear periodic
+    # operator the network can represent; Adam must beat persistence by far
+    rng = np.random.default_rng(14)
+    M, B = 32, 16
+    net = cl.Closure(M, c_in=4, width=32, layers=3, max_batch=B, device=DEV)
+    net.set_weights(dev(inputs.closure_init(30, 4, 32, 3)))
+
+    def batch():
+        u = rng.normal(size=(B, M, M, 2))
+        nb = (np.roll(u, 1, 1) + np.roll(u, -1, 1) + np.roll(u, 1, 2) + np.roll(u, -1, 2)) / 4
+        return u.astype(np.float32), (u + 0.4 * (nb - u)).astype(np.float32)
+
+    cond = np.zeros((B, 2), np.float32)
+    u, t = batch()
+    persist = float(((u - t) ** 2).mean())
+    for _ in range(300):
+        u, t = batch()
+        net.train_step(dev(u), dev(cond), dev(t), lr=2e-3)
+    u, t = batch()
+    loss, _ = net.gradient(dev(u), dev(cond), dev(t))
+    print(f"persistence loss {persist:.4e}, trained loss {loss:.4e}")
+    assert loss < 0.05 * persist
+    net.close()
+
+
+def test_closure_error_paths(cl):
+    net = cl.Closure(16, c_in=4, width=16, layers=2, max_batch=2, device=DEV)
+    u = torch.zeros((3, 16, 16, 2), dtype=torch.float32, device=DEV)
+    c = torch.zeros((3, 2), dtype=torch.float32, device=DEV)
+    with pytest.raises(Exception):
+        net.forward(u, c)  # batch above max_batch
+    with pytest.raises(Exception):
+        net.rollout(u[0], c[0], 5, (-1.0, 0.0))
+    net.close()
