@@ -10,7 +10,9 @@ synthetic random initial state).  Prints one JSON line.
 
 With --workload sweep64 it instead times the batched parameter sweep: 64
 replicas of uneven size advanced together, against the same systems run one
-after another (prints one JSON line of its own).
+after another; with --workload closure it trains the learned closure on
+DPD-generated fields and times its rollout against plain DPD (each prints one
+JSON line of its own).
 """
 from __future__ import annotations
 
@@ -218,6 +220,78 @@ def run_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def run_closure(args):
+    """The learned closure: DPD-generated training pairs, training on the GPU,
+    then 500 closure steps against 25000 DPD steps from the same state, timed,
+    with the energy-spectrum and correlation-length errors of the rollout."""
+    import numpy as np
+    import torch
+
+    from paper_1310_0998_amd import closure, closure_train as ct, inputs
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    runs = ct.generate(dev, log=log)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    train_idx, test_idx = ct.split(runs)
+    net = closure.Closure(ct.M, c_in=4, width=32, layers=4, max_batch=32, device=dev)
+    net.set_weights(torch.from_numpy(inputs.closure_init(601, 4, 32, 4)).to(dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, n_upd = ct.train(net, runs, train_idx, dev, epochs=args.closure_epochs, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    mse_net, mse_per, _ = ct.evaluate(net, runs, test_idx, dev)
+    _, _, res = ct.evaluate(net, runs, train_idx, dev)
+    log(f"held-out one-step MSE: network {mse_net:.5e}, persistence {mse_per:.5e}; "
+        f"training residual rms {res[0]:.4f} {res[1]:.4f}")
+    r_judge = 4  # zeta = 0.5, F_p = 1
+    j = ct.judge(net, runs, r_judge, args.closure_steps, (float(res[0]), float(res[1])), dev, log=log)
+    valid = j["max_band_err"] <= 0.05
+    speed = j["t_dpd"] / j["t_closure"]
+    line = {
+        "metric": "closure speedup at <=5% E(k) err",
+        "value": speed,
+        "unit": "x (plain DPD wall time / closure wall time, same span)",
+        "n_gpus": 1,
+        "steps": args.closure_steps,
+        "warmup": 0,
+        "ms_per_step": 1e3 * j["t_closure"] / args.closure_steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 matmul inputs, f32 accumulate",
+        "data": "synthetic (generated by the DPD engine)",
+        "valid": valid,
+        "config": {
+            "workload": "closure: 200k particles (100k dimers, L=447), gamma=4.5, zeta {0,0.5} x F_p "
+                        "{0.5,1,2}; 64x64 binned velocity every 10 steps; pairs 50 steps apart; "
+                        "4 conv layers, 32 channels, 3x3 periodic; rollout of "
+                        f"{args.closure_steps} steps (x50 DPD steps) at zeta=0.5, F_p=1",
+            "pairs_train": len(train_idx),
+            "pairs_test": len(test_idx),
+            "epochs": args.closure_epochs,
+            "adam_steps": n_upd,
+            "parallelism": "single-gpu",
+        },
+        "timing_s": {"generate": t_gen, "train": t_train, "dpd_span": j["t_dpd"],
+                     "closure_span": j["t_closure"]},
+        "one_step_mse": {"network": mse_net, "persistence": mse_per,
+                         "gain_over_persistence": mse_per / mse_net},
+        "noise_std": [float(res[0]), float(res[1])],
+        "E_band_err": j["band_err"],
+        "max_E_band_err": j["max_band_err"],
+        "L_gv": {"dpd": j["L_gv_ref"], "closure": j["L_gv_closure"], "rel_err": j["L_gv_err"]},
+        "final_training_loss": hist[-1],
+    }
+    print(json.dumps(line), flush=True)
+    for r in runs:
+        r["sim"].close()
+    net.close()
+    _ = np
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +313,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile schedule")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the one-after-another runs (workload sweep64)")
+    ap.add_argument("--closure-epochs", type=int, default=40)
+    ap.add_argument("--closure-steps", type=int, default=500,
+                    help="closure steps of the judged rollout (x50 DPD steps)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the engine has no multi-GPU path "
@@ -246,6 +323,9 @@ def main():
         sys.exit(2)
     if args.workload == "sweep64":
         run_sweep(args)
+        return
+    if args.workload == "closure":
+        run_closure(args)
         return
 
     import numpy as np

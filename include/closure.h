@@ -98,6 +98,19 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t steps
 /* Wait for the stream. */
 int dpd_nn_sync(dpd_nn* nn);
 
+/* ---- field statistics -------------------------------------------------------- */
+
+/* Power spectrum of nfields fields u[f][M][M][2] (Sec. 5.4, Eqs. 5.11-5.12):
+ * with the Fourier coefficients u^(k) = sum_{j,i} u[j][i] e^{-2 pi i (l j + k i)/M}
+ * / M^2 of each component, power[l][k] = sum over the fields and the two
+ * components of |u^(l, k)|^2 (device FP64, M x M; l the row wavenumber index,
+ * k the column one, both 0..M-1).  The energy spectrum is half its shell sums,
+ * and by Wiener-Khinchin its inverse transform is the fields' circular
+ * autocorrelation.  work: device scratch of 4 nfields M^2 floats.  Enqueued on
+ * `stream`.  Errors: DPD_EINVAL, DPD_EHIP. */
+int dpd_field_power(const float* u, int32_t nfields, int32_t M, float* work, double* power,
+                    void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -335,6 +335,57 @@ __global__ void k_noise(int n, const float* __restrict__ pred, float s0, float s
     unext[t] = pred[t] + ((t & 1) ? s1 : s0) * alpha;
 }
 
+// ---- field statistics ------------------------------------------------------------
+
+// Row transforms A[f][j][k][c] = sum_i u[f][j][i][c] e^{-2 pi i k i / M}
+// (complex, FP32), one thread per (field, row, k).
+__global__ void k_dft_rows(int nf, int M, const float* __restrict__ u, float2* A) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)nf * M * M) return;
+    const int k = (int)(t % M);
+    const long long fj = t / M;  // field * M + row
+    const float* row = u + fj * M * 2;
+    float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
+    for (int i = 0; i < M; ++i) {
+        float s, c;
+        sincospif(2.0f * (float)((k * i) % M) / (float)M, &s, &c);  // exact angle index
+        const float a0 = row[2 * i], a1 = row[2 * i + 1];
+        re0 = fmaf(a0, c, re0);
+        im0 = fmaf(-a0, s, im0);
+        re1 = fmaf(a1, c, re1);
+        im1 = fmaf(-a1, s, im1);
+    }
+    A[(fj * M + k) * 2 + 0] = make_float2(re0, im0);
+    A[(fj * M + k) * 2 + 1] = make_float2(re1, im1);
+}
+
+// Column transforms and power: P[l][k] = sum_f sum_c |sum_j A[f][j][k][c]
+// e^{-2 pi i l j / M}|^2 / M^4, summed over the fields in order (FP64), one
+// thread per (l, k).
+__global__ void k_dft_cols_power(int nf, int M, const float2* __restrict__ A, double* P) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M * M) return;
+    const int l = t / M, k = t % M;
+    double acc = 0.0;
+    for (int f = 0; f < nf; ++f) {
+        float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
+        for (int j = 0; j < M; ++j) {
+            float s, c;
+            sincospif(2.0f * (float)((l * j) % M) / (float)M, &s, &c);
+            const float2 a0 = A[(((long long)f * M + j) * M + k) * 2 + 0];
+            const float2 a1 = A[(((long long)f * M + j) * M + k) * 2 + 1];
+            // (a.x + i a.y)(c - i s)
+            re0 += a0.x * c + a0.y * s;
+            im0 += a0.y * c - a0.x * s;
+            re1 += a1.x * c + a1.y * s;
+            im1 += a1.y * c - a1.x * s;
+        }
+        acc += (double)re0 * re0 + (double)im0 * im0 + (double)re1 * re1 + (double)im1 * im1;
+    }
+    const double M2 = (double)M * M;
+    P[t] = acc / (M2 * M2);
+}
+
 __global__ void k_zero(float* p, long long n) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.f;
@@ -733,6 +784,22 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t steps
     } catch (...) {
         return nfail(nn, DPD_EINVAL, "internal error");
     }
+}
+
+int dpd_field_power(const float* u, int32_t nfields, int32_t M, float* work, double* power,
+                    void* stream) {
+    if (!u || !work || !power) return nfail(nullptr, DPD_EINVAL, "NULL argument");
+    if (nfields < 1 || M < 2 || M > 4096 || (long long)nfields * M * M > (1LL << 28))
+        return nfail(nullptr, DPD_EINVAL, "need nfields >= 1, 2 <= M <= 4096, nfields M^2 <= 2^28");
+    hipStream_t s = (hipStream_t)stream;
+    const long long n = (long long)nfields * M * M;
+    hipLaunchKernelGGL(k_dft_rows, dim3((unsigned)blocks(n)), dim3(kThreads), 0, s, (int)nfields,
+                       (int)M, u, (float2*)work);
+    hipLaunchKernelGGL(k_dft_cols_power, dim3(blocks((long long)M * M)), dim3(kThreads), 0, s,
+                       (int)nfields, (int)M, (const float2*)work, power);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return nfail(nullptr, DPD_EHIP, nfmt("kernel launch: %s", hipGetErrorString(e)));
+    return DPD_OK;
 }
 
 int dpd_nn_sync(dpd_nn* nn) {
