@@ -292,6 +292,49 @@ def run_closure(args):
     _ = np
 
 
+def run_paper(args):
+    """The paper's own parameter set as one batch (Sec. 5.1), with the energy
+    spectrum statistics of Sec. 5.4 computed on the GPU and the paper's
+    qualitative findings checked."""
+    import torch
+
+    from paper_1310_0998_amd import paper_runs
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    res = paper_runs.run(dev, args.paper_warm, args.paper_steps, args.paper_every, log=log)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stokes = [r for r in res if r["Gamma_s"] > 0]
+    dense_pair = [r for r in res if r["Gamma_s"] == 0 and r["phi"] == 0.8]
+    line = {
+        "metric": "paper parameter set: E(k) statistics (Sec. 5.4) on the GPU",
+        "value": wall,
+        "unit": "s (whole run)",
+        "n_gpus": 1,
+        "steps": args.paper_warm + args.paper_steps,
+        "warmup": args.paper_warm,
+        "higher_is_better": False,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "paper set: Phi=1.5, r_c=0.5, kT=0.05, kappa=1e3, l=1, f_SP=1, dt=3e-3, L=100, "
+                        "N=4e4 phi agents; (phi, Gamma, Gamma_s) in " + str(paper_runs.REPLICAS)
+                        + f"; u_M on 128x128, eps = L sqrt(10/N), every {args.paper_every} steps",
+            "parallelism": "single-gpu (one batch)",
+        },
+        "replicas": [{k: v for k, v in r.items() if k != "E_over_E1"} for r in res],
+        "checks": {
+            "stokes_low_k_slope_positive": all(r["alpha"] > 0 for r in stokes),
+            "stokes_peak_at_intermediate_k": all(r["k_peak"] > 1 for r in stokes),
+            "pair_only_dense_low_k_slope_negative": all(r["alpha"] < 0 for r in dense_pair),
+            "high_k_slope_negative": all(r["alpha_high"] < 0 for r in res),
+        },
+        "E_over_E1": {f"{r['phi']},{r['Gamma']},{r['Gamma_s']}": r["E_over_E1"] for r in res},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,6 +359,9 @@ def main():
     ap.add_argument("--closure-epochs", type=int, default=40)
     ap.add_argument("--closure-steps", type=int, default=500,
                     help="closure steps of the judged rollout (x50 DPD steps)")
+    ap.add_argument("--paper-warm", type=int, default=100000)
+    ap.add_argument("--paper-steps", type=int, default=200000)
+    ap.add_argument("--paper-every", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the engine has no multi-GPU path "
@@ -326,6 +372,9 @@ def main():
         return
     if args.workload == "closure":
         run_closure(args)
+        return
+    if args.workload == "paper":
+        run_paper(args)
         return
 
     import numpy as np

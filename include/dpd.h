@@ -59,7 +59,9 @@ typedef struct dpd_params {
     int64_t  n_agents;   /* agents, >= 1; particles N = 2 n_agents <= 2^30           */
     double   L;          /* box side, exactly representable in FP32, >= 3 r_c         */
     double   r_c;        /* pair cutoff (Eq. 2.2), > 0; cells per side
-                            n_c = floor(L / (r_c + skin)), >= 3                      */
+                            n_c = floor(L / max(r_c + skin, 1.25 bond_l)), >= 3
+                            (a bond longer than r_c keeps its partner within
+                            the 3 x 3 cell stencil)                                   */
     double   A;          /* conservative amplitude (Eq. 2.3), >= 0                    */
     double   gamma;      /* pair friction (Eq. 2.3), >= 0                             */
     double   kT;         /* thermal energy (Eq. 2.3), >= 0; sigma = sqrt(2 gamma kT)  */
@@ -223,13 +225,13 @@ int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* t
  * (first slot of each cell, row-major cells cy * n_c + cx with
  * c = min(n_c - 1, floor(x * n_c / L)) per axis in FP64), ids_out device
  * int32[N] (particle ids ordered by (cell, id)).  With a Verlet skin it is the
- * list of the last rebuild: cells floor(L / (r_c + skin)) per side, binned
+ * list of the last rebuild: n_c cells per side (dpd_cells_per_side), binned
  * from the positions of that step (no particle has moved more than skin / 2
  * since).  Synchronises the stream. */
 int dpd_get_cells(dpd_handle* h, int32_t* cell_start_out, int32_t* ids_out);
 
-/* Cells per side of the cell list for p (n_c = floor(L / (r_c + skin)), the
- * skin being 0 unless set), or a negative error code. */
+/* Cells per side of the cell list for p (n_c = floor(L / max(r_c + skin,
+ * 1.25 bond_l)), the skin being 0 unless set), or a negative error code. */
 int64_t dpd_cells_per_side(const dpd_params* p);
 
 /* The generator output for n pairs (i[k], j[k]) at `step` with p's seed,

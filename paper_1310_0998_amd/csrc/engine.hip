@@ -140,9 +140,14 @@ int derive_one(const dpd_params* p, DevParams& P, std::string* err) {
         *err = "skin must be finite, >= 0 and below L / 2";
         return DPD_EINVAL;
     }
-    const double width = p->r_c + (double)p->skin;  // smallest cell width
+    // smallest cell width: the cutoff (plus the skin), and room for a bond
+    // longer than the cutoff, whose partner must lie in the 3 x 3 stencil
+    const double width = std::max(p->r_c + (double)p->skin, 1.25 * p->bond_l);
     const double ncd = std::floor(p->L / width);
-    if (!(ncd >= 3.0)) { *err = "L must be at least 3 (r_c + skin) (n_c >= 3)"; return DPD_EINVAL; }
+    if (!(ncd >= 3.0)) {
+        *err = "L must be at least 3 max(r_c + skin, 1.25 bond_l) (n_c >= 3)";
+        return DPD_EINVAL;
+    }
     if (ncd > 46340.0) { *err = "too many cells (n_c^2 must fit in int32)"; return DPD_EINVAL; }
     const double vals[] = {p->A, p->gamma, p->kT, p->kappa, p->bond_l, p->gamma_s};
     for (double v : vals)

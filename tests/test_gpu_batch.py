@@ -253,3 +253,26 @@ def test_batch_error_paths(dpd):
     with pytest.raises(dpd.DPDError):
         b.autotune(4)  # no state yet
     b.close()
+
+
+def test_paper_geometry_batch_steps(dpd):
+    # the paper's own parameters (bond l = 1 longer than r_c = 0.5) in small
+    # boxes, as a batch with windowed 128-point fields: the partner stays in
+    # the stencil (no DPD_EBOND) and the state stays finite
+    from paper_1310_0998_amd import paper_runs
+    cfgs = []
+    for i, (phi, g, gs) in enumerate(paper_runs.REPLICAS):
+        c = paper_runs.replica_cfg(phi, g, gs, seed=900 + i)
+        c = dict(c, L=25.0, n_agents=int(round(4.0e4 * phi / 16)))
+        cfgs.append(c)
+    states = [inputs.initial_state(c) for c in cfgs]
+    x, v = concat(states)
+    b = dpd.Sim(cfgs, device=DEV)
+    b.set_state(dev(x), dev(v), 0)
+    b.set_graph_chunk(50)
+    b.step(600)
+    u, n = b.bin_velocity(64, 2.0, 0)
+    xs, vs, _, s = b.get_state()
+    assert s == 600 and np.isfinite(host(xs)).all() and np.isfinite(host(vs)).all()
+    assert np.isfinite(host(u)).all() and (host(n).sum(axis=(1, 2)) > 0).all()
+    b.close()

@@ -153,6 +153,8 @@ FORCE_CASES = [
     ("w_exp-0.5", dict(C1, w_exp=0.5, seed=19), "random", True),
     ("w_exp-1", dict(C1, w_exp=1.0, seed=20), "edge", True),
     ("w_exp-3", dict(C1, w_exp=3.0, seed=21), "random", True),
+    # the paper's own geometry: bond l = 1 longer than r_c = 0.5 (cells 1.25 l wide)
+    ("l>rc", dict(C1, r_c=0.5, bond_l=1.0, A=1.5, kT=0.05, seed=22), "random", True),
 ]
 
 
