@@ -43,8 +43,8 @@ def lib():
             "dpd_nn_gradient": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp]),
             "dpd_nn_adam": (ctypes.c_int, [vp, vp, f32, f32, f32, f32]),
             "dpd_nn_train_step": (ctypes.c_int, [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp]),
-            "dpd_nn_rollout": (ctypes.c_int, [vp, vp, vp, i32, ctypes.POINTER(f32), ctypes.c_uint64,
-                                              i32, vp]),
+            "dpd_nn_rollout": (ctypes.c_int, [vp, vp, vp, i32, ctypes.POINTER(f32), vp,
+                                              ctypes.c_uint64, i32, vp]),
             "dpd_nn_sync": (ctypes.c_int, [vp]),
         }
         for name, (res, args) in sig.items():
@@ -161,14 +161,20 @@ class Closure:
         return float(self._loss.item())
 
     def rollout(self, u0: torch.Tensor, cond: torch.Tensor, steps: int, noise_std=(0.0, 0.0),
-                seed: int = 0, save_every: int = 1) -> torch.Tensor:
+                seed: int = 0, save_every: int = 1,
+                noise_filter: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """steps applications of the network with noise after each: white
+        noise_std[c] w, or noise_std[c] (h * w) with the periodic filter h
+        ([M][M]) if given."""
         _f32(u0, (self.M, self.M, 2), "u0")
         _f32(cond, (self.c_in - 2,), "cond")
+        if noise_filter is not None:
+            _f32(noise_filter, (self.M, self.M), "noise_filter")
         nsave = steps // save_every
         traj = torch.empty((max(nsave, 1), self.M, self.M, 2), dtype=torch.float32, device=self.device)
         sd = (ctypes.c_float * 2)(float(noise_std[0]), float(noise_std[1]))
-        self._c(lib().dpd_nn_rollout(self._h, _p(u0), _p(cond), int(steps), sd, int(seed),
-                                     int(save_every), _p(traj)))
+        self._c(lib().dpd_nn_rollout(self._h, _p(u0), _p(cond), int(steps), sd, _p(noise_filter),
+                                     int(seed), int(save_every), _p(traj)))
         return traj[:nsave]
 
     def sync(self):

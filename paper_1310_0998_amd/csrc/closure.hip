@@ -335,6 +335,47 @@ __global__ void k_noise(int n, const float* __restrict__ pred, float s0, float s
     unext[t] = pred[t] + ((t & 1) ? s1 : s0) * alpha;
 }
 
+// White noise w[point][component] = alpha(point, component, step) for the
+// coloured rollout noise.
+__global__ void k_white(int n, uint32_t step, uint32_t k0, uint32_t k1, float* w) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint4 r = dpd::philox4x32_10(make_uint4((uint32_t)(t >> 1), (uint32_t)(t & 1), step, 0u), k0, k1);
+    w[t] = dpd::alpha_from_words(0, make_uint2(r.x, r.y));
+}
+
+// u_next[x][c] = pred[x][c] + s_c sum_y h[x - y] w[y][c] (periodic), h and w
+// staged in LDS (M <= 64: 48 KB), one thread per (point, component).
+constexpr int kColourMaxM = 64;
+__global__ __launch_bounds__(kThreads) void k_colour(int M, const float* __restrict__ h,
+                                                      const float* __restrict__ w,
+                                                      const float* __restrict__ pred, float s0,
+                                                      float s1, float* unext) {
+    __shared__ float sh[kColourMaxM * kColourMaxM];
+    __shared__ float sw[kColourMaxM * kColourMaxM * 2];
+    const int M2 = M * M;
+    for (int i = threadIdx.x; i < M2; i += kThreads) sh[i] = h[i];
+    for (int i = threadIdx.x; i < 2 * M2; i += kThreads) sw[i] = w[i];
+    __syncthreads();
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;  // 2 point + component
+    if (t >= 2 * M2) return;
+    const int c = t & 1, p = t >> 1;
+    const int y = p / M, x = p - y * M;
+    float acc = 0.f;
+    for (int yy = 0; yy < M; ++yy) {
+        int dy = y - yy;
+        dy += dy < 0 ? M : 0;
+        const float* hr = sh + dy * M;
+        const float* wr = sw + 2 * yy * M + c;
+        for (int xx = 0; xx < M; ++xx) {
+            int dx = x - xx;
+            dx += dx < 0 ? M : 0;
+            acc = fmaf(hr[dx], wr[2 * xx], acc);
+        }
+    }
+    unext[t] = pred[t] + (c ? s1 : s0) * acc;
+}
+
 // ---- field statistics ------------------------------------------------------------
 
 // Row transforms A[f][j][k][c] = sum_i u[f][j][i][c] e^{-2 pi i k i / M}
@@ -753,13 +794,16 @@ int dpd_nn_train_step(dpd_nn* nn, const float* u, const float* cond, const float
 }
 
 int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t steps,
-                   const float* noise_std, uint64_t seed, int32_t save_every, float* traj) {
+                   const float* noise_std, const float* noise_filter, uint64_t seed,
+                   int32_t save_every, float* traj) {
     if (!nn) return nfail(nullptr, DPD_EINVAL, "handle is NULL");
     if (!u0 || !noise_std || (!cond && nn->net.p.c_in > 2)) return nfail(nn, DPD_EINVAL, "NULL argument");
     if (steps < 0 || save_every < 1) return nfail(nn, DPD_EINVAL, "need steps >= 0, save_every >= 1");
     if (steps / save_every > 0 && !traj) return nfail(nn, DPD_EINVAL, "traj is NULL");
     if (!std::isfinite(noise_std[0]) || !std::isfinite(noise_std[1]) || noise_std[0] < 0.f || noise_std[1] < 0.f)
         return nfail(nn, DPD_EINVAL, "noise_std must be finite and >= 0");
+    if (noise_filter && nn->net.p.M > kColourMaxM)
+        return nfail(nn, DPD_EINVAL, nfmt("a noise filter needs M <= %d", kColourMaxM));
     try {
         const Net& n = nn->net;
         const int M2 = n.p.M * n.p.M, nf = 2 * M2;
@@ -773,8 +817,18 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t steps
         for (int s = 1; s <= steps; ++s) {
             int rc = forward(nn, ucur, cnd, 1, pred);
             if (rc) return rc;
-            hipLaunchKernelGGL(k_noise, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream, nf,
-                               (const float*)pred, noise_std[0], noise_std[1], (uint32_t)s, k0, k1, ucur);
+            if (noise_filter) {
+                float* w = at<float>(nn, n.o_dz[0]);  // free while rolling out
+                hipLaunchKernelGGL(k_white, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream, nf,
+                                   (uint32_t)s, k0, k1, w);
+                hipLaunchKernelGGL(k_colour, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream,
+                                   n.p.M, noise_filter, (const float*)w, (const float*)pred,
+                                   noise_std[0], noise_std[1], ucur);
+            } else {
+                hipLaunchKernelGGL(k_noise, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream, nf,
+                                   (const float*)pred, noise_std[0], noise_std[1], (uint32_t)s, k0,
+                                   k1, ucur);
+            }
             NLAUNCH(nn);
             if (s % save_every == 0)
                 NCHK(nn, hipMemcpyAsync(traj + (size_t)(s / save_every - 1) * nf, ucur, 4 * (size_t)nf,

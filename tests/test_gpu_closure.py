@@ -130,6 +130,32 @@ def test_rollout_zero_network(cl):
     # the same seed repeats the same path
     tr2 = host(net.rollout(dev(u0), dev(cond), 100, s, seed=2, save_every=50))
     assert (tr2 == tr).all()
+    # a unit impulse as the noise filter is the white noise, bit for bit
+    delta = np.zeros((M, M), np.float32)
+    delta[0, 0] = 1.0
+    tr3 = host(net.rollout(dev(u0), dev(cond), 100, s, seed=2, save_every=50, noise_filter=dev(delta)))
+    assert (tr3 == tr).all()
+    net.close()
+
+
+def test_rollout_coloured_noise_spectrum(cl):
+    # one step of the zero network from rest with a filter h: the noise has
+    # normalised Fourier power s^2 |DFT(h)|^2 / M^2 per mode and component
+    from paper_1310_0998_amd import fieldstats as fs
+    M = 32
+    net = cl.Closure(M, c_in=4, width=16, layers=1, max_batch=1, device=DEV)
+    ii = np.arange(M)
+    d = np.minimum(ii, M - ii).astype(np.float64)
+    h = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2 * 1.5 ** 2))
+    h = (h / np.sqrt((h * h).sum())).astype(np.float32)
+    u0 = np.zeros((M, M, 2), np.float32)
+    cond = np.zeros(2, np.float32)
+    fields = [net.rollout(dev(u0), dev(cond), 1, (0.7, 0.7), seed=100 + k, noise_filter=dev(h))[0]
+              for k in range(400)]
+    P = fs.power(torch.stack(fields).contiguous()) / (2 * 400)
+    want = 0.49 * np.abs(np.fft.fft2(h.astype(np.float64))) ** 2 / M ** 2
+    Eb, Wb = fs.bands(fs.shells(P)), fs.bands(fs.shells(want))
+    assert Eb[:4] == pytest.approx(Wb[:4], rel=0.15)
     net.close()
 
 
