@@ -220,9 +220,20 @@ def run_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def _finite(o):
+    """o with non-finite floats replaced by None (JSON has no inf or NaN)."""
+    if isinstance(o, float):
+        return o if o == o and abs(o) != float("inf") else None
+    if isinstance(o, dict):
+        return {k: _finite(v) for k, v in o.items()}
+    if isinstance(o, (list, tuple)):
+        return [_finite(v) for v in o]
+    return o
+
+
 def run_closure(args):
     """The learned closure: DPD-generated training pairs, training on the GPU,
-    then 2000 closure steps against 100000 DPD steps from the same state, timed,
+    then an ensemble of closure rollouts against the same ensemble of DPD runs, timed,
     with the energy-spectrum and correlation-length errors of the rollout."""
     import numpy as np
     import torch
@@ -246,13 +257,21 @@ def run_closure(args):
     _, _, res = ct.evaluate(net, runs, train_idx, dev)
     log(f"held-out one-step MSE: network {mse_net:.5e}, persistence {mse_per:.5e}; "
         f"training residual rms {res[0]:.4f} {res[1]:.4f}")
+    for run in runs:
+        run["sim"].close()
     r_judge = 4  # zeta = 0.5, F_p = 1
     idx_r = [q for q in train_idx if q[0] == r_judge]
     h0, R0 = ct.residual_filter(net, runs, idx_r, dev)
-    h, _, cal = ct.calibrate_filter(net, runs, r_judge, idx_r, R0, dev, log=log)
+    E, T = args.closure_ensemble, args.closure_steps
+    cond = torch.tensor(ct.runs_cond(r_judge), dtype=torch.float32, device=dev)
+    cstart, cfields, t_cal = ct.ensemble(r_judge, E, args.closure_warm, T, 1000, dev, log=log)
+    h, _, cal = ct.calibrate_filter(net, cstart, cfields, cond, R0, dev, log=log)
+    del cfields
+    jstart, jfields, t_dpd = ct.ensemble(r_judge, E, args.closure_warm, T, 2000, dev, log=log)
     noises = {"calibrated": ((1.0, 1.0), h), "residual": ((1.0, 1.0), h0),
               "white": ((float(res[0]), float(res[1])), None)}
-    j = ct.judge(net, runs, r_judge, args.closure_steps, noises, dev, log=log)
+    j = ct.judge(net, r_judge, jstart, jfields, t_dpd, noises, dev, log=log)
+    del jfields
     jm = j["models"]["calibrated"]
     valid = jm["max_band_err"] <= 0.05
     speed = j["t_dpd"] / jm["t_closure"]
@@ -273,21 +292,25 @@ def run_closure(args):
         "config": {
             "workload": "closure: 200k particles (100k dimers, L=447), gamma=4.5, zeta {0,0.5} x F_p "
                         "{0.5,1,2}; 64x64 binned velocity every 10 steps; pairs 50 steps apart; "
-                        "4 conv layers, 32 channels, 3x3 periodic; rollout of "
-                        f"{args.closure_steps} steps (x50 DPD steps) at zeta=0.5, F_p=1 with noise "
-                        "filtered to the residual spectrum of that run's training pairs, scaled per "
-                        "shell so the rollout reproduces the spectrum of those training fields",
+                        "4 conv layers, 32 channels, 3x3 periodic; judged at zeta=0.5, F_p=1: "
+                        f"{E} independent replicas (one batch) x {T * ct.INTERVAL} DPD steps against "
+                        f"{E} batched closure rollouts x {T} steps from the same fields, noise filtered "
+                        "to the training residual's spectrum and scaled per shell to a separate "
+                        f"calibration ensemble ({E} replicas x {T * ct.INTERVAL} steps, other seeds)",
             "pairs_train": len(train_idx),
             "pairs_test": len(test_idx),
             "epochs": args.closure_epochs,
             "adam_steps": n_upd,
             "parallelism": "single-gpu",
         },
-        "timing_s": {"generate": t_gen, "train": t_train, "dpd_span": j["t_dpd"],
+        "timing_s": {"generate": t_gen, "train": t_train, "calibration_dpd": t_cal,
+                     "dpd_span": j["t_dpd"],
                      "closure_span": jm["t_closure"]},
         "one_step_mse": {"network": mse_net, "persistence": mse_per,
                          "gain_over_persistence": mse_per / mse_net},
         "E_band_err": jm["band_err"],
+        "E_band_err_se": jm["band_err_se"],
+        "E_band_ref_rel_se": j["band_ref_se"],
         "max_E_band_err": jm["max_band_err"],
         "L_gv": {"dpd": j["L_gv_ref"], "closure": jm["L_gv_closure"], "rel_err": jm["L_gv_err"]},
         "calibration_max_shell_dev": cal,
@@ -298,9 +321,7 @@ def run_closure(args):
                         "L_gv_rel_err": j["models"]["white"]["L_gv_err"]},
         "final_training_loss": hist[-1],
     }
-    print(json.dumps(line), flush=True)
-    for r in runs:
-        r["sim"].close()
+    print(json.dumps(_finite(line)), flush=True)
     net.close()
     _ = np
 
@@ -369,7 +390,11 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile schedule")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the one-after-another runs (workload sweep64)")
-    ap.add_argument("--closure-epochs", type=int, default=8)
+    ap.add_argument("--closure-epochs", type=int, default=40)
+    ap.add_argument("--closure-ensemble", type=int, default=32,
+                    help="independent replicas of the judged run (and of its calibration ensemble)")
+    ap.add_argument("--closure-warm", type=int, default=4000,
+                    help="DPD warm-up steps of each ensemble before its fields are taken")
     ap.add_argument("--closure-steps", type=int, default=2000,
                     help="closure steps of the judged rollout (x50 DPD steps)")
     ap.add_argument("--paper-warm", type=int, default=100000)

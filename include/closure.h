@@ -84,18 +84,20 @@ int dpd_nn_adam(dpd_nn* nn, const float* grad, float lr, float beta1, float beta
 int dpd_nn_train_step(dpd_nn* nn, const float* u, const float* cond, const float* target,
                       int32_t B, float lr, float beta1, float beta2, float eps, double* loss);
 
-/* Autonomous rollout from u0 ([M][M][2]) under cond ([c_in - 2]): steps
- * applications of the network, each followed by noise.  White Gaussian
- * numbers w (Philox4x32-10, counter (grid point, component, step), key seed,
- * Box-Muller) either enter as noise_std[c] w (noise_filter NULL) or, with a
- * filter h ([M][M] device, M <= 64), as noise_std[c] (h * w) with * the
- * periodic convolution, which gives the noise the spectrum |DFT(h)|^2 (a
- * filter h = IDFT(M sqrt(R)) gives normalised Fourier coefficients of power
- * R(k) per component).  noise_std: host, 2 values.  Every save_every-th field
+/* Autonomous rollout of B fields (1 <= B <= max_batch) from u0 ([B][M][M][2])
+ * under cond ([B][c_in - 2]): steps applications of the network, each
+ * followed by noise.  White Gaussian numbers w (Philox4x32-10, counter
+ * (b M^2 + grid point, component, step), key seed, Box-Muller) either enter as
+ * noise_std[c] w (noise_filter NULL) or, with a filter h ([M][M] device,
+ * M <= 64, B <= 65535, shared by the B fields), as noise_std[c] (h * w) with * the periodic
+ * convolution, which gives the noise the spectrum |DFT(h)|^2 (a filter
+ * h = IDFT(M sqrt(R)) gives normalised Fourier coefficients of power R(k) per
+ * component).  noise_std: host, 2 values.  Every save_every-th set of fields
  * (k = save_every, 2 save_every, ...) is written to traj[k / save_every - 1]
- * ([M][M][2] each; traj holds steps / save_every fields).  The field stays in
- * the workspace between the applications.  Errors: DPD_EINVAL, DPD_EHIP. */
-int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t steps,
+ * ([B][M][M][2] each; traj holds steps / save_every of them).  The fields
+ * stay in the workspace between the applications; u0 and cond are read once,
+ * in stream order.  Errors: DPD_EINVAL, DPD_EHIP. */
+int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, int32_t steps,
                    const float* noise_std, const float* noise_filter, uint64_t seed,
                    int32_t save_every, float* traj);
 

@@ -43,7 +43,7 @@ def lib():
             "dpd_nn_gradient": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp]),
             "dpd_nn_adam": (ctypes.c_int, [vp, vp, f32, f32, f32, f32]),
             "dpd_nn_train_step": (ctypes.c_int, [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp]),
-            "dpd_nn_rollout": (ctypes.c_int, [vp, vp, vp, i32, ctypes.POINTER(f32), vp,
+            "dpd_nn_rollout": (ctypes.c_int, [vp, vp, vp, i32, i32, ctypes.POINTER(f32), vp,
                                               ctypes.c_uint64, i32, vp]),
             "dpd_nn_sync": (ctypes.c_int, [vp]),
         }
@@ -165,17 +165,21 @@ class Closure:
                 noise_filter: Optional[torch.Tensor] = None) -> torch.Tensor:
         """steps applications of the network with noise after each: white
         noise_std[c] w, or noise_std[c] (h * w) with the periodic filter h
-        ([M][M]) if given."""
-        _f32(u0, (self.M, self.M, 2), "u0")
-        _f32(cond, (self.c_in - 2,), "cond")
+        ([M][M]) if given.  u0 is one field [M][M][2] with cond [c_in - 2]
+        (returns [steps // save_every][M][M][2]) or a batch [B][M][M][2] with
+        cond [B][c_in - 2] (returns [steps // save_every][B][M][M][2])."""
+        single = u0.dim() == 3
+        B = 1 if single else int(u0.shape[0])
+        _f32(u0, ((self.M, self.M, 2) if single else (B, self.M, self.M, 2)), "u0")
+        _f32(cond, ((self.c_in - 2,) if single else (B, self.c_in - 2)), "cond")
         if noise_filter is not None:
             _f32(noise_filter, (self.M, self.M), "noise_filter")
         nsave = steps // save_every
-        traj = torch.empty((max(nsave, 1), self.M, self.M, 2), dtype=torch.float32, device=self.device)
+        traj = torch.empty((max(nsave, 1), B, self.M, self.M, 2), dtype=torch.float32, device=self.device)
         sd = (ctypes.c_float * 2)(float(noise_std[0]), float(noise_std[1]))
-        self._c(lib().dpd_nn_rollout(self._h, _p(u0), _p(cond), int(steps), sd, _p(noise_filter),
+        self._c(lib().dpd_nn_rollout(self._h, _p(u0), _p(cond), B, int(steps), sd, _p(noise_filter),
                                      int(seed), int(save_every), _p(traj)))
-        return traj[:nsave]
+        return traj[:nsave, 0] if single else traj[:nsave]
 
     def sync(self):
         self._c(lib().dpd_nn_sync(self._h))

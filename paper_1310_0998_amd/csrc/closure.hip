@@ -325,14 +325,19 @@ __global__ void k_adam(int n, float* w, float* m, float* v, const float* __restr
 }
 
 // u_next = pred + sigma_c alpha, alpha Gaussian by Box-Muller from
-// Philox4x32-10 with counter (point, component, step, 0) and the seed as key.
+// Philox4x32-10 with counter (point, component, step, 0) and the seed as key
+// (point = b M^2 + pixel over a batch).  Also writes u_next rounded to BF16
+// into channels 0 and 1 of the next forward pass's input X (cin channels per
+// pixel; the condition channels stay as they are).
 __global__ void k_noise(int n, const float* __restrict__ pred, float s0, float s1, uint32_t step,
-                        uint32_t k0, uint32_t k1, float* unext) {
+                        uint32_t k0, uint32_t k1, float* unext, int cin, unsigned short* X) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;  // t = 2 point + component
     if (t >= n) return;
     const uint4 w = dpd::philox4x32_10(make_uint4((uint32_t)(t >> 1), (uint32_t)(t & 1), step, 0u), k0, k1);
     const float alpha = dpd::alpha_from_words(0, make_uint2(w.x, w.y));
-    unext[t] = pred[t] + ((t & 1) ? s1 : s0) * alpha;
+    const float v = pred[t] + ((t & 1) ? s1 : s0) * alpha;
+    unext[t] = v;
+    X[(size_t)(t >> 1) * cin + (t & 1)] = to_bf16(v);
 }
 
 // White noise w[point][component] = alpha(point, component, step) for the
@@ -344,18 +349,21 @@ __global__ void k_white(int n, uint32_t step, uint32_t k0, uint32_t k1, float* w
     w[t] = dpd::alpha_from_words(0, make_uint2(r.x, r.y));
 }
 
-// u_next[x][c] = pred[x][c] + s_c sum_y h[x - y] w[y][c] (periodic), h and w
-// staged in LDS (M <= 64: 48 KB), one thread per (point, component).
+// u_next[x][c] = pred[x][c] + s_c sum_y h[x - y] w[y][c] (periodic) for field
+// blockIdx.y of a batch, h and that field's w staged in LDS (M <= 64: 48 KB),
+// one thread per (point, component); u_next also goes to X as in k_noise.
 constexpr int kColourMaxM = 64;
 __global__ __launch_bounds__(kThreads) void k_colour(int M, const float* __restrict__ h,
                                                       const float* __restrict__ w,
                                                       const float* __restrict__ pred, float s0,
-                                                      float s1, float* unext) {
+                                                      float s1, float* unext, int cin,
+                                                      unsigned short* X) {
     __shared__ float sh[kColourMaxM * kColourMaxM];
     __shared__ float sw[kColourMaxM * kColourMaxM * 2];
     const int M2 = M * M;
+    const size_t f0 = (size_t)blockIdx.y * 2 * M2;  // first value of this field
     for (int i = threadIdx.x; i < M2; i += kThreads) sh[i] = h[i];
-    for (int i = threadIdx.x; i < 2 * M2; i += kThreads) sw[i] = w[i];
+    for (int i = threadIdx.x; i < 2 * M2; i += kThreads) sw[i] = w[f0 + i];
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;  // 2 point + component
     if (t >= 2 * M2) return;
@@ -373,7 +381,9 @@ __global__ __launch_bounds__(kThreads) void k_colour(int M, const float* __restr
             acc = fmaf(hr[dx], wr[2 * xx], acc);
         }
     }
-    unext[t] = pred[t] + (c ? s1 : s0) * acc;
+    const float v = pred[f0 + t] + (c ? s1 : s0) * acc;
+    unext[f0 + t] = v;
+    X[((size_t)blockIdx.y * M2 + p) * cin + c] = to_bf16(v);
 }
 
 // ---- field statistics ------------------------------------------------------------
@@ -462,7 +472,7 @@ struct Net {
     long long nparam = 0;
     size_t total = 0;
     // workspace offsets
-    size_t o_w, o_m, o_v, o_g, o_pred, o_dz[2], o_dzb[2], o_part, o_lpart, o_loss, o_u, o_cond;
+    size_t o_w, o_m, o_v, o_g, o_pred, o_dz[2], o_dzb[2], o_part, o_lpart, o_loss, o_u;
     std::vector<size_t> o_x, o_wf, o_wb;
 };
 
@@ -517,8 +527,7 @@ int plan(const dpd_nn_params* p, Net* n, std::string* err) {
     n->o_part = take(nwb * kWgOutMax * 4);
     n->o_lpart = take(((npix + kThreads - 1) / kThreads) * 8);
     n->o_loss = take(8);
-    n->o_u = take((size_t)p->M * p->M * 2 * 4 * 2);  // rollout field and its prediction
-    n->o_cond = take(kMaxC * 4);
+    n->o_u = take(npix * 2 * 4 * 2);  // rollout fields and their predictions
     n->o_x.clear();
     n->o_wf.clear();
     n->o_wb.clear();
@@ -581,13 +590,17 @@ int cast_weights(dpd_nn* h) {
 }
 
 // Forward pass of B fields: activations stay in the workspace, pred -> out.
-int forward(dpd_nn* h, const float* u, const float* cond, int B, float* pred) {
+// With prepared = true the BF16 weights and the first activation are already
+// in place (a rollout's later steps).
+int forward(dpd_nn* h, const float* u, const float* cond, int B, float* pred, bool prepared = false) {
     const Net& n = h->net;
     const int M = n.p.M, M2 = M * M, npix = B * M2;
-    int rc = cast_weights(h);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_input, dim3(blocks(npix)), dim3(kThreads), 0, h->stream, npix, M2,
-                       n.p.c_in, u, cond, at<unsigned short>(h, n.o_x[0]));
+    if (!prepared) {
+        int rc = cast_weights(h);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_input, dim3(blocks(npix)), dim3(kThreads), 0, h->stream, npix, M2,
+                           n.p.c_in, u, cond, at<unsigned short>(h, n.o_x[0]));
+    }
     const int ntile = npix / 16;
     const int grid = (ntile + 3) / 4;
     for (size_t l = 0; l < n.conv.size(); ++l) {
@@ -793,41 +806,47 @@ int dpd_nn_train_step(dpd_nn* nn, const float* u, const float* cond, const float
     return dpd_nn_adam(nn, g, lr, beta1, beta2, eps);
 }
 
-int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t steps,
+int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, int32_t steps,
                    const float* noise_std, const float* noise_filter, uint64_t seed,
                    int32_t save_every, float* traj) {
     if (!nn) return nfail(nullptr, DPD_EINVAL, "handle is NULL");
     if (!u0 || !noise_std || (!cond && nn->net.p.c_in > 2)) return nfail(nn, DPD_EINVAL, "NULL argument");
+    if (B < 1 || B > nn->net.p.max_batch) return nfail(nn, DPD_EINVAL, "need 1 <= B <= max_batch");
     if (steps < 0 || save_every < 1) return nfail(nn, DPD_EINVAL, "need steps >= 0, save_every >= 1");
     if (steps / save_every > 0 && !traj) return nfail(nn, DPD_EINVAL, "traj is NULL");
     if (!std::isfinite(noise_std[0]) || !std::isfinite(noise_std[1]) || noise_std[0] < 0.f || noise_std[1] < 0.f)
         return nfail(nn, DPD_EINVAL, "noise_std must be finite and >= 0");
-    if (noise_filter && nn->net.p.M > kColourMaxM)
-        return nfail(nn, DPD_EINVAL, nfmt("a noise filter needs M <= %d", kColourMaxM));
+    if (noise_filter && (nn->net.p.M > kColourMaxM || B > 65535))
+        return nfail(nn, DPD_EINVAL, nfmt("a noise filter needs M <= %d and B <= 65535", kColourMaxM));
     try {
         const Net& n = nn->net;
-        const int M2 = n.p.M * n.p.M, nf = 2 * M2;
+        const int M2 = n.p.M * n.p.M, nf = 2 * M2 * B;
         float* ucur = at<float>(nn, n.o_u);
         float* pred = ucur + nf;
-        float* cnd = at<float>(nn, n.o_cond);
+        unsigned short* X0 = at<unsigned short>(nn, n.o_x[0]);
         NCHK(nn, hipMemcpyAsync(ucur, u0, 4 * (size_t)nf, hipMemcpyDeviceToDevice, nn->stream));
-        if (n.p.c_in > 2)
-            NCHK(nn, hipMemcpyAsync(cnd, cond, 4 * (size_t)(n.p.c_in - 2), hipMemcpyDeviceToDevice, nn->stream));
+        // weights in BF16 and the first input, once; each step's noise kernel
+        // then writes the next input's field channels
+        int rc = cast_weights(nn);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_input, dim3(blocks(B * M2)), dim3(kThreads), 0, nn->stream, B * M2, M2,
+                           n.p.c_in, (const float*)ucur, cond, X0);
+        NLAUNCH(nn);
         const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
         for (int s = 1; s <= steps; ++s) {
-            int rc = forward(nn, ucur, cnd, 1, pred);
+            rc = forward(nn, ucur, nullptr, B, pred, true);
             if (rc) return rc;
             if (noise_filter) {
                 float* w = at<float>(nn, n.o_dz[0]);  // free while rolling out
                 hipLaunchKernelGGL(k_white, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream, nf,
                                    (uint32_t)s, k0, k1, w);
-                hipLaunchKernelGGL(k_colour, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream,
+                hipLaunchKernelGGL(k_colour, dim3(blocks(2 * M2), B), dim3(kThreads), 0, nn->stream,
                                    n.p.M, noise_filter, (const float*)w, (const float*)pred,
-                                   noise_std[0], noise_std[1], ucur);
+                                   noise_std[0], noise_std[1], ucur, n.p.c_in, X0);
             } else {
                 hipLaunchKernelGGL(k_noise, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream, nf,
                                    (const float*)pred, noise_std[0], noise_std[1], (uint32_t)s, k0,
-                                   k1, ucur);
+                                   k1, ucur, n.p.c_in, X0);
             }
             NLAUNCH(nn);
             if (s % save_every == 0)

@@ -166,4 +166,4 @@ def test_closure_header_and_validation(dpd):
         assert len(lib.dpd_nn_last_error(None)) > 0
     assert lib.dpd_nn_workspace_bytes(ctypes.byref(cl.make_params(64, 4, 32, 4, 8)), ctypes.byref(n)) == 0
     assert lib.dpd_nn_forward(None, None, None, 1, None) == -1
-    assert lib.dpd_nn_rollout(None, None, None, 1, None, None, 0, 1, None) == -1
+    assert lib.dpd_nn_rollout(None, None, None, 1, 1, None, None, 0, 1, None) == -1

@@ -138,6 +138,35 @@ def test_rollout_zero_network(cl):
     net.close()
 
 
+def test_batched_rollout(cl):
+    # a batch of B fields rolls out as B single rollouts: without noise every
+    # field bit for bit, with noise field 0 (its noise counters are the single
+    # field's); and the noise-free rollout is the oracle's network applied
+    # step after step
+    rng = np.random.default_rng(14)
+    M, B, c_in, width, layers, steps = 32, 3, 4, 16, 2, 3
+    net = cl.Closure(M, c_in=c_in, width=width, layers=layers, max_batch=B, device=DEV)
+    w = inputs.closure_init(31, c_in, width, layers, out_scale=0.3)
+    net.set_weights(dev(w))
+    u0 = rng.normal(size=(B, M, M, 2)).astype(np.float32)
+    cond = rng.normal(size=(B, c_in - 2)).astype(np.float32)
+    tb = host(net.rollout(dev(u0), dev(cond), steps, (0.0, 0.0), seed=3))
+    assert tb.shape == (steps, B, M, M, 2)
+    for b in range(B):
+        ts = host(net.rollout(dev(u0[b]), dev(cond[b]), steps, (0.0, 0.0), seed=3))
+        assert (ts == tb[:, b]).all()
+    ref = u0.astype(np.float64)
+    for k in range(steps):
+        ref, _ = oc.forward(w, ref, cond, c_in, width, layers)
+        ref = ref.astype(np.float32).astype(np.float64)  # the fields are stored in FP32
+        assert rel_l2(tb[k] - u0, ref - u0) < 1e-4
+    tn = host(net.rollout(dev(u0), dev(cond), steps, (0.2, 0.1), seed=5))
+    t0 = host(net.rollout(dev(u0[0]), dev(cond[0]), steps, (0.2, 0.1), seed=5))
+    assert (tn[:, 0] == t0).all()
+    assert not (tn[:, 1] == tb[:, 1]).all()
+    net.close()
+
+
 def test_rollout_coloured_noise_spectrum(cl):
     # one step of the zero network from rest with a filter h: the noise has
     # normalised Fourier power s^2 |DFT(h)|^2 / M^2 per mode and component
