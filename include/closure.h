@@ -89,8 +89,9 @@ int dpd_nn_train_step(dpd_nn* nn, const float* u, const float* cond, const float
  * followed by noise.  White Gaussian numbers w (Philox4x32-10, counter
  * (b M^2 + grid point, component, step), key seed, Box-Muller) either enter as
  * noise_std[c] w (noise_filter NULL) or, with a filter h ([M][M] device,
- * M <= 64, B <= 65535, shared by the B fields), as noise_std[c] (h * w) with * the periodic
- * convolution, which gives the noise the spectrum |DFT(h)|^2 (a filter
+ * M <= 64, B <= 65535, shared by the B fields), as noise_std[c] (h * w) with *
+ * the periodic convolution (evaluated as IDFT(DFT(h) DFT(w)) with FP32 DFTs),
+ * which gives the noise the spectrum |DFT(h)|^2 (a filter
  * h = IDFT(M sqrt(R)) gives normalised Fourier coefficients of power R(k) per
  * component).  noise_std: host, 2 values.  Every save_every-th set of fields
  * (k = save_every, 2 save_every, ...) is written to traj[k / save_every - 1]

@@ -162,6 +162,65 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd(Conv cv, int M, int npix,
     }
 }
 
+// The same convolution for c_in = CIN in {16, 32}, where every chunk of 16
+// K values lies within one tap: the 9 neighbour pixels are found once per tile
+// and all 9 CIN / 16 activation loads are issued before the matrix-core chain
+// (same products, same accumulation order as k_conv_fwd).
+template <int CIN, bool LAST>
+__global__ __launch_bounds__(kThreads) void k_conv_fwd_c(Conv cv, int M, int npix,
+                                                          const unsigned short* __restrict__ X,
+                                                          const unsigned short* __restrict__ Wf,
+                                                          const float* __restrict__ bias,
+                                                          unsigned short* Xnext,
+                                                          const float* __restrict__ u, float* pred) {
+    static_assert(CIN % 16 == 0, "CIN must be a multiple of 16");
+    constexpr int CH = CIN / 16;  // chunks per tap
+    const int tile = blockIdx.x * (kThreads / kWaveN) + threadIdx.x / kWaveN;
+    if (tile * 16 >= npix) return;
+    const int lane = threadIdx.x & (kWaveN - 1), r16 = lane & 15, g = lane >> 4;
+    const int pa = tile * 16 + r16;
+    const int M2 = M * M;
+    const int b = pa / M2, rr = pa - b * M2;
+    const int y = rr / M, x = rr - y * M;
+    const int ys[3] = {y == 0 ? M - 1 : y - 1, y, y == M - 1 ? 0 : y + 1};
+    const int xs[3] = {x == 0 ? M - 1 : x - 1, x, x == M - 1 ? 0 : x + 1};
+    bf16x4 a[9 * CH];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const size_t q = (size_t)b * M2 + ys[tap / 3] * M + xs[tap % 3];
+#pragma unroll
+        for (int h = 0; h < CH; ++h)
+            a[tap * CH + h] = *reinterpret_cast<const bf16x4*>(X + q * CIN + h * 16 + 4 * g);
+    }
+    const int nct = cv.cout16 / 16;
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 9 * CH; ++i) {
+        const int k = i * 16 + 4 * g;  // = tap CIN + channel
+        const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(Wf + (size_t)r16 * cv.Kpad + k);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b0, acc0, 0, 0, 0);
+        if (nct > 1) {
+            const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(Wf + (size_t)(16 + r16) * cv.Kpad + k);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b1, acc1, 0, 0, 0);
+        }
+    }
+    for (int ct = 0; ct < nct; ++ct) {
+        const int o = ct * 16 + r16;
+        if (o >= cv.cout) continue;
+        const f32x4 acc = ct == 0 ? acc0 : acc1;
+        const float bo = bias[o];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = tile * 16 + 4 * g + i;
+            const float z = acc[i] + bo;
+            if (LAST)
+                pred[2 * (size_t)p + o] = u[2 * (size_t)p + o] + z;
+            else
+                Xnext[(size_t)p * cv.cout + o] = to_bf16(fmaxf(z, 0.f));
+        }
+    }
+}
+
 // ---- loss --------------------------------------------------------------------------
 
 // d = pred - target; loss partials sum d^2 (FP64, per block); the gradient of
@@ -340,50 +399,117 @@ __global__ void k_noise(int n, const float* __restrict__ pred, float s0, float s
     X[(size_t)(t >> 1) * cin + (t & 1)] = to_bf16(v);
 }
 
-// White noise w[point][component] = alpha(point, component, step) for the
-// coloured rollout noise.
-__global__ void k_white(int n, uint32_t step, uint32_t k0, uint32_t k1, float* w) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const uint4 r = dpd::philox4x32_10(make_uint4((uint32_t)(t >> 1), (uint32_t)(t & 1), step, 0u), k0, k1);
-    w[t] = dpd::alpha_from_words(0, make_uint2(r.x, r.y));
+constexpr int kColourMaxM = 64;  // largest grid side of a filtered rollout
+
+// ---- coloured rollout noise -----------------------------------------------------
+// noise = s_c (h * w) for the periodic convolution *, computed as
+// IDFT(DFT(h) DFT(w)) with FP32 direct DFTs of length M along rows and columns
+// (O(M^3) per field instead of O(M^4)); twiddles tw[m] = e^{-2 pi i m / M}
+// from an LDS table.  One block per (row or column, field), 2 M threads:
+// thread t = 2 index + component.  All sums run in a fixed order.
+
+__device__ __forceinline__ void twiddle_table(int M, float2* tw) {
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        float sn, cs;
+        sincospif(2.0f * (float)m / (float)M, &sn, &cs);
+        tw[m] = make_float2(cs, -sn);
+    }
 }
 
-// u_next[x][c] = pred[x][c] + s_c sum_y h[x - y] w[y][c] (periodic) for field
-// blockIdx.y of a batch, h and that field's w staged in LDS (M <= 64: 48 KB),
-// one thread per (point, component); u_next also goes to X as in k_noise.
-constexpr int kColourMaxM = 64;
-__global__ __launch_bounds__(kThreads) void k_colour(int M, const float* __restrict__ h,
-                                                      const float* __restrict__ w,
-                                                      const float* __restrict__ pred, float s0,
-                                                      float s1, float* unext, int cin,
-                                                      unsigned short* X) {
-    __shared__ float sh[kColourMaxM * kColourMaxM];
-    __shared__ float sw[kColourMaxM * kColourMaxM * 2];
-    const int M2 = M * M;
-    const size_t f0 = (size_t)blockIdx.y * 2 * M2;  // first value of this field
-    for (int i = threadIdx.x; i < M2; i += kThreads) sh[i] = h[i];
-    for (int i = threadIdx.x; i < 2 * M2; i += kThreads) sw[i] = w[f0 + i];
+// Hhat[l][k] = sum_{j,i} h[j][i] tw[(l j + k i) mod M], once per rollout.
+__global__ __launch_bounds__(kThreads) void k_filter_hat(int M, const float* __restrict__ h, float2* Hhat) {
+    __shared__ float2 tw[kColourMaxM];
+    twiddle_table(M, tw);
     __syncthreads();
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;  // 2 point + component
-    if (t >= 2 * M2) return;
-    const int c = t & 1, p = t >> 1;
-    const int y = p / M, x = p - y * M;
-    float acc = 0.f;
-    for (int yy = 0; yy < M; ++yy) {
-        int dy = y - yy;
-        dy += dy < 0 ? M : 0;
-        const float* hr = sh + dy * M;
-        const float* wr = sw + 2 * yy * M + c;
-        for (int xx = 0; xx < M; ++xx) {
-            int dx = x - xx;
-            dx += dx < 0 ? M : 0;
-            acc = fmaf(hr[dx], wr[2 * xx], acc);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M * M) return;
+    const int l = t / M, k = t - l * M;
+    float re = 0.f, im = 0.f;
+    for (int j = 0; j < M; ++j)
+        for (int i = 0; i < M; ++i) {
+            const float2 e = tw[(l * j + k * i) % M];
+            const float v = h[j * M + i];
+            re = fmaf(v, e.x, re);
+            im = fmaf(v, e.y, im);
         }
+    Hhat[t] = make_float2(re, im);
+}
+
+// Row j of field b: white numbers w[j][i][c] = alpha(b M^2 + j M + i, c, step)
+// (Philox4x32-10 and Box-Muller, as k_noise), then A[b][j][k][c] =
+// sum_i w[j][i][c] tw[k i mod M].
+__global__ void k_colour_rows(int M, uint32_t step, uint32_t k0, uint32_t k1, float2* A) {
+    __shared__ float2 tw[kColourMaxM];
+    __shared__ float sw[2 * kColourMaxM];
+    const int j = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    twiddle_table(M, tw);
+    const uint32_t point = (uint32_t)(((size_t)b * M + j) * M + (t >> 1));
+    const uint4 r = dpd::philox4x32_10(make_uint4(point, (uint32_t)(t & 1), step, 0u), k0, k1);
+    sw[t] = dpd::alpha_from_words(0, make_uint2(r.x, r.y));
+    __syncthreads();
+    const int k = t >> 1, c = t & 1;
+    float re = 0.f, im = 0.f;
+    for (int i = 0; i < M; ++i) {
+        const float2 e = tw[(k * i) % M];
+        const float v = sw[2 * i + c];
+        re = fmaf(v, e.x, re);
+        im = fmaf(v, e.y, im);
     }
-    const float v = pred[f0 + t] + (c ? s1 : s0) * acc;
-    unext[f0 + t] = v;
-    X[((size_t)blockIdx.y * M2 + p) * cin + c] = to_bf16(v);
+    A[(((size_t)b * M + j) * M + k) * 2 + c] = make_float2(re, im);
+}
+
+// Column k of field b: the column DFT, times Hhat, and the inverse column
+// DFT (without its 1/M), in place: A[b][j][k][c] <- sum_l conj(tw[l j])
+// Hhat[l][k] sum_j' A[b][j'][k][c] tw[l j'].
+__global__ void k_colour_cols(int M, const float2* __restrict__ Hhat, float2* A) {
+    __shared__ float2 tw[kColourMaxM];
+    __shared__ float2 sa[2 * kColourMaxM], sb[2 * kColourMaxM];
+    const int k = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    const int q = t >> 1, c = t & 1;
+    twiddle_table(M, tw);
+    float2* col = A + ((size_t)b * M * M + k) * 2 + c;  // + 2 M row
+    sa[t] = col[(size_t)2 * M * q];
+    __syncthreads();
+    float re = 0.f, im = 0.f;  // forward: l = q
+    for (int jj = 0; jj < M; ++jj) {
+        const float2 e = tw[(q * jj) % M], z = sa[2 * jj + c];
+        re = fmaf(z.x, e.x, fmaf(-z.y, e.y, re));
+        im = fmaf(z.y, e.x, fmaf(z.x, e.y, im));
+    }
+    const float2 hh = Hhat[q * M + k];
+    sb[t] = make_float2(re * hh.x - im * hh.y, re * hh.y + im * hh.x);
+    __syncthreads();
+    re = 0.f;
+    im = 0.f;  // inverse: j = q
+    for (int l = 0; l < M; ++l) {
+        const float2 e = tw[(l * q) % M], z = sb[2 * l + c];
+        re = fmaf(z.x, e.x, fmaf(z.y, e.y, re));
+        im = fmaf(z.y, e.x, fmaf(-z.x, e.y, im));
+    }
+    col[(size_t)2 * M * q] = make_float2(re, im);
+}
+
+// Row j of field b: the inverse row DFT's real part over M^2 is the noise;
+// u_next = pred + s_c noise, also written to the next input X as in k_noise.
+__global__ void k_colour_out(int M, const float2* __restrict__ A, const float* __restrict__ pred,
+                             float s0, float s1, float* unext, int cin, unsigned short* X) {
+    __shared__ float2 tw[kColourMaxM];
+    __shared__ float2 sa[2 * kColourMaxM];
+    const int j = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    twiddle_table(M, tw);
+    sa[t] = A[((size_t)b * M + j) * M * 2 + t];
+    __syncthreads();
+    const int i = t >> 1, c = t & 1;
+    float re = 0.f;
+    for (int k = 0; k < M; ++k) {
+        const float2 e = tw[(k * i) % M], z = sa[2 * k + c];
+        re = fmaf(z.x, e.x, fmaf(z.y, e.y, re));
+    }
+    const float inv = 1.0f / (float)(M * M);
+    const size_t p = ((size_t)b * M + j) * M + i;
+    const float v = pred[2 * p + c] + (c ? s1 : s0) * (re * inv);
+    unext[2 * p + c] = v;
+    X[p * cin + c] = to_bf16(v);
 }
 
 // ---- field statistics ------------------------------------------------------------
@@ -608,13 +734,14 @@ int forward(dpd_nn* h, const float* u, const float* cond, int B, float* pred, bo
         const unsigned short* X = at<unsigned short>(h, n.o_x[l]);
         const unsigned short* Wf = at<unsigned short>(h, n.o_wf[l]);
         const float* b = at<float>(h, n.o_w + 4 * n.boff[l]);
-        if (l + 1 == n.conv.size())
-            hipLaunchKernelGGL(k_conv_fwd<true>, dim3(grid), dim3(kThreads), 0, h->stream, c, M, npix,
-                               X, Wf, b, (unsigned short*)nullptr, u, pred);
-        else
-            hipLaunchKernelGGL(k_conv_fwd<false>, dim3(grid), dim3(kThreads), 0, h->stream, c, M,
-                               npix, X, Wf, b, at<unsigned short>(h, n.o_x[l + 1]),
-                               (const float*)nullptr, (float*)nullptr);
+        const bool last = l + 1 == n.conv.size();
+        unsigned short* Xn = last ? nullptr : at<unsigned short>(h, n.o_x[l + 1]);
+        const float* uu = last ? u : nullptr;
+        float* pp = last ? pred : nullptr;
+        auto kern = last ? k_conv_fwd<true> : k_conv_fwd<false>;
+        if (c.cin == 32) kern = last ? k_conv_fwd_c<32, true> : k_conv_fwd_c<32, false>;
+        if (c.cin == 16) kern = last ? k_conv_fwd_c<16, true> : k_conv_fwd_c<16, false>;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, h->stream, c, M, npix, X, Wf, b, Xn, uu, pp);
     }
     NLAUNCH(h);
     return DPD_OK;
@@ -833,16 +960,25 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
                            n.p.c_in, (const float*)ucur, cond, X0);
         NLAUNCH(nn);
         const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+        // filtered noise: DFT(h) once; the fields' spectra in a free buffer
+        float2* Aw = at<float2>(nn, n.o_dz[0]);  // [B][M][M][2] complex
+        float2* Hh = at<float2>(nn, n.o_dz[1]);  // [M][M] complex
+        if (noise_filter) {
+            hipLaunchKernelGGL(k_filter_hat, dim3(blocks(M2)), dim3(kThreads), 0, nn->stream, n.p.M,
+                               noise_filter, Hh);
+            NLAUNCH(nn);
+        }
         for (int s = 1; s <= steps; ++s) {
             rc = forward(nn, ucur, nullptr, B, pred, true);
             if (rc) return rc;
             if (noise_filter) {
-                float* w = at<float>(nn, n.o_dz[0]);  // free while rolling out
-                hipLaunchKernelGGL(k_white, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream, nf,
-                                   (uint32_t)s, k0, k1, w);
-                hipLaunchKernelGGL(k_colour, dim3(blocks(2 * M2), B), dim3(kThreads), 0, nn->stream,
-                                   n.p.M, noise_filter, (const float*)w, (const float*)pred,
-                                   noise_std[0], noise_std[1], ucur, n.p.c_in, X0);
+                hipLaunchKernelGGL(k_colour_rows, dim3(n.p.M, B), dim3(2 * n.p.M), 0, nn->stream, n.p.M,
+                                   (uint32_t)s, k0, k1, Aw);
+                hipLaunchKernelGGL(k_colour_cols, dim3(n.p.M, B), dim3(2 * n.p.M), 0, nn->stream, n.p.M,
+                                   (const float2*)Hh, Aw);
+                hipLaunchKernelGGL(k_colour_out, dim3(n.p.M, B), dim3(2 * n.p.M), 0, nn->stream, n.p.M,
+                                   (const float2*)Aw, (const float*)pred, noise_std[0], noise_std[1],
+                                   ucur, n.p.c_in, X0);
             } else {
                 hipLaunchKernelGGL(k_noise, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream, nf,
                                    (const float*)pred, noise_std[0], noise_std[1], (uint32_t)s, k0,
