@@ -459,7 +459,7 @@ void launch_pair_kernel(dpd_handle* h, const PairArgs& b, int reduce) {
 template <int MODE, bool BATCH>
 void launch_overflow(dpd_handle* h, const PairArgs& b, int reduce) {
     // tiles over an LDS capacity (dense clusters), if any
-    const int Go = (int)std::min<long long>(h->d.tiles, 64);
+    const int Go = (int)std::min<long long>(h->d.tiles, 512);
     hipLaunchKernelGGL((k_pair_overflow<MODE, BATCH>), dim3(Go), dim3(kWave), 0, h->stream, P0(h),
                        b, reduce);
 }

@@ -13,6 +13,7 @@ the first ten shells, Eq. 5.13) and the shell of its maximum.
 from __future__ import annotations
 
 import math
+import time
 
 import numpy as np
 import torch
@@ -47,13 +48,20 @@ def run(device, warm: int, steps: int, every: int, log=print):
     sim = dpd.Sim(cfgs, device=device)
     sim.set_state(torch.from_numpy(x).to(device), torch.from_numpy(v).to(device), 0)
     sim.set_graph_chunk(100)
-    sim.step(warm)
+    t0 = time.perf_counter()
+    for w0 in range(0, warm, 20000):
+        sim.step(min(20000, warm - w0))
+        sim.sync()
+        log(f"warm-up: {min(w0 + 20000, warm)} of {warm} steps, {time.perf_counter() - t0:.1f} s")
     R = len(cfgs)
     nsnap = steps // every
     fields = torch.empty((nsnap, R, M, M, 2), dtype=torch.float32, device=device)
     counts = torch.empty((R, M, M), dtype=torch.int32, device=device)
     for s in range(nsnap):
         sim.step(every)
+        if (s + 1) % 20 == 0:
+            sim.sync()
+            log(f"snapshot {s + 1} of {nsnap}, {time.perf_counter() - t0:.1f} s")
         # windows of eps = L sqrt(10 / N) per replica: one call per replica's eps
         for q, c in enumerate(cfgs):
             eps = c["L"] * math.sqrt(10.0 / c["n_agents"])
