@@ -50,11 +50,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the pair kernel from the committed rocprofv3
-    counter summary (lines "key: value"), if it was taken with the current
-    kernel sources."""
-    path = os.path.join(ROOT, "profiles", "pair_kernel_dimers_4M_counters.txt")
+def _profile_fields(name: str):
+    """"key: value" lines of a committed profile summary, or None when the file
+    is missing or was taken with other kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     d = {}
@@ -65,9 +64,40 @@ def measured_traffic():
                 d[k.strip()] = val.strip()
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
+    return d
+
+
+def measured_traffic():
+    """HBM bytes per launch of the pair kernel from the committed rocprofv3
+    counter summary, if it was taken with the current kernel sources."""
+    d = _profile_fields("pair_kernel_dimers_4M_counters.txt")
     try:
-        return float(d["hbm_bytes_per_launch"])
+        return None if d is None else float(d["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
+        return None
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes per clock (a 64-lane
+# instruction takes 4 clocks) at 2.4 GHz
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def measured_valu(avg_launch_us: float):
+    """Issued VALU lane-ops of the pair kernel per second against the issue
+    peak: the committed SQ counter summary's instructions per launch (if taken
+    with the current sources) over the launch time measured in this run."""
+    d = _profile_fields("pair_kernel_dimers_4M_valu_counters.txt")
+    if d is None:
+        return None
+    try:
+        ops = 64.0 * float(d["valu_insts_per_launch"])
+        achieved = ops / (avg_launch_us * 1e-6)
+        return {"achieved": achieved, "peak": VALU_PEAK_LANE_OPS, "unit": "lane-ops/s",
+                "frac": achieved / VALU_PEAK_LANE_OPS, "issued_lane_ops_per_launch": ops,
+                "valu_busy_pct": float(d["valu_busy_pct"]),
+                "lane_util_pct": float(d["valu_lane_util_pct"]),
+                "source": "profiles/pair_kernel_dimers_4M_valu_counters.txt"}
+    except (KeyError, ValueError, ZeroDivisionError):
         return None
 
 
@@ -532,6 +562,7 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": alg,
             "avg_launch_us": avg_us,
+            "valu": measured_valu(avg_us),
         },
         "cpu_baseline": cpu,
     }
