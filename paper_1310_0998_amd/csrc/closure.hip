@@ -163,60 +163,83 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd(Conv cv, int M, int npix,
 }
 
 // The same convolution for c_in = CIN in {16, 32}, where every chunk of 16
-// K values lies within one tap: the 9 neighbour pixels are found once per tile
-// and all 9 CIN / 16 activation loads are issued before the matrix-core chain
-// (same products, same accumulation order as k_conv_fwd).
-template <int CIN, bool LAST>
+// K values lies within one tap.  A wavefront keeps its lanes' weight operands
+// in registers and computes TPW consecutive 16-pixel tiles with them; per tile
+// the 9 neighbour pixels are found once and all 9 CIN / 16 activation loads
+// are issued before the matrix-core chain (same products, same accumulation
+// order as k_conv_fwd).  NCT: output-channel tiles (cout16 / 16).
+constexpr int kConvTPW = 4;
+template <int CIN, int NCT, bool LAST>
 __global__ __launch_bounds__(kThreads) void k_conv_fwd_c(Conv cv, int M, int npix,
                                                           const unsigned short* __restrict__ X,
                                                           const unsigned short* __restrict__ Wf,
                                                           const float* __restrict__ bias,
                                                           unsigned short* Xnext,
                                                           const float* __restrict__ u, float* pred) {
-    static_assert(CIN % 16 == 0, "CIN must be a multiple of 16");
+    static_assert(CIN % 16 == 0 && (NCT == 1 || NCT == 2), "unsupported shape");
     constexpr int CH = CIN / 16;  // chunks per tap
-    const int tile = blockIdx.x * (kThreads / kWaveN) + threadIdx.x / kWaveN;
-    if (tile * 16 >= npix) return;
+    constexpr int NK = 9 * CH;    // chunks of 16 K values
+    const int wave = blockIdx.x * (kThreads / kWaveN) + threadIdx.x / kWaveN;
+    const int ntile = npix / 16;
+    if (wave * kConvTPW >= ntile) return;
     const int lane = threadIdx.x & (kWaveN - 1), r16 = lane & 15, g = lane >> 4;
-    const int pa = tile * 16 + r16;
-    const int M2 = M * M;
-    const int b = pa / M2, rr = pa - b * M2;
-    const int y = rr / M, x = rr - y * M;
-    const int ys[3] = {y == 0 ? M - 1 : y - 1, y, y == M - 1 ? 0 : y + 1};
-    const int xs[3] = {x == 0 ? M - 1 : x - 1, x, x == M - 1 ? 0 : x + 1};
-    bf16x4 a[9 * CH];
+    bf16x4 wb[NCT][NK];
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const size_t q = (size_t)b * M2 + ys[tap / 3] * M + xs[tap % 3];
+    for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-        for (int h = 0; h < CH; ++h)
-            a[tap * CH + h] = *reinterpret_cast<const bf16x4*>(X + q * CIN + h * 16 + 4 * g);
-    }
-    const int nct = cv.cout16 / 16;
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < NK; ++i)
+            wb[ct][i] = *reinterpret_cast<const bf16x4*>(Wf + (size_t)(ct * 16 + r16) * cv.Kpad + i * 16 + 4 * g);
+    float bo[NCT];
 #pragma unroll
-    for (int i = 0; i < 9 * CH; ++i) {
-        const int k = i * 16 + 4 * g;  // = tap CIN + channel
-        const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(Wf + (size_t)r16 * cv.Kpad + k);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b0, acc0, 0, 0, 0);
-        if (nct > 1) {
-            const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(Wf + (size_t)(16 + r16) * cv.Kpad + k);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b1, acc1, 0, 0, 0);
-        }
-    }
-    for (int ct = 0; ct < nct; ++ct) {
+    for (int ct = 0; ct < NCT; ++ct) {
         const int o = ct * 16 + r16;
-        if (o >= cv.cout) continue;
-        const f32x4 acc = ct == 0 ? acc0 : acc1;
-        const float bo = bias[o];
+        bo[ct] = o < cv.cout ? bias[o] : 0.f;
+    }
+    const int M2 = M * M;
+    // activation operands of tile t: the 9 CIN / 16 chunks of its 16 pixels
+    auto load = [&](int t, bf16x4 (&dst)[NK]) {
+        const int pa = t * 16 + r16;
+        const int b = pa / M2, rr = pa - b * M2;
+        const int y = rr / M, x = rr - y * M;
+        const int ys[3] = {y == 0 ? M - 1 : y - 1, y, y == M - 1 ? 0 : y + 1};
+        const int xs[3] = {x == 0 ? M - 1 : x - 1, x, x == M - 1 ? 0 : x + 1};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int p = tile * 16 + 4 * g + i;
-            const float z = acc[i] + bo;
-            if (LAST)
-                pred[2 * (size_t)p + o] = u[2 * (size_t)p + o] + z;
-            else
-                Xnext[(size_t)p * cv.cout + o] = to_bf16(fmaxf(z, 0.f));
+        for (int tap = 0; tap < 9; ++tap) {
+            const size_t q = (size_t)b * M2 + ys[tap / 3] * M + xs[tap % 3];
+#pragma unroll
+            for (int h = 0; h < CH; ++h)
+                dst[tap * CH + h] = *reinterpret_cast<const bf16x4*>(X + q * CIN + h * 16 + 4 * g);
+        }
+    };
+    bf16x4 a[2][NK];
+    load(wave * kConvTPW, a[0]);
+#pragma unroll
+    for (int tt = 0; tt < kConvTPW; ++tt) {
+        const int tile = wave * kConvTPW + tt;
+        if (tile >= ntile) break;
+        // the next tile's loads are in flight while this one's products run
+        if (tt + 1 < kConvTPW && tile + 1 < ntile) load(tile + 1, a[(tt + 1) & 1]);
+        f32x4 acc[NCT];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < NK; ++i)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[tt & 1][i], wb[ct][i], acc[ct], 0, 0, 0);
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            const int o = ct * 16 + r16;
+            if (o >= cv.cout) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = tile * 16 + 4 * g + i;
+                const float z = acc[ct][i] + bo[ct];
+                if (LAST)
+                    pred[2 * (size_t)p + o] = u[2 * (size_t)p + o] + z;
+                else
+                    Xnext[(size_t)p * cv.cout + o] = to_bf16(fmaxf(z, 0.f));
+            }
         }
     }
 }
@@ -449,11 +472,13 @@ __global__ void k_colour_rows(int M, uint32_t step, uint32_t k0, uint32_t k1, fl
     __syncthreads();
     const int k = t >> 1, c = t & 1;
     float re = 0.f, im = 0.f;
-    for (int i = 0; i < M; ++i) {
-        const float2 e = tw[(k * i) % M];
+    for (int i = 0, m = 0; i < M; ++i) {  // m = k i mod M
+        const float2 e = tw[m];
         const float v = sw[2 * i + c];
         re = fmaf(v, e.x, re);
         im = fmaf(v, e.y, im);
+        m += k;
+        m -= (m >= M) ? M : 0;
     }
     A[(((size_t)b * M + j) * M + k) * 2 + c] = make_float2(re, im);
 }
@@ -471,20 +496,24 @@ __global__ void k_colour_cols(int M, const float2* __restrict__ Hhat, float2* A)
     sa[t] = col[(size_t)2 * M * q];
     __syncthreads();
     float re = 0.f, im = 0.f;  // forward: l = q
-    for (int jj = 0; jj < M; ++jj) {
-        const float2 e = tw[(q * jj) % M], z = sa[2 * jj + c];
+    for (int jj = 0, m = 0; jj < M; ++jj) {  // m = q jj mod M
+        const float2 e = tw[m], z = sa[2 * jj + c];
         re = fmaf(z.x, e.x, fmaf(-z.y, e.y, re));
         im = fmaf(z.y, e.x, fmaf(z.x, e.y, im));
+        m += q;
+        m -= (m >= M) ? M : 0;
     }
     const float2 hh = Hhat[q * M + k];
     sb[t] = make_float2(re * hh.x - im * hh.y, re * hh.y + im * hh.x);
     __syncthreads();
     re = 0.f;
     im = 0.f;  // inverse: j = q
-    for (int l = 0; l < M; ++l) {
-        const float2 e = tw[(l * q) % M], z = sb[2 * l + c];
+    for (int l = 0, m = 0; l < M; ++l) {  // m = l q mod M
+        const float2 e = tw[m], z = sb[2 * l + c];
         re = fmaf(z.x, e.x, fmaf(z.y, e.y, re));
         im = fmaf(z.y, e.x, fmaf(-z.x, e.y, im));
+        m += q;
+        m -= (m >= M) ? M : 0;
     }
     col[(size_t)2 * M * q] = make_float2(re, im);
 }
@@ -501,9 +530,11 @@ __global__ void k_colour_out(int M, const float2* __restrict__ A, const float* _
     __syncthreads();
     const int i = t >> 1, c = t & 1;
     float re = 0.f;
-    for (int k = 0; k < M; ++k) {
-        const float2 e = tw[(k * i) % M], z = sa[2 * k + c];
+    for (int k = 0, m = 0; k < M; ++k) {  // m = k i mod M
+        const float2 e = tw[m], z = sa[2 * k + c];
         re = fmaf(z.x, e.x, fmaf(z.y, e.y, re));
+        m += i;
+        m -= (m >= M) ? M : 0;
     }
     const float inv = 1.0f / (float)(M * M);
     const size_t p = ((size_t)b * M + j) * M + i;
@@ -739,9 +770,19 @@ int forward(dpd_nn* h, const float* u, const float* cond, int B, float* pred, bo
         const float* uu = last ? u : nullptr;
         float* pp = last ? pred : nullptr;
         auto kern = last ? k_conv_fwd<true> : k_conv_fwd<false>;
-        if (c.cin == 32) kern = last ? k_conv_fwd_c<32, true> : k_conv_fwd_c<32, false>;
-        if (c.cin == 16) kern = last ? k_conv_fwd_c<16, true> : k_conv_fwd_c<16, false>;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, h->stream, c, M, npix, X, Wf, b, Xn, uu, pp);
+        int g = grid;
+        if (c.cin == 32 || c.cin == 16) {
+            const int nct = c.cout16 / 16;
+            if (c.cin == 32)
+                kern = last ? (nct == 1 ? k_conv_fwd_c<32, 1, true> : k_conv_fwd_c<32, 2, true>)
+                            : (nct == 1 ? k_conv_fwd_c<32, 1, false> : k_conv_fwd_c<32, 2, false>);
+            else
+                kern = last ? (nct == 1 ? k_conv_fwd_c<16, 1, true> : k_conv_fwd_c<16, 2, true>)
+                            : (nct == 1 ? k_conv_fwd_c<16, 1, false> : k_conv_fwd_c<16, 2, false>);
+            const int waves = (ntile + kConvTPW - 1) / kConvTPW;
+            g = (waves + kThreads / kWaveN - 1) / (kThreads / kWaveN);
+        }
+        hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, h->stream, c, M, npix, X, Wf, b, Xn, uu, pp);
     }
     NLAUNCH(h);
     return DPD_OK;
