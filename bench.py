@@ -12,7 +12,8 @@ With --workload sweep64 it instead times the batched parameter sweep: 64
 replicas of uneven size advanced together, against the same systems run one
 after another; with --workload closure it trains the learned closure on
 DPD-generated fields and times its rollout against plain DPD (each prints one
-JSON line of its own).
+JSON line of its own); --workload paper runs the paper's own parameter set
+and --workload rollout times the closure's batched rollout alone.
 """
 from __future__ import annotations
 
@@ -356,6 +357,60 @@ def run_closure(args):
     _ = np
 
 
+def run_rollout(args):
+    """The closure's batched rollout alone: B = 32 fields of 64 x 64 through the
+    4-layer, 32-channel network for 200 steps, with white and with filtered
+    noise (seeded random weights and fields; the timing does not depend on
+    their values)."""
+    import numpy as np
+    import torch
+
+    from paper_1310_0998_amd import closure, inputs
+
+    dev = torch.device("cuda:0")
+    M, B, steps = 64, 32, args.rollout_steps
+    net = closure.Closure(M, c_in=4, width=32, layers=4, max_batch=B, device=dev)
+    net.set_weights(torch.from_numpy(inputs.closure_init(601, 4, 32, 4)).to(dev))
+    rng = np.random.Generator(np.random.PCG64(17))
+    u0 = torch.from_numpy((0.1 * rng.standard_normal((B, M, M, 2))).astype(np.float32)).to(dev)
+    cond = torch.full((B, 2), 0.5, dtype=torch.float32, device=dev)
+    ii = np.arange(M)
+    d = np.minimum(ii, M - ii).astype(np.float64)
+    h = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / 4.5)
+    h = torch.from_numpy((h / np.sqrt((h * h).sum())).astype(np.float32)).to(dev)
+    res = {}
+    for name, filt in (("white", None), ("filtered", h)):
+        net.rollout(u0, cond, 5, (0.05, 0.05), seed=1, noise_filter=filt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net.rollout(u0, cond, steps, (0.05, 0.05), seed=2, noise_filter=filt)
+        torch.cuda.synchronize()
+        res[name] = 1e6 * (time.perf_counter() - t0) / steps
+        log(f"{name}: {res[name]:.1f} us per batched step")
+    net.close()
+    # multiply-adds per pixel of the four 3 x 3 convolutions (4 -> 32 -> 32 -> 32 -> 2)
+    macs = 9 * (4 * 32 + 32 * 32 + 32 * 32 + 32 * 2)
+    flops = 2.0 * macs * B * M * M
+    line = {
+        "metric": "closure rollout: us per batched step (B=32, 64x64, 4x32 conv)",
+        "value": res["filtered"],
+        "unit": "us/step",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 5,
+        "higher_is_better": False,
+        "dtype": "bf16 matmul inputs, f32 accumulate",
+        "data": "synthetic (seeded random weights and fields)",
+        "config": {"workload": "closure rollout, B=32 fields of 64x64, 4 periodic 3x3 convolutions "
+                               "(4->32->32->32->2 channels), filtered noise (h = periodic Gaussian)",
+                   "parallelism": "single-gpu"},
+        "white_noise_us_per_step": res["white"],
+        "conv_flops_per_step": flops,
+        "step_tflops_white": flops / (res["white"] * 1e-6) / 1e12,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_paper(args):
     """The paper's own parameter set as one batch (Sec. 5.1), with the energy
     spectrum statistics of Sec. 5.4 computed on the GPU and the paper's
@@ -427,6 +482,8 @@ def main():
                     help="DPD warm-up steps of each ensemble before its fields are taken")
     ap.add_argument("--closure-steps", type=int, default=2000,
                     help="closure steps of the judged rollout (x50 DPD steps)")
+    ap.add_argument("--rollout-steps", type=int, default=200,
+                    help="batched closure steps (workload rollout)")
     ap.add_argument("--paper-warm", type=int, default=100000)
     ap.add_argument("--paper-steps", type=int, default=200000)
     ap.add_argument("--paper-every", type=int, default=2000)
@@ -443,6 +500,9 @@ def main():
         return
     if args.workload == "paper":
         run_paper(args)
+        return
+    if args.workload == "rollout":
+        run_rollout(args)
         return
 
     import numpy as np
