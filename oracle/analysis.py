@@ -1,7 +1,7 @@
 """Statistics of the filtered velocity field and of agent velocities
 (Sec. 5.3 and Sec. 5.4 of the paper), written as plain numpy definitions.
 
-TEST INFRASTRUCTURE ONLY (the judge of long-run statistics); the engine's hot
+TEST INFRASTRUCTURE ONLY (the reference for long-run statistics); the engine's hot
 path ends at the binned field u_M.
 
 Readings where the paper is silent or garbled:

@@ -162,12 +162,15 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd(Conv cv, int M, int npix,
     }
 }
 
-// The same convolution for c_in = CIN in {16, 32}, where every chunk of 16
-// K values lies within one tap.  A wavefront keeps its lanes' weight operands
-// in registers and computes TPW consecutive 16-pixel tiles with them; per tile
-// the 9 neighbour pixels are found once and all 9 CIN / 16 activation loads
-// are issued before the matrix-core chain (same products, same accumulation
-// order as k_conv_fwd).  NCT: output-channel tiles (cout16 / 16).
+// The same convolution for c_in = CIN in {4, 16, 32}.  At CIN >= 16 every
+// chunk of 16 K values lies within one tap; at CIN = 4 a lane group's 4 K
+// values are the 4 channels of one tap (K = 36, padded to 48 with zero
+// activations).  A wavefront keeps its lanes' weight operands in registers and
+// computes kConvTPW consecutive 16-pixel tiles with them; per tile the
+// neighbour pixels are found once and all activation loads are issued before
+// the matrix-core chain, the next tile's loads overlapping this tile's
+// products (same products, same accumulation order as k_conv_fwd).  NCT:
+// output-channel tiles (cout16 / 16).
 constexpr int kConvTPW = 4;
 template <int CIN, int NCT, bool LAST>
 __global__ __launch_bounds__(kThreads) void k_conv_fwd_c(Conv cv, int M, int npix,
@@ -176,9 +179,9 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_c(Conv cv, int M, int npi
                                                           const float* __restrict__ bias,
                                                           unsigned short* Xnext,
                                                           const float* __restrict__ u, float* pred) {
-    static_assert(CIN % 16 == 0 && (NCT == 1 || NCT == 2), "unsupported shape");
-    constexpr int CH = CIN / 16;  // chunks per tap
-    constexpr int NK = 9 * CH;    // chunks of 16 K values
+    static_assert((CIN == 4 || CIN % 16 == 0) && (NCT == 1 || NCT == 2), "unsupported shape");
+    constexpr int CH = CIN >= 16 ? CIN / 16 : 1;  // chunks per tap (CIN >= 16)
+    constexpr int NK = CIN >= 16 ? 9 * CH : 3;    // chunks of 16 K values (K = 36 padded to 48 at CIN = 4)
     const int wave = blockIdx.x * (kThreads / kWaveN) + threadIdx.x / kWaveN;
     const int ntile = npix / 16;
     if (wave * kConvTPW >= ntile) return;
@@ -196,19 +199,35 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_c(Conv cv, int M, int npi
         bo[ct] = o < cv.cout ? bias[o] : 0.f;
     }
     const int M2 = M * M;
-    // activation operands of tile t: the 9 CIN / 16 chunks of its 16 pixels
+    // activation operands of tile t: the NK chunks of its 16 pixels
     auto load = [&](int t, bf16x4 (&dst)[NK]) {
         const int pa = t * 16 + r16;
         const int b = pa / M2, rr = pa - b * M2;
         const int y = rr / M, x = rr - y * M;
         const int ys[3] = {y == 0 ? M - 1 : y - 1, y, y == M - 1 ? 0 : y + 1};
         const int xs[3] = {x == 0 ? M - 1 : x - 1, x, x == M - 1 ? 0 : x + 1};
+        if constexpr (CIN == 4) {
+            // chunk i, lane group g: the 4 channels of tap 4 i + g (zero past tap 8)
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const size_t q = (size_t)b * M2 + ys[tap / 3] * M + xs[tap % 3];
+            for (int i = 0; i < NK; ++i) {
+                const int tap = 4 * i + g;
+                dst[i] = bf16x4{0, 0, 0, 0};
+                if (tap < 9) {
+                    const int ty = tap / 3, tx = tap - 3 * ty;
+                    const int yy = ty == 0 ? ys[0] : (ty == 1 ? ys[1] : ys[2]);
+                    const int xx = tx == 0 ? xs[0] : (tx == 1 ? xs[1] : xs[2]);
+                    const size_t q = (size_t)b * M2 + yy * M + xx;
+                    dst[i] = *reinterpret_cast<const bf16x4*>(X + q * 4);
+                }
+            }
+        } else {
 #pragma unroll
-            for (int h = 0; h < CH; ++h)
-                dst[tap * CH + h] = *reinterpret_cast<const bf16x4*>(X + q * CIN + h * 16 + 4 * g);
+            for (int tap = 0; tap < 9; ++tap) {
+                const size_t q = (size_t)b * M2 + ys[tap / 3] * M + xs[tap % 3];
+#pragma unroll
+                for (int h = 0; h < CH; ++h)
+                    dst[tap * CH + h] = *reinterpret_cast<const bf16x4*>(X + q * CIN + h * 16 + 4 * g);
+            }
         }
     };
     bf16x4 a[2][NK];
@@ -771,9 +790,12 @@ int forward(dpd_nn* h, const float* u, const float* cond, int B, float* pred, bo
         float* pp = last ? pred : nullptr;
         auto kern = last ? k_conv_fwd<true> : k_conv_fwd<false>;
         int g = grid;
-        if (c.cin == 32 || c.cin == 16) {
+        if (c.cin == 32 || c.cin == 16 || c.cin == 4) {
             const int nct = c.cout16 / 16;
-            if (c.cin == 32)
+            if (c.cin == 4)
+                kern = last ? (nct == 1 ? k_conv_fwd_c<4, 1, true> : k_conv_fwd_c<4, 2, true>)
+                            : (nct == 1 ? k_conv_fwd_c<4, 1, false> : k_conv_fwd_c<4, 2, false>);
+            else if (c.cin == 32)
                 kern = last ? (nct == 1 ? k_conv_fwd_c<32, 1, true> : k_conv_fwd_c<32, 2, true>)
                             : (nct == 1 ? k_conv_fwd_c<32, 1, false> : k_conv_fwd_c<32, 2, false>);
             else
