@@ -479,7 +479,8 @@ __global__ __launch_bounds__(kThreads) void k_filter_hat(int M, const float* __r
 
 // Row j of field b: white numbers w[j][i][c] = alpha(b M^2 + j M + i, c, step)
 // (Philox4x32-10 and Box-Muller, as k_noise), then A[b][j][k][c] =
-// sum_i w[j][i][c] tw[k i mod M].
+// sum_i w[j][i][c] tw[k i mod M] for k <= M / 2 (the rest of a real field's
+// spectrum is conjugate to it).
 __global__ void k_colour_rows(int M, uint32_t step, uint32_t k0, uint32_t k1, float2* A) {
     __shared__ float2 tw[kColourMaxM];
     __shared__ float sw[2 * kColourMaxM];
@@ -490,6 +491,7 @@ __global__ void k_colour_rows(int M, uint32_t step, uint32_t k0, uint32_t k1, fl
     sw[t] = dpd::alpha_from_words(0, make_uint2(r.x, r.y));
     __syncthreads();
     const int k = t >> 1, c = t & 1;
+    if (k > M / 2) return;
     float re = 0.f, im = 0.f;
     for (int i = 0, m = 0; i < M; ++i) {  // m = k i mod M
         const float2 e = tw[m];
@@ -502,8 +504,8 @@ __global__ void k_colour_rows(int M, uint32_t step, uint32_t k0, uint32_t k1, fl
     A[(((size_t)b * M + j) * M + k) * 2 + c] = make_float2(re, im);
 }
 
-// Column k of field b: the column DFT, times Hhat, and the inverse column
-// DFT (without its 1/M), in place: A[b][j][k][c] <- sum_l conj(tw[l j])
+// Column k <= M / 2 of field b: the column DFT, times Hhat, and the inverse
+// column DFT (without its 1/M), in place: A[b][j][k][c] <- sum_l conj(tw[l j])
 // Hhat[l][k] sum_j' A[b][j'][k][c] tw[l j'].
 __global__ void k_colour_cols(int M, const float2* __restrict__ Hhat, float2* A) {
     __shared__ float2 tw[kColourMaxM];
@@ -539,13 +541,21 @@ __global__ void k_colour_cols(int M, const float2* __restrict__ Hhat, float2* A)
 
 // Row j of field b: the inverse row DFT's real part over M^2 is the noise;
 // u_next = pred + s_c noise, also written to the next input X as in k_noise.
+// h and w are real, so the filtered spectrum is Hermitian and so is each row
+// of its inverse column transform: C[j][M - k] = conj(C[j][k]) fills the
+// columns past M / 2.
 __global__ void k_colour_out(int M, const float2* __restrict__ A, const float* __restrict__ pred,
                              float s0, float s1, float* unext, int cin, unsigned short* X) {
     __shared__ float2 tw[kColourMaxM];
     __shared__ float2 sa[2 * kColourMaxM];
     const int j = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
     twiddle_table(M, tw);
-    sa[t] = A[((size_t)b * M + j) * M * 2 + t];
+    {
+        const int k = t >> 1, c = t & 1;
+        const int kk = k <= M / 2 ? k : M - k;
+        const float2 z = A[(((size_t)b * M + j) * M + kk) * 2 + c];
+        sa[t] = k <= M / 2 ? z : make_float2(z.x, -z.y);
+    }
     __syncthreads();
     const int i = t >> 1, c = t & 1;
     float re = 0.f;
@@ -1037,8 +1047,8 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
             if (noise_filter) {
                 hipLaunchKernelGGL(k_colour_rows, dim3(n.p.M, B), dim3(2 * n.p.M), 0, nn->stream, n.p.M,
                                    (uint32_t)s, k0, k1, Aw);
-                hipLaunchKernelGGL(k_colour_cols, dim3(n.p.M, B), dim3(2 * n.p.M), 0, nn->stream, n.p.M,
-                                   (const float2*)Hh, Aw);
+                hipLaunchKernelGGL(k_colour_cols, dim3(n.p.M / 2 + 1, B), dim3(2 * n.p.M), 0, nn->stream,
+                                   n.p.M, (const float2*)Hh, Aw);
                 hipLaunchKernelGGL(k_colour_out, dim3(n.p.M, B), dim3(2 * n.p.M), 0, nn->stream, n.p.M,
                                    (const float2*)Aw, (const float*)pred, noise_std[0], noise_std[1],
                                    ucur, n.p.c_in, X0);
