@@ -263,6 +263,109 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_c(Conv cv, int M, int npi
     }
 }
 
+// The convolution for CIN in {16, 32} on grids with M in {16, 32, 64}, with
+// its operands staged in LDS: a block of 4 wavefronts computes kLdsPix
+// consecutive pixels (kLdsPix / M whole rows of one field).  It stages those
+// rows and one halo row on each side (periodic), all M columns, and the
+// layer's BF16 weights; both layouts are padded by 8 elements per pixel or
+// output channel so that the 16 pixels (or channels) a matrix-core operand
+// load spans fall in different LDS banks.  Each wavefront then computes
+// kLdsPix / 64 tiles from LDS, with its weight operands held in registers.
+// Same products and accumulation order as k_conv_fwd.
+constexpr int kLdsPix = 256;
+template <int CIN, int NCT, bool LAST>
+__global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npix,
+                                                          const unsigned short* __restrict__ X,
+                                                          const unsigned short* __restrict__ Wf,
+                                                          const float* __restrict__ bias,
+                                                          unsigned short* Xnext,
+                                                          const float* __restrict__ u, float* pred) {
+    static_assert(CIN % 16 == 0 && (NCT == 1 || NCT == 2), "unsupported shape");
+    constexpr int CH = CIN / 16, NK = 9 * CH, K = 9 * CIN;
+    constexpr int XS = CIN + 8;  // staged elements per pixel
+    constexpr int WS = K + 8;    // staged elements per output channel
+    constexpr int kRowsMax = kLdsPix / 16 + 2;  // staged rows at M = 16
+    __shared__ __align__(16) unsigned short sx[kRowsMax * 16 * XS > (kLdsPix / 64 + 2) * 64 * XS
+                                                   ? kRowsMax * 16 * XS
+                                                   : (kLdsPix / 64 + 2) * 64 * XS];
+    __shared__ __align__(16) unsigned short sw[NCT * 16 * WS];
+    const int p0 = blockIdx.x * kLdsPix;
+    if (p0 >= npix) return;
+    const int M2 = M * M, R = kLdsPix / M;
+    const int b = p0 / M2, y0 = (p0 - b * M2) / M;
+    // stage rows y0 - 1 .. y0 + R (periodic) in 16-byte vectors
+    const int nvec = (R + 2) * M * CIN / 8;
+    for (int t = threadIdx.x; t < nvec; t += kThreads) {
+        const int e = t * 8, pix = e / CIN, c = e - pix * CIN;  // staged pixel, channel
+        const int rr = pix / M, xx = pix - rr * M;
+        int yy = y0 - 1 + rr;
+        yy += (yy < 0) ? M : 0;
+        yy -= (yy >= M) ? M : 0;
+        const uint4 v = *reinterpret_cast<const uint4*>(X + (((size_t)b * M2 + (size_t)yy * M + xx) * CIN + c));
+        *reinterpret_cast<uint4*>(sx + pix * XS + c) = v;
+    }
+    // the weights of the NCT * 16 output channels (rows of Wf, K = Kpad here)
+    const int wvec = NCT * 16 * K / 8;
+    for (int t = threadIdx.x; t < wvec; t += kThreads) {
+        const int e = t * 8, o = e / K, k = e - o * K;
+        *reinterpret_cast<uint4*>(sw + o * WS + k) =
+            *reinterpret_cast<const uint4*>(Wf + (size_t)o * cv.Kpad + k);
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / kWaveN, lane = threadIdx.x & (kWaveN - 1);
+    const int r16 = lane & 15, g = lane >> 4;
+    bf16x4 wb[NCT][NK];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int i = 0; i < NK; ++i)
+            wb[ct][i] = *reinterpret_cast<const bf16x4*>(sw + (ct * 16 + r16) * WS + i * 16 + 4 * g);
+    float bo[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+        const int o = ct * 16 + r16;
+        bo[ct] = o < cv.cout ? bias[o] : 0.f;
+    }
+    constexpr int TPW = kLdsPix / 16 / (kThreads / kWaveN);
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+        const int tile = (p0 >> 4) + wave * TPW + tt;
+        const int lp = (wave * TPW + tt) * 16 + r16;  // pixel within the block
+        const int ly = lp / M, x = lp - ly * M;
+        const int xs[3] = {x == 0 ? M - 1 : x - 1, x, x == M - 1 ? 0 : x + 1};
+        bf16x4 a[NK];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int pix = (ly + tap / 3) * M + xs[tap % 3];  // staged row ly + dy + 1
+#pragma unroll
+            for (int h = 0; h < CH; ++h)
+                a[tap * CH + h] = *reinterpret_cast<const bf16x4*>(sx + pix * XS + h * 16 + 4 * g);
+        }
+        f32x4 acc[NCT];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < NK; ++i)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], wb[ct][i], acc[ct], 0, 0, 0);
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            const int o = ct * 16 + r16;
+            if (o >= cv.cout) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = tile * 16 + 4 * g + i;
+                const float z = acc[ct][i] + bo[ct];
+                if (LAST)
+                    pred[2 * (size_t)p + o] = u[2 * (size_t)p + o] + z;
+                else
+                    Xnext[(size_t)p * cv.cout + o] = to_bf16(fmaxf(z, 0.f));
+            }
+        }
+    }
+}
+
 // ---- loss --------------------------------------------------------------------------
 
 // d = pred - target; loss partials sum d^2 (FP64, per block); the gradient of
@@ -813,6 +916,15 @@ int forward(dpd_nn* h, const float* u, const float* cond, int B, float* pred, bo
                             : (nct == 1 ? k_conv_fwd_c<16, 1, false> : k_conv_fwd_c<16, 2, false>);
             const int waves = (ntile + kConvTPW - 1) / kConvTPW;
             g = (waves + kThreads / kWaveN - 1) / (kThreads / kWaveN);
+            if ((c.cin == 32 || c.cin == 16) && (M == 16 || M == 32 || M == 64) && npix % kLdsPix == 0) {
+                if (c.cin == 32)
+                    kern = last ? (nct == 1 ? k_conv_fwd_l<32, 1, true> : k_conv_fwd_l<32, 2, true>)
+                                : (nct == 1 ? k_conv_fwd_l<32, 1, false> : k_conv_fwd_l<32, 2, false>);
+                else
+                    kern = last ? (nct == 1 ? k_conv_fwd_l<16, 1, true> : k_conv_fwd_l<16, 2, true>)
+                                : (nct == 1 ? k_conv_fwd_l<16, 1, false> : k_conv_fwd_l<16, 2, false>);
+                g = npix / kLdsPix;
+            }
         }
         hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, h->stream, c, M, npix, X, Wf, b, Xn, uu, pp);
     }
