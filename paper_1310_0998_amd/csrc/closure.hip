@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_c(Conv cv, int M, int npi
 // load spans fall in different LDS banks.  Each wavefront then computes
 // kLdsPix / 64 tiles from LDS, with its weight operands held in registers.
 // Same products and accumulation order as k_conv_fwd.
-constexpr int kLdsPix = 256;
+constexpr int kLdsPix = 128;
 template <int CIN, int NCT, bool LAST>
 __global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npix,
                                                           const unsigned short* __restrict__ X,
