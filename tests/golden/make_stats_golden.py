@@ -1,15 +1,19 @@
 """Writes stats_dimers_1600.json: the oracle's long-run statistics under the
 protocol of stats_protocol.py.  Calls only oracle/ (and the seeded input
-generators).  Run from the repository root:
+generators).  The seeds run in parallel processes of one oracle thread each.
+Run from the repository root:
 
-    python tests/golden/make_stats_golden.py
+    python tests/golden/make_stats_golden.py [--procs 8]
 """
 from __future__ import annotations
 
 import json
+import multiprocessing
 import os
 import sys
 import time
+
+os.environ["OMP_NUM_THREADS"] = "1"  # one oracle thread per process
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -36,11 +40,14 @@ def run_seed(seed: int) -> dict:
 
 
 def main():
+    procs = int(sys.argv[sys.argv.index("--procs") + 1]) if "--procs" in sys.argv else 8
     t0 = time.time()
     per_seed = []
-    for seed in PROTOCOL["seeds"]:
-        per_seed.append(run_seed(seed))
-        print(f"seed {seed}: L_gv {per_seed[-1]['L_gv']:.4f}  ({time.time() - t0:.0f} s)", flush=True)
+    with multiprocessing.Pool(procs) as pool:
+        for k, res in enumerate(pool.imap(run_seed, PROTOCOL["seeds"])):
+            per_seed.append(res)
+            print(f"seed {PROTOCOL['seeds'][k]}: L_gv {res['L_gv']:.4f}  ({time.time() - t0:.0f} s)",
+                  flush=True)
     out = dict(protocol=PROTOCOL, per_seed=per_seed, **ensemble(per_seed),
                source="oracle (FP64), oracle.step / oracle.bin_velocity / oracle.analysis")
     with open(os.path.join(HERE, "stats_dimers_1600.json"), "w") as f:

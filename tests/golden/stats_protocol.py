@@ -14,7 +14,13 @@ For every snapshot:
     (Eqs. 5.5-5.6) in bins of r_c / 4.
 Each seed gives the band energies averaged over its snapshots and the
 integral length (Eq. 5.7) of its snapshot-averaged correlation function; the
-ensemble mean and its standard error over seeds are compared.
+ensemble mean and its standard error over seeds are compared.  512 seeds
+bring the standard error of every compared mean below 0.5 % (the lowest band,
+with its 8 modes, has a spread of about 7 % between seeds).
+
+The correlation function is computed by vcf_pairs, a vectorised form of the
+oracle's pair loop (analysis.vcf_bruteforce) over the same pairs and bins; a
+CPU test checks that the two agree.
 
 This module holds the protocol and the statistics, both written with the
 oracle's analysis routines; it generates no trajectories.
@@ -27,7 +33,7 @@ from oracle import analysis
 
 PROTOCOL = dict(
     workload="dimers_1600",
-    seeds=[101, 102, 103, 104, 105, 106, 107, 108],
+    seeds=list(range(1001, 1001 + 512)),  # independent replicas
     warmup=4000,        # steps from the random start (20 time units)
     steps=40000,        # measured steps per seed (200 time units)
     every=200,          # steps between snapshots
@@ -35,6 +41,46 @@ PROTOCOL = dict(
     dr=0.25,            # correlation-function bin width (r_c / 4)
     bands=[(1, 1), (2, 2), (3, 4), (5, 7), (8, 10)],
 )
+
+
+def vcf_pairs(pos: np.ndarray, V: np.ndarray, L: float, dr: float):
+    """analysis.vcf_bruteforce over the same pairs k < l and bins, vectorised:
+    (r_centres, g, counts) with g(0) := 1 prepended at r = 0."""
+    pos = np.asarray(pos, np.float64)
+    V = np.asarray(V, np.float64)
+    n = len(pos)
+    mean = V.mean(axis=0)
+    mean2 = float(mean @ mean)
+    var = float((V * V).sum(axis=1).mean()) - mean2
+    nb = int(np.floor(0.5 * L / dr))
+    i, j = np.triu_indices(n, 1)
+    d = pos[j] - pos[i]
+    d -= L * np.round(d / L)
+    r = np.sqrt((d * d).sum(axis=1))
+    b = np.floor(r / dr).astype(np.int64)
+    ok = b < nb
+    dots = (V[j] * V[i]).sum(axis=1)
+    num = np.bincount(b[ok], weights=dots[ok], minlength=nb)[:nb]
+    cnt = np.bincount(b[ok], minlength=nb)[:nb]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        g = (num / cnt - mean2) / var
+    rc = (np.arange(nb) + 0.5) * dr
+    return np.concatenate([[0.0], rc]), np.concatenate([[1.0], g]), np.concatenate([[0], cnt])
+
+
+def band_energies_batch(u: np.ndarray) -> np.ndarray:
+    """band_energies(analysis.energy_spectrum(u[f])) for a batch of fields
+    u [F][M][M][2] at once: (F, bands)."""
+    u = np.asarray(u, np.float64)
+    M = u.shape[1]
+    uh = np.fft.fft2(u, axes=(1, 2)) / float(M * M)
+    e = 0.5 * (np.abs(uh[..., 0]) ** 2 + np.abs(uh[..., 1]) ** 2)
+    shell = np.floor(analysis.wavenumber_magnitude(M) + 0.5).astype(np.int64)
+    out = np.zeros((u.shape[0], len(PROTOCOL["bands"])))
+    for q, (a, b) in enumerate(PROTOCOL["bands"]):
+        m = (shell >= a) & (shell <= b)
+        out[:, q] = e[:, m].sum(axis=1)
+    return out
 
 
 def band_energies(E: np.ndarray) -> np.ndarray:
@@ -53,7 +99,7 @@ class SeedAccumulator:
     def add(self, u: np.ndarray, x: np.ndarray, v: np.ndarray):
         self.E += band_energies(analysis.energy_spectrum(np.asarray(u, np.float64)))
         com, V = analysis.agent_com(x, v, self.L)
-        r, g, _ = analysis.vcf_bruteforce(com, V, self.L, PROTOCOL["dr"])
+        r, g, _ = vcf_pairs(com, V, self.L, PROTOCOL["dr"])
         self.r = r
         self.g = g if self.g is None else self.g + g
         self.n += 1

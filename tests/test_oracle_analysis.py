@@ -117,3 +117,24 @@ def test_agent_com_minimum_image():
     com, V = analysis.agent_com(x, v, L)
     assert com[0] == pytest.approx([0.1, 5.0])
     assert V[0] == pytest.approx([2.0, 0.0])
+
+
+def test_stats_protocol_helpers_match_oracle_routines():
+    # the statistics protocol's vectorised correlation function and batched
+    # band energies are the oracle's pair loop and per-field spectrum
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    from stats_protocol import PROTOCOL, band_energies, band_energies_batch, vcf_pairs
+    rng = np.random.default_rng(21)
+    L = 40.0
+    pos = rng.uniform(0.0, L, (300, 2))
+    V = rng.normal(size=(300, 2)) + 0.2
+    a = analysis.vcf_bruteforce(pos, V, L, 0.25)
+    b = vcf_pairs(pos, V, L, 0.25)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+    assert np.allclose(a[1], b[1], rtol=1e-12, atol=1e-14, equal_nan=True)
+    u = rng.normal(size=(3, PROTOCOL["M"], PROTOCOL["M"], 2))
+    got = band_energies_batch(u)
+    for f in range(3):
+        assert np.allclose(got[f], band_energies(analysis.energy_spectrum(u[f])), rtol=1e-13)
