@@ -763,18 +763,23 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
 }
 
 // Slow path for a tile that overflows an LDS capacity (dense clusters), one
-// 64-lane wavefront per tile: the members of the tile's cells are numbered in
-// cell order (a scan of the cell counts) and dealt to the lanes, so that both
-// sparse tiles (many cells, few members each) and dense ones (one cell, many
-// members) keep the lanes busy.  A member's canonical slot is its cell's start
-// plus the number of members of the cell with a smaller id; it sums its pairs
-// over the full 3x3 stencil straight from global memory.  The sums are fixed
-// point, so the result is bitwise the fast path's.
+// 64-lane wavefront per tile.  The members of the tile's cells are numbered
+// in canonical order (cells in turn, each cell's members by id; a scan of the
+// cell counts gives each cell's first number) and dealt to the lanes in that
+// order, so that both sparse tiles (many cells, few members each) and dense
+// ones (one cell, many members) keep the lanes busy, and every lane's velocity
+// sums run over the same particles in the same order from run to run.  A
+// first pass gives each member, taken in slot order, its canonical number (its
+// cell's first number plus the members of the cell with a smaller id) and
+// records the slot under that number in LDS, kOvfWindow numbers at a time.
+// Each member sums its pairs over the full 3x3 stencil straight from global
+// memory.  The sums are fixed point, so the result is bitwise the fast path's.
 // REBUILT is a template parameter, not a runtime flag: the lanes' loops here
 // diverge, and a wave-uniform flag tested inside them was compiled into a lane
 // mask taken under one loop's exec mask and reused under another's, which sent
 // some lanes down the wrong side of the test.  The velocity sums are always
 // accumulated (the caller decides whether to store them).
+constexpr int kOvfWindow = 2048;
 template <int MODE, bool REBUILT>
 __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int cy0, int tw,
                             int th, double rv[3]) {
@@ -782,6 +787,7 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
     // the last rebuild: slot g holds particle g
     __shared__ int s_pre[kTileMax * kTileMax + 1];  // first member number of each tile cell
     __shared__ int s_beg[kTileMax * kTileMax];      // its first global slot
+    __shared__ int s_slot[kOvfWindow];              // global slot of canonical number w0 + i
     const int nc = P.nc, ncell = tw * th, lane = threadIdx.x;
     int cnt = 0;
     if (lane < ncell) {
@@ -795,76 +801,96 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
     if (lane < ncell) s_pre[lane] = ex;
     if (lane == 0) s_pre[ncell] = tot;
     __syncthreads();
-    for (int t = lane; t < tot; t += kWave) {
-        // the tile cell of member t: the last with s_pre <= t (it is not empty)
+    // the tile cell of member number t: the last with s_pre <= t (not empty)
+    auto cell_of = [&](int t) {
         int lo = 0, hi = ncell - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (s_pre[mid] <= t) lo = mid;
             else hi = mid - 1;
         }
-        const int gx = cx0 + lo % tw, gy = cy0 + lo / tw;
-        const int b = s_beg[lo], e = b + (s_pre[lo + 1] - s_pre[lo]);
-        const int g = b + (t - s_pre[lo]);
-        int p = REBUILT ? a.src[g] : g;
-        if ((unsigned)(p - P.pbase) >= (unsigned)P.N) {  // outside this system
-            atomicOr(a.status, kStatusBinning);
-            p = P.pbase;
+        return lo;
+    };
+    for (int w0 = 0; w0 < tot; w0 += kOvfWindow) {
+        const int w1 = min(tot, w0 + kOvfWindow);
+        // canonical numbers of the members, taken in slot order
+        for (int t = lane; t < tot; t += kWave) {
+            const int lo = cell_of(t);
+            const int b = s_beg[lo], e = b + (s_pre[lo + 1] - s_pre[lo]);
+            const int g = b + (t - s_pre[lo]);
+            int p = REBUILT ? a.src[g] : g;
+            if ((unsigned)(p - P.pbase) >= (unsigned)P.N) {  // outside this system
+                atomicOr(a.status, kStatusBinning);
+                p = P.pbase;
+            }
+            const int idi = a.idin[p];
+            int r = 0;  // members of the cell with a smaller id (ids are distinct)
+            for (int g1 = b; g1 < e; ++g1) {
+                int p1 = REBUILT ? a.src[g1] : g1;
+                if ((unsigned)(p1 - P.pbase) >= (unsigned)P.N) p1 = P.pbase;
+                r += (a.idin[p1] < idi) ? 1 : 0;
+            }
+            const int tc = s_pre[lo] + r;
+            if (tc >= w0 && tc < w1) s_slot[tc - w0] = g;
         }
-        const int idi = a.idin[p];
-        // canonical rank within the cell (ids are distinct)
-        int r = 0;
-        for (int g1 = b; g1 < e; ++g1) {
-            int p1 = REBUILT ? a.src[g1] : g1;
-            if ((unsigned)(p1 - P.pbase) >= (unsigned)P.N) p1 = P.pbase;
-            r += (a.idin[p1] < idi) ? 1 : 0;
-        }
-        const float2 xi = a.xin[p], ui = a.uin[p];
-        const int pid = idi ^ 1;
-        long long qx = 0, qy = 0;
-        bool found = false, bad = false;
-        float2 xpart = xi;
-        for (int oy = -1; oy <= 1; ++oy) {
-            for (int ox = -1; ox <= 1; ++ox) {
-                const int c2 = wrap_cell(gy + oy, nc) * nc + wrap_cell(gx + ox, nc);
-                const int b2 = a.cs[c2], e2 = a.cs[c2 + 1];
-                for (int g2 = b2; g2 < e2; ++g2) {
-                    if (g2 == g) continue;
-                    int q = REBUILT ? a.src[g2] : g2;
-                    if ((unsigned)(q - P.pbase) >= (unsigned)P.N) q = P.pbase;
-                    const int idj = a.idin[q];
-                    const float2 xj = a.xin[q];
-                    if (idj == pid) {
-                        found = true;
-                        xpart = xj;
-                        continue;
-                    }
-                    const float dx = minimg_sub(xi.x, xj.x, P);
-                    const float dy = minimg_sub(xi.y, xj.y, P);
-                    const float gap = cutoff_gap(P, dx, dy);
-                    const float r2 = fmaf(dx, dx, dy * dy);
-                    if (interacts(gap, r2)) {
-                        float fx = 0.f, fy = 0.f;
-                        add_pair_force(P, dx, dy, gap, r2, ui, a.uin[q], idi, idj, a.step, fx, fy);
-                        bad |= !(__builtin_isfinite(fx) && __builtin_isfinite(fy));
-                        qx += to_fixed(fx);
-                        qy += to_fixed(fy);
+        __syncthreads();
+        for (int tc = w0 + lane; tc < w1; tc += kWave) {
+            const int lo = cell_of(tc);
+            const int gx = cx0 + lo % tw, gy = cy0 + lo / tw;
+            const int b = s_beg[lo], e = b + (s_pre[lo + 1] - s_pre[lo]);
+            const int r = tc - s_pre[lo];  // canonical rank in the cell: output slot b + r
+            int g = s_slot[tc - w0];
+            g = (g >= b && g < e) ? g : b;  // a valid slot of the cell even on corrupt input
+            int p = REBUILT ? a.src[g] : g;
+            if ((unsigned)(p - P.pbase) >= (unsigned)P.N) p = P.pbase;
+            const int idi = a.idin[p];
+            const float2 xi = a.xin[p], ui = a.uin[p];
+            const int pid = idi ^ 1;
+            long long qx = 0, qy = 0;
+            bool found = false, bad = false;
+            float2 xpart = xi;
+            for (int oy = -1; oy <= 1; ++oy) {
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const int c2 = wrap_cell(gy + oy, nc) * nc + wrap_cell(gx + ox, nc);
+                    const int b2 = a.cs[c2], e2 = a.cs[c2 + 1];
+                    for (int g2 = b2; g2 < e2; ++g2) {
+                        if (g2 == g) continue;
+                        int q = REBUILT ? a.src[g2] : g2;
+                        if ((unsigned)(q - P.pbase) >= (unsigned)P.N) q = P.pbase;
+                        const int idj = a.idin[q];
+                        const float2 xj = a.xin[q];
+                        if (idj == pid) {
+                            found = true;
+                            xpart = xj;
+                            continue;
+                        }
+                        const float dx = minimg_sub(xi.x, xj.x, P);
+                        const float dy = minimg_sub(xi.y, xj.y, P);
+                        const float gap = cutoff_gap(P, dx, dy);
+                        const float r2 = fmaf(dx, dx, dy * dy);
+                        if (interacts(gap, r2)) {
+                            float fx = 0.f, fy = 0.f;
+                            add_pair_force(P, dx, dy, gap, r2, ui, a.uin[q], idi, idj, a.step, fx, fy);
+                            bad |= !(__builtin_isfinite(fx) && __builtin_isfinite(fy));
+                            qx += to_fixed(fx);
+                            qy += to_fixed(fy);
+                        }
                     }
                 }
             }
+            if (bad) atomicOr(a.status, kStatusNonFinite);
+            float fx = from_fixed(qx), fy = from_fixed(qy);
+            if (found) {
+                add_agent_force(P, xi, xpart, ui, idi, fx, fy);
+            } else {
+                atomicOr(a.status, kStatusBond);
+                fx -= P.gamma_s * ui.x;
+                fy -= P.gamma_s * ui.y;
+            }
+            finish_particle<MODE, true>(P, a, b + r, xi, ui, idi, fx, fy, rv, true, REBUILT);
         }
-        if (bad) atomicOr(a.status, kStatusNonFinite);
-        float fx = from_fixed(qx), fy = from_fixed(qy);
-        if (found) {
-            add_agent_force(P, xi, xpart, ui, idi, fx, fy);
-        } else {
-            atomicOr(a.status, kStatusBond);
-            fx -= P.gamma_s * ui.x;
-            fy -= P.gamma_s * ui.y;
-        }
-        finish_particle<MODE, true>(P, a, b + r, xi, ui, idi, fx, fy, rv, true, REBUILT);
+        __syncthreads();  // s_slot is rewritten for the next window, s_pre for the next tile
     }
-    __syncthreads();  // s_pre and s_beg are reused by the next tile
 }
 
 // The tiles k_pair left over, one 64-lane wavefront per listed tile, through
