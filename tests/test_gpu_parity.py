@@ -416,6 +416,25 @@ def test_dense_cluster_steps(dpd):
     sim.close()
 
 
+def test_dense_cluster_reductions_run_to_run(dpd):
+    # tiles of a dense cluster take the global-memory kernel, whose lanes take
+    # the members of each tile in canonical order: the FP64 momentum and
+    # kinetic-energy sums, like the states, are bitwise the same in every run
+    # (the slot order the members arrive in comes from atomic ranks and varies)
+    cfg = dict(C1, f_sp=0.0, gamma_s=0.0)
+    x, v = inputs.initial_state(cfg, kind="clustered", thermal=True)
+    runs = []
+    for _ in range(3):
+        sim = make_sim(dpd, cfg, x, v)
+        pk = host(sim.step(30, reduce_every=1))
+        xs, vs, _, _ = sim.get_state()
+        runs.append((pk, host(xs), host(vs)))
+        sim.close()
+    for pk, xs, vs in runs[1:]:
+        assert (pk == runs[0][0]).all()
+        assert (xs == runs[0][1]).all() and (vs == runs[0][2]).all()
+
+
 def test_stokes_momentum_decay_on_gpu(dpd):
     cfg = dict(C1, f_sp=0.0, gamma_s=0.8)
     x, v = inputs.initial_state(cfg, thermal=True)
