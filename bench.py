@@ -277,7 +277,9 @@ def run_closure(args):
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     train_idx, test_idx = ct.split(runs)
-    net = closure.Closure(ct.M, c_in=4, width=32, layers=4, max_batch=32, device=dev)
+    # batches of 32 in training; the judged rollout runs one field per replica
+    net = closure.Closure(ct.M, c_in=4, width=32, layers=4, max_batch=max(32, args.closure_ensemble),
+                          device=dev)
     net.set_weights(torch.from_numpy(inputs.closure_init(601, 4, 32, 4)).to(dev))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
