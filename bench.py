@@ -266,7 +266,6 @@ def run_closure(args):
     """The learned closure: DPD-generated training pairs, training on the GPU,
     then an ensemble of closure rollouts against the same ensemble of DPD runs, timed,
     with the energy-spectrum and correlation-length errors of the rollout."""
-    import numpy as np
     import torch
 
     from paper_1310_0998_amd import closure, closure_train as ct, inputs
@@ -356,7 +355,6 @@ def run_closure(args):
     }
     print(json.dumps(_finite(line)), flush=True)
     net.close()
-    _ = np
 
 
 def run_rollout(args):
