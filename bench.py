@@ -103,8 +103,6 @@ def measured_valu(avg_launch_us: float):
 
 
 def cpu_baseline(cfg, x, v, steps: int):
-    import numpy as np
-
     import oracle
     t0 = time.perf_counter()
     F = oracle.forces(cfg, x, v, 0)
@@ -112,14 +110,24 @@ def cpu_baseline(cfg, x, v, steps: int):
     oracle.step(cfg, x, v, F, 0, steps)
     t2 = time.perf_counter()
     n = len(x)
+    cores = oracle.num_threads()
+    # the same from the same state on one thread, for one step
+    oracle.set_threads(1)
+    try:
+        t3 = time.perf_counter()
+        oracle.step(cfg, x, v, F, 0, 1)
+        t4 = time.perf_counter()
+    finally:
+        oracle.set_threads(cores)
     return {
         "value": n * steps / (t2 - t1),
         "unit": "particle-steps/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"{steps} velocity-Verlet steps of the full {n}-particle system from the "
-                  f"benchmark's initial state (FP64 oracle, OpenMP; initial force "
-                  f"evaluation {t1 - t0:.2f} s not counted)",
+                  f"benchmark's initial state (FP64 oracle, OpenMP; initial force evaluation "
+                  f"{t1 - t0:.2f} s not counted); one further step on one thread for value_1_thread",
+        "value_1_thread": n / (t4 - t3),
     }
 
 

@@ -99,6 +99,7 @@ def lib():
             "oracle_minimg": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
             "oracle_wrap": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
             "oracle_num_threads": (ctypes.c_int, []),
+            "oracle_set_threads": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -152,6 +153,11 @@ def _vec64(a, n):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    lib().oracle_set_threads(int(n))
 
 
 def philox4x32_10(ctr, key):

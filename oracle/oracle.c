@@ -39,6 +39,14 @@ int oracle_num_threads(void) {
 #endif
 }
 
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* Philox: a Feistel-like network whose S-box is a 32x32->64 multiply, with a
  * Weyl-sequence key schedule (Salmon, Moraes, Dror & Shaw, "Parallel random

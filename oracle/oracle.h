@@ -134,6 +134,8 @@ double oracle_minimg(double d, double L);
 double oracle_wrap(double y, double L);
 
 int oracle_num_threads(void);
+/* OpenMP threads of the following calls (n > 0; ignored without OpenMP). */
+void oracle_set_threads(int n);
 
 #ifdef __cplusplus
 }

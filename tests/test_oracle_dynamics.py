@@ -215,3 +215,20 @@ def test_wrap_and_minimum_image(oracle_mod):
     assert oracle_mod.minimg(39.5, L) == -0.5
     assert oracle_mod.minimg(-39.5, L) == 0.5
     assert oracle_mod.minimg(0.25, L) == 0.25
+
+
+def test_forces_do_not_depend_on_thread_count():
+    # each particle's pair list is summed in j order, so the oracle's forces
+    # are the same bits on one thread and on all of them
+    import oracle
+    cfg = inputs.physics(inputs.WORKLOADS["dimers_1600"])
+    x, v = inputs.initial_state(cfg, thermal=True)
+    n = oracle.num_threads()
+    F_all = oracle.forces(cfg, x, v, 3)
+    oracle.set_threads(1)
+    try:
+        F_one = oracle.forces(cfg, x, v, 3)
+    finally:
+        oracle.set_threads(n)
+    assert (F_all == F_one).all()
+    assert oracle.num_threads() == n
