@@ -532,15 +532,18 @@ __global__ void k_adam(int n, float* w, float* m, float* v, const float* __restr
 // Philox4x32-10 with counter (point, component, step, 0) and the seed as key
 // (point = b M^2 + pixel over a batch).  Also writes u_next rounded to BF16
 // into channels 0 and 1 of the next forward pass's input X (cin channels per
-// pixel; the condition channels stay as they are).
+// pixel; the condition channels stay as they are), and u_next to `save` too
+// when that is not null (a saved step of a rollout).
 __global__ void k_noise(int n, const float* __restrict__ pred, float s0, float s1, uint32_t step,
-                        uint32_t k0, uint32_t k1, float* unext, int cin, unsigned short* X) {
+                        uint32_t k0, uint32_t k1, float* unext, int cin, unsigned short* X,
+                        float* save) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;  // t = 2 point + component
     if (t >= n) return;
     const uint4 w = dpd::philox4x32_10(make_uint4((uint32_t)(t >> 1), (uint32_t)(t & 1), step, 0u), k0, k1);
     const float alpha = dpd::alpha_from_words(0, make_uint2(w.x, w.y));
     const float v = pred[t] + ((t & 1) ? s1 : s0) * alpha;
     unext[t] = v;
+    if (save) save[t] = v;
     X[(size_t)(t >> 1) * cin + (t & 1)] = to_bf16(v);
 }
 
@@ -643,12 +646,14 @@ __global__ void k_colour_cols(int M, const float2* __restrict__ Hhat, float2* A)
 }
 
 // Row j of field b: the inverse row DFT's real part over M^2 is the noise;
-// u_next = pred + s_c noise, also written to the next input X as in k_noise.
+// u_next = pred + s_c noise, also written to the next input X (and to `save`)
+// as in k_noise.
 // h and w are real, so the filtered spectrum is Hermitian and so is each row
 // of its inverse column transform: C[j][M - k] = conj(C[j][k]) fills the
 // columns past M / 2.
 __global__ void k_colour_out(int M, const float2* __restrict__ A, const float* __restrict__ pred,
-                             float s0, float s1, float* unext, int cin, unsigned short* X) {
+                             float s0, float s1, float* unext, int cin, unsigned short* X,
+                             float* save) {
     __shared__ float2 tw[kColourMaxM];
     __shared__ float2 sa[2 * kColourMaxM];
     const int j = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
@@ -672,6 +677,7 @@ __global__ void k_colour_out(int M, const float2* __restrict__ A, const float* _
     const size_t p = ((size_t)b * M + j) * M + i;
     const float v = pred[2 * p + c] + (c ? s1 : s0) * (re * inv);
     unext[2 * p + c] = v;
+    if (save) save[2 * p + c] = v;
     X[p * cin + c] = to_bf16(v);
 }
 
@@ -1156,6 +1162,7 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
         for (int s = 1; s <= steps; ++s) {
             rc = forward(nn, ucur, nullptr, B, pred, true);
             if (rc) return rc;
+            float* save = (s % save_every == 0) ? traj + (size_t)(s / save_every - 1) * nf : nullptr;
             if (noise_filter) {
                 hipLaunchKernelGGL(k_colour_rows, dim3(n.p.M, B), dim3(2 * n.p.M), 0, nn->stream, n.p.M,
                                    (uint32_t)s, k0, k1, Aw);
@@ -1163,16 +1170,13 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
                                    n.p.M, (const float2*)Hh, Aw);
                 hipLaunchKernelGGL(k_colour_out, dim3(n.p.M, B), dim3(2 * n.p.M), 0, nn->stream, n.p.M,
                                    (const float2*)Aw, (const float*)pred, noise_std[0], noise_std[1],
-                                   ucur, n.p.c_in, X0);
+                                   ucur, n.p.c_in, X0, save);
             } else {
                 hipLaunchKernelGGL(k_noise, dim3(blocks(nf)), dim3(kThreads), 0, nn->stream, nf,
                                    (const float*)pred, noise_std[0], noise_std[1], (uint32_t)s, k0,
-                                   k1, ucur, n.p.c_in, X0);
+                                   k1, ucur, n.p.c_in, X0, save);
             }
             NLAUNCH(nn);
-            if (s % save_every == 0)
-                NCHK(nn, hipMemcpyAsync(traj + (size_t)(s / save_every - 1) * nf, ucur, 4 * (size_t)nf,
-                                        hipMemcpyDeviceToDevice, nn->stream));
         }
         return DPD_OK;
     } catch (...) {
