@@ -280,10 +280,14 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npi
                                                           const float* __restrict__ bias,
                                                           unsigned short* Xnext,
                                                           const float* __restrict__ u, float* pred) {
-    static_assert(CIN % 16 == 0 && (NCT == 1 || NCT == 2), "unsupported shape");
-    constexpr int CH = CIN / 16, NK = 9 * CH, K = 9 * CIN;
-    constexpr int XS = CIN + 8;  // staged elements per pixel
-    constexpr int WS = K + 8;    // staged elements per output channel
+    static_assert((CIN == 4 || CIN % 16 == 0) && (NCT == 1 || NCT == 2), "unsupported shape");
+    constexpr int CH = CIN >= 16 ? CIN / 16 : 1;
+    constexpr int NK = CIN >= 16 ? 9 * CH : 3;  // chunks of 16 K values (K = 36 padded to 48 at CIN = 4)
+    constexpr int K = NK * 16;                  // weights per output channel, padding included
+    // staged elements per pixel: 4 channels at CIN = 4 (16 consecutive pixels
+    // then fill consecutive banks), else padded by 8
+    constexpr int XS = CIN == 4 ? 4 : CIN + 8;
+    constexpr int WS = K + 8;  // staged elements per output channel
     constexpr int kRowsMax = kLdsPix / 16 + 2;  // staged rows at M = 16
     __shared__ __align__(16) unsigned short sx[kRowsMax * 16 * XS > (kLdsPix / 64 + 2) * 64 * XS
                                                    ? kRowsMax * 16 * XS
@@ -293,16 +297,29 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npi
     if (p0 >= npix) return;
     const int M2 = M * M, R = kLdsPix / M;
     const int b = p0 / M2, y0 = (p0 - b * M2) / M;
-    // stage rows y0 - 1 .. y0 + R (periodic) in 16-byte vectors
-    const int nvec = (R + 2) * M * CIN / 8;
-    for (int t = threadIdx.x; t < nvec; t += kThreads) {
-        const int e = t * 8, pix = e / CIN, c = e - pix * CIN;  // staged pixel, channel
-        const int rr = pix / M, xx = pix - rr * M;
-        int yy = y0 - 1 + rr;
-        yy += (yy < 0) ? M : 0;
-        yy -= (yy >= M) ? M : 0;
-        const uint4 v = *reinterpret_cast<const uint4*>(X + (((size_t)b * M2 + (size_t)yy * M + xx) * CIN + c));
-        *reinterpret_cast<uint4*>(sx + pix * XS + c) = v;
+    // stage rows y0 - 1 .. y0 + R (periodic) in 16-byte vectors (8-byte ones,
+    // a pixel each, at CIN = 4)
+    if constexpr (CIN == 4) {
+        const int npx = (R + 2) * M;
+        for (int pix = threadIdx.x; pix < npx; pix += kThreads) {
+            const int rr = pix / M, xx = pix - rr * M;
+            int yy = y0 - 1 + rr;
+            yy += (yy < 0) ? M : 0;
+            yy -= (yy >= M) ? M : 0;
+            *reinterpret_cast<uint2*>(sx + pix * XS) =
+                *reinterpret_cast<const uint2*>(X + ((size_t)b * M2 + (size_t)yy * M + xx) * 4);
+        }
+    } else {
+        const int nvec = (R + 2) * M * CIN / 8;
+        for (int t = threadIdx.x; t < nvec; t += kThreads) {
+            const int e = t * 8, pix = e / CIN, c = e - pix * CIN;  // staged pixel, channel
+            const int rr = pix / M, xx = pix - rr * M;
+            int yy = y0 - 1 + rr;
+            yy += (yy < 0) ? M : 0;
+            yy -= (yy >= M) ? M : 0;
+            const uint4 v = *reinterpret_cast<const uint4*>(X + (((size_t)b * M2 + (size_t)yy * M + xx) * CIN + c));
+            *reinterpret_cast<uint4*>(sx + pix * XS + c) = v;
+        }
     }
     // the weights of the NCT * 16 output channels (rows of Wf, K = Kpad here)
     const int wvec = NCT * 16 * K / 8;
@@ -334,12 +351,26 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npi
         const int ly = lp / M, x = lp - ly * M;
         const int xs[3] = {x == 0 ? M - 1 : x - 1, x, x == M - 1 ? 0 : x + 1};
         bf16x4 a[NK];
+        if constexpr (CIN == 4) {
+            // chunk i, lane group g: the 4 channels of tap 4 i + g (zero past tap 8)
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int pix = (ly + tap / 3) * M + xs[tap % 3];  // staged row ly + dy + 1
+            for (int i = 0; i < NK; ++i) {
+                const int tap = 4 * i + g;
+                a[i] = bf16x4{0, 0, 0, 0};
+                if (tap < 9) {
+                    const int ty = tap / 3, tx = tap - 3 * ty;
+                    const int xx = tx == 0 ? xs[0] : (tx == 1 ? xs[1] : xs[2]);
+                    a[i] = *reinterpret_cast<const bf16x4*>(sx + ((ly + ty) * M + xx) * XS);
+                }
+            }
+        } else {
 #pragma unroll
-            for (int h = 0; h < CH; ++h)
-                a[tap * CH + h] = *reinterpret_cast<const bf16x4*>(sx + pix * XS + h * 16 + 4 * g);
+            for (int tap = 0; tap < 9; ++tap) {
+                const int pix = (ly + tap / 3) * M + xs[tap % 3];  // staged row ly + dy + 1
+#pragma unroll
+                for (int h = 0; h < CH; ++h)
+                    a[tap * CH + h] = *reinterpret_cast<const bf16x4*>(sx + pix * XS + h * 16 + 4 * g);
+            }
         }
         f32x4 acc[NCT];
 #pragma unroll
@@ -922,8 +953,12 @@ int forward(dpd_nn* h, const float* u, const float* cond, int B, float* pred, bo
                             : (nct == 1 ? k_conv_fwd_c<16, 1, false> : k_conv_fwd_c<16, 2, false>);
             const int waves = (ntile + kConvTPW - 1) / kConvTPW;
             g = (waves + kThreads / kWaveN - 1) / (kThreads / kWaveN);
-            if ((c.cin == 32 || c.cin == 16) && (M == 16 || M == 32 || M == 64) && npix % kLdsPix == 0) {
-                if (c.cin == 32)
+            if ((c.cin == 32 || c.cin == 16 || c.cin == 4) && (M == 16 || M == 32 || M == 64) &&
+                npix % kLdsPix == 0) {
+                if (c.cin == 4)
+                    kern = last ? (nct == 1 ? k_conv_fwd_l<4, 1, true> : k_conv_fwd_l<4, 2, true>)
+                                : (nct == 1 ? k_conv_fwd_l<4, 1, false> : k_conv_fwd_l<4, 2, false>);
+                else if (c.cin == 32)
                     kern = last ? (nct == 1 ? k_conv_fwd_l<32, 1, true> : k_conv_fwd_l<32, 2, true>)
                                 : (nct == 1 ? k_conv_fwd_l<32, 1, false> : k_conv_fwd_l<32, 2, false>);
                 else
