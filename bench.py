@@ -2,18 +2,23 @@
 
 One step = one velocity-Verlet step of the whole hot path (cell binning, fused
 pair / agent / integrator kernel), with the FP64 momentum and kinetic-energy
-reduction every 100 steps and the binned 256 x 256 velocity field every 20
-steps, on the 4M-particle system (2M dimers in a 2000 x 2000 periodic box,
-synthetic random initial state).  Prints one JSON line.
+reduction every 100 steps (and at least once per timed window) and the binned
+256 x 256 velocity field every 20 steps, on the 4M-particle system (2M dimers
+in a 2000 x 2000 periodic box, synthetic random initial state).  The first
+--t0-steps steps from the random start are timed on their own; then a fixed,
+untimed relaxation of --relax steps (default 2000) brings the system to its
+steady state, whatever --warmup is; then --warmup more steps, then exactly
+--steps timed steps.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-steps S]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--relax R] [--cpu-steps S]
 
 With --workload sweep64 it instead times the batched parameter sweep: 64
 replicas of uneven size advanced together, against the same systems run one
 after another; with --workload closure it trains the learned closure on
 DPD-generated fields and times its rollout against plain DPD (each prints one
-JSON line of its own); --workload paper runs the paper's own parameter set
-and --workload rollout times the closure's batched rollout alone.
+JSON line of its own); --workload paper runs the paper's own parameter set,
+--workload rollout times the closure's batched rollout alone and --workload
+grid200k the 200k-particle gamma x zeta grid.
 """
 from __future__ import annotations
 
@@ -35,11 +40,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def pair_kernel_bytes(n_particles: int, n_cells: int) -> int:
-    """Algorithmic HBM bytes of one launch of the fused pair kernel (step mode):
-    reads slot->index (4), x (8), u (8), id (4) per particle and cell_start
-    (4 per cell + 1); writes x (8), u (8), id (4), key (4), rank (4) per
-    particle; one 4-byte atomic read-modify-write of a cell counter (8)."""
+def pair_pass_bytes(n_particles: int, n_cells: int) -> int:
+    """Algorithmic HBM bytes of one pair-force pass as the hot-path survey
+    counts them: per particle the sorted x (8), u (8) and id (4) read and the
+    force (8) written, plus cell_start (4 per cell, n_cells + 1 entries);
+    32 B per particle at one particle per cell."""
+    return n_particles * (8 + 8 + 4 + 8) + 4 * (n_cells + 1)
+
+
+def fused_kernel_bytes(n_particles: int, n_cells: int) -> int:
+    """What the fused step kernel itself must move: reads slot->index (4),
+    x (8), u (8), id (4) per particle and cell_start (4 per cell + 1); writes
+    the next x (8), u (8), id (4), cell key (4) and rank (4); one 4-byte atomic
+    read-modify-write of a cell counter (8).  60 B per particle + 4 per cell."""
     return n_particles * (4 + 8 + 8 + 4 + 8 + 8 + 4 + 4 + 4 + 8) + 4 * (n_cells + 1)
 
 
@@ -208,7 +221,7 @@ def run_sweep(args):
         log(f"sequential ({mode}): {total:.3f} s")
 
     avg_us = 1e3 * pair_ms / max(launches, 1)
-    alg = pair_kernel_bytes(N, n_cells)
+    alg = pair_pass_bytes(N, n_cells)
     achieved = alg / (avg_us * 1e-6) / 1e9
     rate = N * steps / t_batch
     line = {
@@ -257,6 +270,88 @@ def run_sweep(args):
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_grid200k(args):
+    """The 200k-particle pair-friction x Stokes-friction grid: gamma in
+    {1, 4.5, 20} x zeta in {0, 0.5, 5} (seeds 201-209), each point advanced
+    from its random start for --grid-steps steps in captured 50-step chunks
+    (FP64 totals every 100 steps), then 200 eager steps with the pair kernel
+    bracketed by events for its launch time.  The working set (about 12 MB)
+    stays in the caches, so the pair kernel's byte rate is a cache-level
+    figure, not an HBM one."""
+    import torch
+
+    from paper_1310_0998_amd import dpd, inputs
+
+    dev = torch.device("cuda:0")
+    base = inputs.physics(inputs.WORKLOADS["dimers_200k"])
+    steps = args.grid_steps
+    K = 50
+    red_every = 100 if steps % 100 == 0 else 0
+    points = []
+    t_total = 0.0
+    n_total = 0
+    for k, (g, z) in enumerate(inputs.GAMMA_ZETA_GRID_200K):
+        cfg = dict(base, gamma=g, gamma_s=z, seed=201 + k)
+        x, v = inputs.initial_state(cfg)
+        N = len(x)
+        sim = dpd.Sim(cfg, device=dev)
+        sim.set_state(torch.from_numpy(x).to(dev), torch.from_numpy(v).to(dev), 0)
+        sim.set_graph_chunk(K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if red_every:
+            sim.step(steps, reduce_every=red_every)
+        else:
+            sim.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sim.sync()
+        sim.set_graph_chunk(0)
+        sim.set_profiling(True)
+        sim.step(200)
+        pair_ms, launches = sim.pair_kernel_time()
+        sim.set_profiling(False)
+        n_cells = sim.n_cells
+        sim.close()
+        avg_us = 1e3 * pair_ms / max(launches, 1)
+        alg = pair_pass_bytes(N, n_cells)
+        p = {"gamma": g, "zeta": z, "seed": 201 + k, "ms_per_step": 1e3 * dt / steps,
+             "particle_steps_per_s": N * steps / dt, "pair_kernel_us": avg_us,
+             "pair_kernel_GBps_alg": alg / (avg_us * 1e-6) / 1e9}
+        points.append(p)
+        t_total += dt
+        n_total += N * steps
+        log(f"gamma={g} zeta={z}: {p['ms_per_step']:.4f} ms/step, pair kernel {avg_us:.2f} us, "
+            f"{p['pair_kernel_GBps_alg']:.0f} GB/s (32 B/particle)")
+    line = {
+        "metric": "200k grid: particle-steps/s over the gamma x zeta grid; pair kernel GB/s",
+        "value": n_total / t_total,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": 1e3 * t_total / (steps * len(points)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "grid200k: 2-D periodic box L=447 r_c, 100000 dimers (200000 particles), "
+                        "a=25, kT=1, F_p=1, dt=0.005, gamma {1,4.5,20} x zeta {0,0.5,5}, "
+                        f"{steps} steps per point from random positions at rest",
+            "graph_chunk": K,
+            "fp64_reduction_every": red_every,
+            "parallelism": "single-gpu",
+        },
+        "points": points,
+        "pair_kernel_GBps_alg_mean": sum(p["pair_kernel_GBps_alg"] for p in points) / len(points),
+        "cache_note": "working set about 12 MB: L2 / Infinity-Cache resident, not an HBM figure",
+        "cpu_baseline": None,
+    }
+    print(json.dumps(_finite(line)), flush=True)
 
 
 def _finite(o):
@@ -467,6 +562,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--relax", type=int, default=2000,
+                    help="untimed steps from the random start before the warm-up")
+    ap.add_argument("--t0-steps", type=int, default=20,
+                    help="steps timed on their own from the random start")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="dimers_4M")
@@ -492,6 +591,8 @@ def main():
                     help="closure steps of the judged rollout (x50 DPD steps)")
     ap.add_argument("--rollout-steps", type=int, default=200,
                     help="batched closure steps (workload rollout)")
+    ap.add_argument("--grid-steps", type=int, default=10000,
+                    help="steps per grid point (workload grid200k)")
     ap.add_argument("--paper-warm", type=int, default=100000)
     ap.add_argument("--paper-steps", type=int, default=200000)
     ap.add_argument("--paper-every", type=int, default=2000)
@@ -512,7 +613,18 @@ def main():
     if args.workload == "rollout":
         run_rollout(args)
         return
+    if args.workload == "grid200k":
+        run_grid200k(args)
+        return
 
+    run_headline(args)
+
+
+def run_headline(args):
+    """The 4M-particle system: a timed window of K steps (velocity field after
+    every 20, FP64 totals every 100 and at least once), preceded by a fixed,
+    untimed relaxation from the random start and W further warm-up steps; the
+    rate of the first steps from the random start is timed on its own."""
     import numpy as np
     import torch
 
@@ -524,8 +636,10 @@ def main():
     bin_M = wl.get("bin_M", 256)
     bin_every = wl.get("bin_every", 20)
     reduce_every = wl.get("reduce_every", 100)
-    steps = max(bin_every, (args.steps // bin_every) * bin_every)
+    steps = max(1, args.steps)
     warm = max(0, args.warmup)
+    relax = max(0, args.relax)
+    t0_steps = max(1, args.t0_steps)
     dev = torch.device("cuda:0")
     if args.calibrate_copy_mb > 0:
         nb = args.calibrate_copy_mb << 20
@@ -538,29 +652,42 @@ def main():
         del a, b
     x, v = inputs.initial_state(cfg)
     N = len(x)
-    log(f"workload {args.workload}: N={N} L={cfg['L']} steps={steps} warmup={warm}")
+    log(f"workload {args.workload}: N={N} L={cfg['L']} t0 window {t0_steps}, relaxation {relax}, "
+        f"warm-up {warm}, timed {steps} steps")
 
     sim = dpd.Sim(dict(cfg, bin_M_max=bin_M), device=dev)
     sim.set_state(torch.from_numpy(x).to(dev), torch.from_numpy(v).to(dev), 0)
     out = (torch.empty((bin_M, bin_M, 2), dtype=torch.float32, device=dev),
            torch.empty((bin_M, bin_M), dtype=torch.int32, device=dev))
-    n_chunks_red = max(1, reduce_every // bin_every)
-    pk = torch.zeros((steps // reduce_every + 1, 3), dtype=torch.float64, device=dev)
+    pk = torch.zeros((steps // reduce_every + 2, 3), dtype=torch.float64, device=dev)
 
-    def run(nsteps, record_pk):
-        rec = 0
-        for c in range(nsteps // bin_every):
-            do_red = record_pk and ((c + 1) % n_chunks_red == 0)
-            if do_red:
-                sim.step(bin_every, reduce_every=bin_every, pk=pk[rec:rec + 1])
-                rec += 1
+    def run(nsteps, record):
+        """nsteps steps in chunks of bin_every, the velocity field after every
+        full chunk; with record, the FP64 totals after every reduce_every steps
+        and after the last chunk if none was taken.  Returns (bins, reductions)."""
+        bins = reds = done = 0
+        while done < nsteps:
+            n = min(bin_every, nsteps - done)
+            last = done + n == nsteps
+            if record and ((done + n) % reduce_every == 0 or (last and reds == 0)):
+                sim.step(n, reduce_every=n, pk=pk[reds:reds + 1])
+                reds += 1
             else:
-                sim.step(bin_every)
-            sim.bin_velocity(bin_M, 0.0, 0, out=out)
-        rem = nsteps % bin_every
-        if rem:
-            sim.step(rem)
+                sim.step(n)
+            done += n
+            if n == bin_every:
+                sim.bin_velocity(bin_M, 0.0, 0, out=out)
+                bins += 1
+        return bins, reds
 
+    # t = 0: the first steps from the random start (Poisson cell occupancy)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    sim.step(t0_steps)
+    torch.cuda.synchronize()
+    t0_time = time.perf_counter() - ta
+    # relaxation to the steady state, untimed and of fixed length
+    sim.step(relax)
     run(warm, False)
     sim.sync()
     torch.cuda.synchronize()
@@ -568,7 +695,7 @@ def main():
     sim.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run(steps, True)
+    n_bins, n_red = run(steps, True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sim.sync()
@@ -579,12 +706,17 @@ def main():
     value = N * steps / elapsed
     ms_per_step = 1e3 * elapsed / steps
     avg_us = 1e3 * pair_ms / max(launches, 1)
-    alg = pair_kernel_bytes(N, sim.n_c * sim.n_c)
+    n_cells = sim.n_c * sim.n_c
+    alg = pair_pass_bytes(N, n_cells)
+    fused = fused_kernel_bytes(N, n_cells)
     achieved = alg / (avg_us * 1e-6) / 1e9
     traffic = measured_traffic()
+    valu = measured_valu(avg_us)
     pkh = pk.cpu().numpy()
-    log(f"elapsed {elapsed:.3f} s, {ms_per_step:.4f} ms/step, pair kernel {avg_us:.1f} us avg over "
-        f"{launches} launches, {achieved:.0f} GB/s algorithmic; last KE {pkh[max(0, steps // reduce_every - 1), 2]:.1f}")
+    step_t0 = t0_steps + relax + warm
+    log(f"t=0: {1e3 * t0_time / t0_steps:.4f} ms/step; timed: {elapsed:.4f} s, {ms_per_step:.4f} ms/step, "
+        f"pair kernel {avg_us:.1f} us avg over {launches} launches, {achieved:.0f} GB/s algorithmic "
+        f"(32 B/particle); {n_bins} velocity fields, {n_red} FP64 reductions (last KE {pkh[n_red - 1, 2]:.1f})")
 
     cpu = None
     if not args.no_cpu and args.cpu_steps > 0:
@@ -592,6 +724,7 @@ def main():
         cpu = cpu_baseline(cfg, x, v, args.cpu_steps)
         log(f"cpu baseline {cpu['value']:.3e} particle-steps/s on {cpu['cores']} threads")
 
+    hbm_frac = achieved / HBM_PEAK_GBS
     line = {
         "metric": METRIC,
         "value": value,
@@ -609,33 +742,46 @@ def main():
             "workload": f"{args.workload}: 2-D periodic box L={cfg['L']:g} r_c, "
                         f"{cfg['n_agents']} dimers ({N} particles, density 1), a=25, "
                         f"gamma={cfg['gamma']}, kT=1, zeta={cfg['gamma_s']}, F_p=1, "
-                        f"dt={cfg['dt']}; 256x256 velocity field every {bin_every} steps, "
-                        f"FP64 momentum/KE every {reduce_every} steps",
+                        f"dt={cfg['dt']}; {bin_M}x{bin_M} velocity field every {bin_every} steps, "
+                        f"FP64 momentum/KE every {reduce_every} steps and at least once per window",
             "n_particles": N,
-            "cells": sim.n_c * sim.n_c,
+            "cells": n_cells,
             "rng": ["philox4x32-10", "philox2x32-10"][cfg["rng_kind"]],
             "noise": ["gaussian", "uniform"][cfg["noise_kind"]],
             "state": "fp32 (fp64 wrap and reductions)",
             "cell_list": (f"Verlet skin {args.skin:g}: {reb} rebuilds in {steps} timed steps"
                           if args.skin > 0 else "rebuilt every step"),
+            "timed_window": {"first_step": step_t0, "steps": steps, "velocity_fields": n_bins,
+                             "fp64_reductions": n_red,
+                             "untimed_before": {"t0_window": t0_steps, "relaxation": relax,
+                                                "warmup": warm}},
             "parallelism": "single-gpu",
         },
+        "t0": {"steps": t0_steps, "value": N * t0_steps / t0_time,
+               "ms_per_step": 1e3 * t0_time / t0_steps,
+               "note": "first steps from the random start, before relaxation"},
         "roofline": {
             "kernel": "k_pair (fused pair + agent + Verlet)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": hbm_frac,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": alg,
+            "algorithmic_bytes_rule": "32 B per particle: x 8 + u 8 + id 4 read, F 8 written, "
+                                      "cell_start 4 per cell",
             "avg_launch_us": avg_us,
-            "valu": measured_valu(avg_us),
+            "timed_launches": launches,
+            "fused_kernel_bytes_per_launch": fused,
+            "frac_fused_bytes": fused / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "valu": valu,
+            "binding": None if valu is None else ("valu" if valu["frac"] > hbm_frac else "hbm"),
         },
         "cpu_baseline": cpu,
     }
     sim.close()
-    print(json.dumps(line), flush=True)
+    print(json.dumps(_finite(line)), flush=True)
 
 
 if __name__ == "__main__":
