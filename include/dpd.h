@@ -219,6 +219,28 @@ int dpd_get_schedule(dpd_handle* h, int32_t* tile_x, int32_t* tile_y, int32_t* t
 int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* tile_y,
                  int32_t* tile_order, double* best_ms);
 
+/* ---- one call that allocates nothing ---------------------------------------- */
+
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the force F(x, v, step) of dpd_forces (pair + bond + propulsion
+ * + Stokes, Eqs. 2.1-2.7) for one system given directly by its state, with the
+ * library's own static device scratch as the workspace.
+ *   p: parameters as for dpd_create (skin and bin_M_max are ignored);
+ *   x, v: device N x 2 FP32 in id order (caller's, read only);
+ *   F_out: device N x 2 FP32 in id order (caller's, written);
+ *   stream: a hipStream_t (NULL = the null stream).
+ * The scratch is a fixed 32 MiB per device (about 250k particles at one
+ * particle per cell); larger systems are refused with DPD_EWORKSPACE before
+ * any device work.  It calls no hipMalloc or hipFree and creates no stream or
+ * event.  Every call on a device shares that device's scratch and clears what
+ * must start at zero: calls that overlap on one device (other streams or
+ * threads) race.  Synchronises the stream; the results are bitwise those of
+ * dpd_create + dpd_set_state + dpd_forces.
+ * Errors: DPD_EINVAL, DPD_EWORKSPACE, DPD_EHIP, device flags. */
+int dpd_forces_noalloc(const dpd_params* p, const float* x, const float* v, int64_t step,
+                       float* F_out, void* stream);
+
 /* ---- diagnostics used by tests and the benchmark --------------------------- */
 
 /* The cell list of the current state: cell_start_out device int32[n_c^2 + 1]

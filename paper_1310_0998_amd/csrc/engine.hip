@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -21,6 +22,14 @@
 #include "kernels.h"
 
 using namespace dpd;
+
+// Device scratch of dpd_forces_noalloc: the workspace of a one-system handle,
+// for callers that cannot allocate device memory.  Every device the library
+// runs on holds its own copy until the process ends.  In host code the name
+// is not a device address: the address comes from hipGetSymbolAddress, per
+// device (noalloc_scratch below).
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -769,6 +778,35 @@ int apply_schedule(dpd_handle* h, const Sched& s) {
 
 }  // namespace
 
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int noalloc_scratch(void** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(nullptr, DPD_EHIP, fmt("hipGetDevice: %s", hipGetErrorString(e)));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(nullptr, DPD_EHIP, fmt("device %d outside [0, %d)", dev, kMaxDevices));
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, DPD_EHIP,
+                        fmt("hipGetSymbolAddress(scratch): %s", hipGetErrorString(e)));
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return DPD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int dpd_batch_workspace_bytes(const dpd_params* p, int32_t n_rep, size_t* bytes) {
@@ -1363,6 +1401,42 @@ int dpd_copy_kernel(const void* src, void* dst, size_t bytes, void* stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(nullptr, DPD_EHIP, fmt("kernel launch: %s", hipGetErrorString(e)));
     return DPD_OK;
+}
+
+int dpd_forces_noalloc(const dpd_params* p, const float* x, const float* v, int64_t step,
+                       float* F_out, void* stream) {
+    try {
+        if (!p) return fail(nullptr, DPD_EINVAL, "params is NULL");
+        if (!x || !v || !F_out) return fail(nullptr, DPD_EINVAL, "x, v and F_out must not be NULL");
+        // forces do not depend on the skin (bitwise) and bin nothing: the
+        // smallest layout for these parameters
+        dpd_params q = *p;
+        q.skin = 0.0f;
+        q.bin_M_max = 1;
+        Derived d;
+        std::string err;
+        int rc = derive(&q, 1, &d, &err);
+        if (rc) return fail(nullptr, rc, err);
+        if (d.lay.total > kNoAllocScratchBytes)
+            return fail(nullptr, DPD_EWORKSPACE,
+                        fmt("%lld particles need %zu bytes of scratch; the static scratch of "
+                            "dpd_forces_noalloc holds %zu (about %lld particles at one per cell)",
+                            (long long)d.N, d.lay.total, kNoAllocScratchBytes,
+                            (long long)(kNoAllocScratchBytes / 128)));
+        void* ws = nullptr;
+        rc = noalloc_scratch(&ws);
+        if (rc) return rc;
+        dpd_handle* h = nullptr;
+        rc = dpd_create(&q, ws, kNoAllocScratchBytes, stream, &h);
+        if (rc) return rc;
+        rc = dpd_set_state(h, x, v, step, nullptr);
+        if (!rc) rc = dpd_get_state(h, nullptr, nullptr, F_out, nullptr);
+        if (rc) g_last_error = h->err;
+        dpd_destroy(h);
+        return rc;
+    } catch (...) {
+        return fail(nullptr, DPD_EINVAL, "internal error");
+    }
 }
 
 }  // extern "C"

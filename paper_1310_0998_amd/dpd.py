@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
             "dpd_pair_kernel_time": (ctypes.c_int, [vp, ctypes.POINTER(f64), ctypes.POINTER(i64)]),
             "dpd_cell_list_rebuilds": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
             "dpd_copy_kernel": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+            "dpd_forces_noalloc": (ctypes.c_int, [P, vp, vp, i64, vp, vp]),
             "dpd_batch_workspace_bytes": (ctypes.c_int, [P, i32, ctypes.POINTER(ctypes.c_size_t)]),
             "dpd_create_batch": (ctypes.c_int, [P, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
             "dpd_set_graph_chunk": (ctypes.c_int, [vp, i32]),
@@ -318,3 +319,17 @@ def copy_kernel(src: torch.Tensor, dst: torch.Tensor):
     nbytes = src.numel() * src.element_size()
     _check(lib().dpd_copy_kernel(_ptr(src), _ptr(dst), ctypes.c_size_t(nbytes),
                                  _stream_handle(src.device)))
+
+
+def forces_noalloc(cfg: Mapping, x: torch.Tensor, v: torch.Tensor, step: int = 0,
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """F(x, v, step) of one system through dpd_forces_noalloc (the library's
+    static device scratch, no workspace); out may be given to avoid any
+    allocation here too."""
+    n = 2 * int(cfg["n_agents"])
+    _vec(x, n, "x")
+    _vec(v, n, "v")
+    F = torch.empty((n, 2), dtype=torch.float32, device=x.device) if out is None else _vec(out, n, "out")
+    _check(lib().dpd_forces_noalloc(ctypes.byref(make_params(cfg)), _ptr(x), _ptr(v), int(step),
+                                    _ptr(F), _stream_handle(x.device)))
+    return F
