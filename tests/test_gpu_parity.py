@@ -177,6 +177,16 @@ def test_forces_match_oracle(dpd, name, cfg, kind, thermal):
     sim.close()
 
 
+def _sampled_errors(cfg, x, v, step, F, idx):
+    """Per-particle error of the sampled particles relative to their scale S_i
+    (the oracle evaluates the sampled forces one by one; S_i comes from its
+    whole-system force parts)."""
+    Fo = oracle.forces_subset(cfg, x, v, step, idx)
+    _, scale = oracle.force_parts(cfg, x, v, step)
+    err = np.sqrt(((F[idx].astype(np.float64) - Fo) ** 2).sum(1))
+    return err / scale[idx], Fo
+
+
 def test_forces_full_size_sampled(dpd):
     # 4M particles in the benchmark's launch configuration: every force is
     # computed on the GPU, a sample is checked against the oracle one by one
@@ -186,10 +196,9 @@ def test_forces_full_size_sampled(dpd):
     F = host(sim.forces())
     rng = np.random.default_rng(0)
     idx = np.concatenate([rng.choice(len(x), 3000, replace=False), [0, 1, len(x) - 2, len(x) - 1]])
-    Fo = oracle.forces_subset(cfg, x, v, 3, idx)
-    err = np.sqrt(((F[idx].astype(np.float64) - Fo) ** 2).sum(1))
-    scale = np.sqrt((Fo ** 2).sum(1)) + 25.0
-    assert (err / scale).max() <= 1e-5
+    per, _ = _sampled_errors(cfg, x, v, 3, F, idx)
+    print(f"4M sampled: max per-particle error / S_i {per.max():.2e}")
+    assert per.max() <= 1e-5
     # cell list of the full system is bit-exact
     cs, ids = sim.cells()
     cso, idso = oracle.bin_cells(cfg, x)
@@ -202,16 +211,19 @@ def test_forces_full_size_sampled(dpd):
     sim.close()
 
 
-def test_forces_200k_sampled(dpd):
-    cfg = dict(C2, gamma=20.0, gamma_s=5.0)
+@pytest.mark.parametrize("k,gz", list(enumerate(inputs.GAMMA_ZETA_GRID_200K)),
+                         ids=[f"gamma{g:g}-zeta{z:g}" for g, z in inputs.GAMMA_ZETA_GRID_200K])
+def test_forces_200k_grid_sampled(dpd, k, gz):
+    # every point of the 200k-particle gamma x zeta grid, from its own seed
+    g, z = gz
+    cfg = dict(C2, gamma=g, gamma_s=z, seed=201 + k)
     x, v = inputs.initial_state(cfg, thermal=True)
     sim = make_sim(dpd, cfg, x, v, step=11)
     F = host(sim.forces())
-    idx = np.random.default_rng(1).choice(len(x), 4000, replace=False)
-    Fo = oracle.forces_subset(cfg, x, v, 11, idx)
-    err = np.sqrt(((F[idx].astype(np.float64) - Fo) ** 2).sum(1))
-    scale = np.sqrt((Fo ** 2).sum(1)) + 25.0
-    assert (err / scale).max() <= 1e-5
+    idx = np.random.default_rng(1 + k).choice(len(x), 3000, replace=False)
+    per, _ = _sampled_errors(cfg, x, v, 11, F, idx)
+    print(f"200k gamma={g} zeta={z}: max per-particle error / S_i {per.max():.2e}")
+    assert per.max() <= 1e-5
     sim.close()
 
 
