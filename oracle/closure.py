@@ -9,10 +9,13 @@ between them, input channels (u_x, u_y, conditions), output added to u:
 
 with off(tap) = (tap mod 3 - 1, floor(tap / 3) - 1) as (dx, dy).  The loss is
 the mean of (pred - target)^2 over every value; the gradients are those of
-that loss, by the chain rule written out layer by layer.  Optionally
-(bf16_ops=True) the operands are rounded to BF16 where the GPU rounds them: the
-weights and activations entering a convolution, and the output gradient
-entering an input-gradient convolution; every sum is FP64.  Adam follows
+that loss, by the chain rule written out layer by layer.  The network is
+defined with BF16 weights and activations as the operands of its
+convolutions (FP32-or-better sums): with bf16_ops=True the operands are
+rounded to BF16 (nearest, ties to even) at exactly those points - the weights
+and activations entering a convolution, and the output gradient entering an
+input-gradient convolution - and every sum is FP64; with bf16_ops=False it is
+the same network in plain FP64, which bounds what the BF16 operands cost.  Adam follows
 Kingma & Ba (ICLR 2015), Algorithm 1.
 """
 from __future__ import annotations
