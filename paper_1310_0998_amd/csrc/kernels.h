@@ -23,9 +23,14 @@ constexpr int kBlock = 256;  // threads per block of the streaming kernels
 constexpr int kTileX = 8, kTileY = 7;                // default tile (cells)
 constexpr int kTileMax = 8;                          // largest tile side
 constexpr int kLocMax = (kTileMax + 2) * (kTileMax + 2);  // tile + halo cells
-constexpr int kCap = 192;   // staged particles (tile + halo); indices fit a byte, 0xFF = none
-constexpr int kTP = 128;    // tile particles (7-bit index in a kept pair)
-constexpr int kEcap = 256;  // kept pairs per tile
+// Capacities of a tile in LDS, about 4-5 standard deviations above what an
+// 8 x 7 tile holds at one particle per cell (56 tile particles, 90 staged, about
+// 100 kept pairs); a tile over any of them goes to the global-memory kernel
+// (the same results bit for bit).  Small capacities keep the LDS of a
+// wavefront near 6 KB, so that about 25 wavefronts fit on a CU.
+constexpr int kCap = 128;   // staged particles (tile + halo); indices fit a byte, 0xFF = none
+constexpr int kTP = 96;     // tile particles
+constexpr int kEcap = 192;  // kept pairs per tile
 constexpr int kItems = kCap / kWave;  // staged particles per lane
 constexpr int kLcap = 512;  // listed pairs per tile (Verlet skin)
 
@@ -313,6 +318,39 @@ __device__ __forceinline__ int wave_scan_excl(int v, int& total) {
     return incl - v;
 }
 
+// Inclusive prefix sum and prefix maximum over the 64 lanes with DPP lane
+// moves (no LDS round trip): sums within rows of 16 lanes by shifts of 1, 2,
+// 4 and 8, then each row adds the last lane of the rows before it (row_bcast
+// of lanes 15 and 31).  A lane whose source lies outside its row takes the
+// identity (0 for the sum; for the maximum, callers pass values >= 0 and -1
+// as "none", and 0 <= any value keeps the maximum).
+__device__ __forceinline__ int wave_incl_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));
+    return v;
+}
+
+// Exclusive prefix sum over the lanes; total = the sum of all 64.
+__device__ __forceinline__ int wave_excl_sum(int v, int& total) {
+    const int incl = wave_incl_sum(v);
+    total = __builtin_amdgcn_readlane(incl, kWave - 1);
+    return incl - v;
+}
+
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
@@ -413,7 +451,7 @@ __device__ __forceinline__ bool pair_sums(const DevParams& P, uint32_t step, boo
 // parameters from a.reps (the kernel argument P is then unused).
 template <int MODE, bool SKIN, bool BATCH>
 __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int reduce) {
-    __shared__ int s_ofs[kLocMax + 1];       // first staged index of each local cell
+    __shared__ unsigned char s_ofs[kLocMax + 1];  // first staged index of each local cell
     __shared__ int s_gbeg[kLocMax];          // first global slot of each local cell
     __shared__ unsigned char s_tofs[kLocMax];  // first tile index of each local cell
     __shared__ unsigned char s_lcell[kCap];  // local cell of each staged index
@@ -423,12 +461,13 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
     __shared__ unsigned char s_tslot[kTP];   // tile index -> staged index
     __shared__ unsigned char s_partner[kTP]; // tile index -> staged index of the partner
     __shared__ unsigned short s_pair[kEcap]; // kept pair: staged index of the tile particle << 8 | other
-    // one buffer, two lifetimes: ids in arrival order while staging, fixed-point
-    // force sums after
+    // one buffer, three lifetimes: ids in arrival order while staging, the
+    // candidate list of phase A, fixed-point force sums after
     constexpr int kPhaseBytes = kTP * 16;
     static_assert(kPhaseBytes >= kCap * 4, "phase buffer too small");
     __shared__ __align__(16) unsigned char s_phase[kPhaseBytes];
     int* s_tmpid = reinterpret_cast<int*>(s_phase);                       // [kCap]
+    constexpr int kCand = kPhaseBytes / 2;  // candidate pairs of phase A
     long long (*s_acc)[2] = reinterpret_cast<long long (*)[2]>(s_phase);  // [kTP][2]
 
     // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs, so give
@@ -488,29 +527,41 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
         const int v0 = cnt[0] + (tcell[0] ? cnt[0] << 16 : 0);
         const int v1 = cnt[1] + (tcell[1] ? cnt[1] << 16 : 0);
         int tot;
-        const int ex = wave_scan_excl(v0 + v1, tot);
+        const int ex = wave_excl_sum(v0 + v1, tot);
         const int total = tot & 0xFFFF;
         ntile = tot >> 16;
         const bool fits = !__any(big) && total <= kCap && ntile <= kTP;
+        // (offsets are only used when the tile fits, i.e. below kCap <= 255)
         if (2 * lane < nloc) {
-            s_ofs[2 * lane] = ex & 0xFFFF;
+            s_ofs[2 * lane] = (unsigned char)(ex & 0xFF);
             s_tofs[2 * lane] = (unsigned char)min(ex >> 16, 255);
         }
         if (2 * lane + 1 < nloc) {
-            s_ofs[2 * lane + 1] = (ex + v0) & 0xFFFF;
+            s_ofs[2 * lane + 1] = (unsigned char)((ex + v0) & 0xFF);
             s_tofs[2 * lane + 1] = (unsigned char)min((ex + v0) >> 16, 255);
         }
-        if (lane == 0) s_ofs[nloc] = total;
+        if (lane == 0) s_ofs[nloc] = (unsigned char)(total & 0xFF);
+        // S2 (first half): every staged index is "no cell start" (0xFF) ...
+        for (int q = lane; q < kCap; q += kWave) s_lcell[q] = 0xFF;
         __syncthreads();
 
         if (fits) {
-            // ---- S2: staged index -> local cell
+            // ---- S2: staged index -> local cell.  ... except the first staged
+            // index of each non-empty cell, which is marked with its cell; cells
+            // follow each other in staged order, so the running maximum of the
+            // marks is the cell of every staged index.
+            if (cnt[0] > 0) s_lcell[ex & 0xFF] = (unsigned char)(2 * lane);
+            if (cnt[1] > 0) s_lcell[(ex + v0) & 0xFF] = (unsigned char)(2 * lane + 1);
+            __syncthreads();
+            {
+                int carry = -1;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int lc = 2 * lane + h;
-                if (lc < nloc) {
-                    const int o = s_ofs[lc];
-                    for (int q = o; q < o + cnt[h]; ++q) s_lcell[q] = (unsigned char)lc;
+                for (int r = 0; r < kItems; ++r) {
+                    const int q = r * kWave + lane;
+                    const int m = s_lcell[q];
+                    const int lc = max(wave_incl_max(m == 0xFF ? -1 : m), carry);
+                    carry = __builtin_amdgcn_readlane(lc, kWave - 1);
+                    if (q < total) s_lcell[q] = (unsigned char)lc;
                 }
             }
             __syncthreads();
@@ -567,65 +618,86 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 }
             }
             __syncthreads();
-            // ---- A: every tile particle tests its half stencil in one loop over up
-            // to three ranges of staged indices:
+            // ---- A: the candidates of the tile's half stencil, tested as one
+            // flat list.  A tile particle's candidates are up to three ranges of
+            // staged indices:
             //   own row: the rest of the own cell and the cell to the right (from
             //            the left neighbour on when that is a halo cell);
             //   row above: the three cells of the stencil;
             //   row below: its three cells where they include halo cells (first
             //            tile row, first or last tile column).
-            // A pair is kept from a particle if the other one is in the halo or
+            // A1: each tile particle finds its ranges, and a wavefront scan of
+            // their lengths gives its offset in the list; A2: it writes its
+            // candidates there (staged index of the particle << 8 | staged index of
+            // the candidate); A3: the list is tested 64 candidates at a time, every
+            // lane busy.  A pair is kept if the other particle is in the halo or
             // later in the canonical order, so each pair inside the tile is kept
-            // once and each tile-halo pair once, from the tile side.  The bonded
-            // partner is recorded for both members.
+            // once and each tile-halo pair once, from the tile side.  Kept pairs
+            // are compacted by ballot; a bonded pair records each member as the
+            // other's partner.  The list lives in the staging buffer (free until
+            // the force sums).
+            unsigned short* s_cand = reinterpret_cast<unsigned short*>(s_phase);  // [kCand]
             const int rounds = (ntile + kWave - 1) / kWave;
-            int EL = 0;
+            int T = 0;
             for (int r = 0; r < rounds; ++r) {
                 const int k = r * kWave + lane;
-                int si = 0, b0 = 0, n0 = 0, b1 = 0, n01 = 0, b2 = 0, n = 0;
-                float4 ri = make_float4(0.f, 0.f, 0.f, 0.f);
+                int si = 0, b0 = 0, n0 = 0, bu = 0, nu = 0, bd = 0, nd = 0;
                 if (k < ntile) {
                     si = s_tslot[k];
                     const int lc = s_lcell[si];
                     const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
-                    const int dn = (ly - 1) * W + lx - 1, me = ly * W + lx - 1, up = (ly + 1) * W + lx - 1;
+                    const int me = ly * W + lx - 1, up = me + W;
                     b0 = (lx == 1) ? s_ofs[me] : si + 1;
                     n0 = s_ofs[me + 3] - b0;
-                    const int bu = s_ofs[up];
-                    n01 = n0 + (s_ofs[up + 3] - bu);
-                    b1 = bu - n0;  // j = b1 + t for n0 <= t < n01
-                    int nd = 0, bd = 0;
+                    bu = s_ofs[up];
+                    nu = s_ofs[up + 3] - bu;
                     if (ly == 1 || lx == 1 || lx == tw) {
+                        const int dn = me - W;
                         bd = s_ofs[dn];
                         nd = s_ofs[dn + 3] - bd;
                     }
-                    b2 = bd - n01;  // j = b2 + t for n01 <= t < n
-                    n = n01 + nd;
-                    ri = s_rec[si];
                 }
-                const int tmax = __builtin_amdgcn_readfirstlane(wave_max(n));
-                const int pid = __float_as_int(ri.z) ^ 1;
-                int partner = 0xFF, ptile = 0xFF;  // partner's staged index; its tile index
-                // the record of candidate t + 1 is read while candidate t is tested
-                int jn = (0 < n) ? ((0 < n0) ? b0 : ((0 < n01) ? b1 : b2)) : si;
-                float4 rn = s_rec[jn];
-                for (int t = 0; t < tmax; ++t) {
-                    const int j = jn;
-                    const float4 rj = rn;
-                    const int t1 = t + 1;
-                    jn = t1 + ((t1 < n0) ? b0 : ((t1 < n01) ? b1 : b2));
-                    jn = (t1 < n) ? jn : si;
-                    rn = s_rec[jn];
-                    const int tj = __float_as_int(rj.w);
-                    const bool mine = (t < n) && (j != si) && (tj == 0xFF || j > si);
-                    const bool isp = mine && (__float_as_int(rj.z) == pid);
-                    partner = isp ? j : partner;
-                    ptile = isp ? tj : ptile;
-                    const float dx = edge ? minimg_sub(ri.x, rj.x, P) : ri.x - rj.x;
-                    const float dy = edge ? minimg_sub(ri.y, rj.y, P) : ri.y - rj.y;
-                    const float r2 = fmaf(dx, dx, dy * dy);
-                    const unsigned short w = (unsigned short)((si << 8) | j);
-                    const bool keep = mine && !isp && interacts(cutoff_gap(P, dx, dy), r2);
+                int tot;
+                const int pos = T + wave_excl_sum(n0 + nu + nd, tot);
+                if (T + tot <= kCand) {
+                    // staged indices are below 256, so (si << 8) | j == (si << 8) + j
+                    unsigned short* dst = s_cand + pos;
+                    const int w0 = (si << 8) + b0;
+                    for (int t = 0; t < n0; ++t) dst[t] = (unsigned short)(w0 + t);
+                    dst += n0;
+                    const int wu = (si << 8) + bu;
+                    for (int t = 0; t < nu; ++t) dst[t] = (unsigned short)(wu + t);
+                    dst += nu;
+                    const int wd = (si << 8) + bd;
+                    for (int t = 0; t < nd; ++t) dst[t] = (unsigned short)(wd + t);
+                }
+                T += tot;
+            }
+            __syncthreads();
+            const bool fits_cand = T <= kCand;
+            int EL = 0;
+            if (fits_cand) {
+                for (int f0 = 0; f0 < T; f0 += kWave) {
+                    const int f = f0 + lane;
+                    bool keep = false, lk = false;
+                    unsigned short w = 0;
+                    if (f < T) {
+                        w = s_cand[f];
+                        const int si = w >> 8, j = w & 0xFF;
+                        const float4 ri = s_rec[si], rj = s_rec[j];
+                        const int tj = __float_as_int(rj.w);
+                        const bool mine = (tj == 0xFF) || (j > si);
+                        const bool isp = mine && ((__float_as_int(ri.z) ^ __float_as_int(rj.z)) == 1);
+                        if (isp) {
+                            s_partner[__float_as_int(ri.w)] = (unsigned char)j;
+                            if (tj != 0xFF) s_partner[tj] = (unsigned char)si;
+                        }
+                        const float dx = edge ? minimg_sub(ri.x, rj.x, P) : ri.x - rj.x;
+                        const float dy = edge ? minimg_sub(ri.y, rj.y, P) : ri.y - rj.y;
+                        const float r2 = fmaf(dx, dx, dy * dy);
+                        keep = mine && !isp && interacts(cutoff_gap(P, dx, dy), r2);
+                        if (keep_list) lk = mine && !isp && r2 > 0.f && r2 < P.list_rc2;
+                    }
                     const unsigned long long msk = __ballot(keep);
                     const int nk = __popcll(msk);
                     if (E + nk <= kEcap) {
@@ -633,7 +705,6 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                     }
                     E += nk;
                     if (keep_list) {
-                        const bool lk = mine && !isp && r2 > 0.f && r2 < P.list_rc2;
                         const unsigned long long ml = __ballot(lk);
                         const int nl = __popcll(ml);
                         if (EL + nl <= kLcap) {
@@ -642,13 +713,9 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                         EL += nl;
                     }
                 }
-                if (k < ntile) {
-                    if (partner != 0xFF) s_partner[k] = (unsigned char)partner;
-                    if (ptile != 0xFF) s_partner[ptile] = (unsigned char)si;
-                }
             }
             __syncthreads();
-            ok = (E <= kEcap) && (!keep_list || EL <= kLcap);
+            ok = fits_cand && (E <= kEcap) && (!keep_list || EL <= kLcap);
             if (keep_list) {
                 for (int k = lane; k < ntile; k += kWave) {
                     R->tslot[k] = s_tslot[k];
