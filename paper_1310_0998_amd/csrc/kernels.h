@@ -363,6 +363,14 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask) {
                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
+// Local cell lc -> (ly, lx) on a local grid W cells wide, by multiply-shift
+// (exact for lc < 128 and W <= 10, wmul = ceil(2^16 / W)); the operands are
+// far below 2^24, so the 24-bit multiplies (full rate) give the exact products.
+__device__ __forceinline__ void local_xy(int lc, int wmul, int W, int& ly, int& lx) {
+    ly = (int)(__umul24((unsigned)lc, (unsigned)wmul) >> 16);
+    lx = lc - (int)__umul24((unsigned)ly, (unsigned)W);
+}
+
 // Cell origin and size of tile t (row-major tiles of tile_x x tile_y cells).
 struct TileGeom {
     int cx0, cy0, tw, th;
@@ -512,9 +520,13 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
         for (int h = 0; h < 2; ++h) {
             const int lc = 2 * lane + h;
             if (lc < nloc) {
-                const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
-                const int c = (int)__umul24((unsigned)wrap_cell(cy0 - 1 + ly, P.nc), (unsigned)P.nc) +
-                              wrap_cell(cx0 - 1 + lx, P.nc);
+                int ly, lx;
+                local_xy(lc, wmul, W, ly, lx);
+                // the periodic wrap only matters for tiles at the box edge
+                const int gy = cy0 - 1 + ly, gx = cx0 - 1 + lx;
+                const int c = edge ? (int)__umul24((unsigned)wrap_cell(gy, P.nc), (unsigned)P.nc) +
+                                         wrap_cell(gx, P.nc)
+                                   : (int)__umul24((unsigned)gy, (unsigned)P.nc) + gx;
                 const int b = a.cs[c];
                 const int n = a.cs[c + 1] - b;
                 s_gbeg[lc] = b;
@@ -600,7 +612,8 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                     int rank = 0;
                     for (int t = b; t < e; ++t) rank += (s_tmpid[t] < idq[r]) ? 1 : 0;
                     const int qs = b + rank;
-                    const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
+                    int ly, lx;
+                local_xy(lc, wmul, W, ly, lx);
                     int ti = 0xFF;
                     if (lx >= 1 && lx <= tw && ly >= 1 && ly <= th) {
                         ti = s_tofs[lc] + rank;
@@ -645,7 +658,8 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 if (k < ntile) {
                     si = s_tslot[k];
                     const int lc = s_lcell[si];
-                    const int ly = (lc * wmul) >> 16, lx = lc - ly * W;
+                    int ly, lx;
+                local_xy(lc, wmul, W, ly, lx);
                     const int me = ly * W + lx - 1, up = me + W;
                     b0 = (lx == 1) ? s_ofs[me] : si + 1;
                     n0 = s_ofs[me + 3] - b0;
@@ -661,14 +675,18 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 const int pos = T + wave_excl_sum(n0 + nu + nd, tot);
                 if (T + tot <= kCand) {
                     // staged indices are below 256, so (si << 8) | j == (si << 8) + j
+                    // (loops of a few trips: kept simple, one 2-byte write each)
                     unsigned short* dst = s_cand + pos;
                     const int w0 = (si << 8) + b0;
+#pragma clang loop unroll(disable) vectorize(disable)
                     for (int t = 0; t < n0; ++t) dst[t] = (unsigned short)(w0 + t);
                     dst += n0;
                     const int wu = (si << 8) + bu;
+#pragma clang loop unroll(disable) vectorize(disable)
                     for (int t = 0; t < nu; ++t) dst[t] = (unsigned short)(wu + t);
                     dst += nu;
                     const int wd = (si << 8) + bd;
+#pragma clang loop unroll(disable) vectorize(disable)
                     for (int t = 0; t < nd; ++t) dst[t] = (unsigned short)(wd + t);
                 }
                 T += tot;
