@@ -565,36 +565,42 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
             if (cnt[0] > 0) s_lcell[ex & 0xFF] = (unsigned char)(2 * lane);
             if (cnt[1] > 0) s_lcell[(ex + v0) & 0xFF] = (unsigned char)(2 * lane + 1);
             __syncthreads();
+            // ---- S3: gather in arrival order, by the lane that found the cell
+            // (every slot load is issued before the loads that depend on it)
+            float2 xq[kItems], uq[kItems];
+            int idq[kItems], lcq[kItems], pq[kItems];
             {
                 int carry = -1;
 #pragma unroll
                 for (int r = 0; r < kItems; ++r) {
                     const int q = r * kWave + lane;
                     const int m = s_lcell[q];
-                    const int lc = max(wave_incl_max(m == 0xFF ? -1 : m), carry);
-                    carry = __builtin_amdgcn_readlane(lc, kWave - 1);
-                    if (q < total) s_lcell[q] = (unsigned char)lc;
+                    lcq[r] = max(wave_incl_max(m == 0xFF ? -1 : m), carry);
+                    carry = __builtin_amdgcn_readlane(lcq[r], kWave - 1);
                 }
             }
-            __syncthreads();
-            // ---- S3: gather in arrival order
-            float2 xq[kItems], uq[kItems];
-            int idq[kItems], lcq[kItems];
+#pragma unroll
+            for (int r = 0; r < kItems; ++r) {
+                const int q = r * kWave + lane;
+                pq[r] = P.pbase;
+                if (q < total) {
+                    const int lc = lcq[r];
+                    s_lcell[q] = (unsigned char)lc;
+                    pq[r] = a.src[s_gbeg[lc] + (q - s_ofs[lc])];
+                }
+            }
 #pragma unroll
             for (int r = 0; r < kItems; ++r) {
                 const int q = r * kWave + lane;
                 idq[r] = 0;
-                lcq[r] = 0;
                 xq[r] = make_float2(0.f, 0.f);
                 uq[r] = make_float2(0.f, 0.f);
                 if (q < total) {
-                    const int lc = s_lcell[q];
-                    int p = a.src[s_gbeg[lc] + (q - s_ofs[lc])];
+                    int p = pq[r];
                     if ((unsigned)(p - P.pbase) >= (unsigned)P.N) {  // outside this system
                         atomicOr(a.status, kStatusBinning);
                         p = P.pbase;
                     }
-                    lcq[r] = lc;
                     idq[r] = a.idin[p];
                     xq[r] = a.xin[p];
                     uq[r] = a.uin[p];
