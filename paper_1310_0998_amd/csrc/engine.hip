@@ -469,8 +469,12 @@ template <int MODE, bool BATCH>
 void launch_overflow(dpd_handle* h, const PairArgs& b, int reduce) {
     // tiles over an LDS capacity (dense clusters), if any
     const int Go = (int)std::min<long long>(h->d.tiles, 512);
-    hipLaunchKernelGGL((k_pair_overflow<MODE, BATCH>), dim3(Go), dim3(kWave), 0, h->stream, P0(h),
-                       b, reduce);
+    if (h->d.skin)  // tile records of a skin hold the small capacities only
+        hipLaunchKernelGGL((k_pair_overflow<MODE, BATCH, false>), dim3(Go), dim3(kWave), 0, h->stream,
+                           P0(h), b, reduce);
+    else
+        hipLaunchKernelGGL((k_pair_overflow<MODE, BATCH, true>), dim3(Go), dim3(kWave), 0, h->stream,
+                           P0(h), b, reduce);
 }
 
 int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {

@@ -452,47 +452,39 @@ __device__ __forceinline__ bool pair_sums(const DevParams& P, uint32_t step, boo
 //      to the first particle and subtracted from the second (Newton's third
 //      law) with LDS integer atomics - exact, so the order does not matter;
 //   C  every tile particle adds its agent forces and finishes the step.
-// A tile that overflows an LDS capacity is left to k_pair_overflow.
+// A tile that overflows an LDS capacity (CAP staged particles, TP tile
+// particles, ECAP kept pairs) is left to k_pair_overflow (returns false).
 // SKIN compiles the Verlet-skin code (records, list steps, displacement test)
 // in; without it the kernel carries none of it.  BATCH: the tiles of all
 // replicas of a batch form one launch; each wavefront reads its replica's
 // parameters from a.reps (the kernel argument P is then unused).
-template <int MODE, bool SKIN, bool BATCH>
-__global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int reduce) {
+template <int MODE, bool SKIN, bool BATCH, int CAP, int TP, int ECAP>
+__device__ __forceinline__ bool pair_tile(DevParams P, PairArgs a, int reduce, int gtile) {
+    constexpr int kItemsT = CAP / kWave;  // staged particles per lane
+    static_assert(CAP % kWave == 0 && CAP <= 255 && TP <= 255, "tile capacities");
     __shared__ unsigned char s_ofs[kLocMax + 1];  // first staged index of each local cell
     __shared__ int s_gbeg[kLocMax];          // first global slot of each local cell
     __shared__ unsigned char s_tofs[kLocMax];  // first tile index of each local cell
-    __shared__ unsigned char s_lcell[kCap];  // local cell of each staged index
-    __shared__ float4 s_rec[kCap];           // x, y, id, tile index (0xFF: halo)
-    __shared__ float2 s_u[kCap];
-    __shared__ int s_slot[SKIN ? kCap : 1];  // global slot of each staged index (skin only)
-    __shared__ unsigned char s_tslot[kTP];   // tile index -> staged index
-    __shared__ unsigned char s_partner[kTP]; // tile index -> staged index of the partner
-    __shared__ unsigned short s_pair[kEcap]; // kept pair: staged index of the tile particle << 8 | other
+    __shared__ unsigned char s_lcell[CAP];  // local cell of each staged index
+    __shared__ float4 s_rec[CAP];           // x, y, id, tile index (0xFF: halo)
+    __shared__ float2 s_u[CAP];
+    __shared__ int s_slot[SKIN ? CAP : 1];  // global slot of each staged index (skin only)
+    __shared__ unsigned char s_tslot[TP];   // tile index -> staged index
+    __shared__ unsigned char s_partner[TP]; // tile index -> staged index of the partner
+    __shared__ unsigned short s_pair[ECAP]; // kept pair: staged index of the tile particle << 8 | other
     // one buffer, three lifetimes: ids in arrival order while staging, the
     // candidate list of phase A, fixed-point force sums after
-    constexpr int kPhaseBytes = kTP * 16;
-    static_assert(kPhaseBytes >= kCap * 4, "phase buffer too small");
+    constexpr int kPhaseBytes = TP * 16;
+    static_assert(kPhaseBytes >= CAP * 4, "phase buffer too small");
     __shared__ __align__(16) unsigned char s_phase[kPhaseBytes];
-    int* s_tmpid = reinterpret_cast<int*>(s_phase);                       // [kCap]
+    int* s_tmpid = reinterpret_cast<int*>(s_phase);                       // [CAP]
     constexpr int kCand = kPhaseBytes / 2;  // candidate pairs of phase A
-    long long (*s_acc)[2] = reinterpret_cast<long long (*)[2]>(s_phase);  // [kTP][2]
+    long long (*s_acc)[2] = reinterpret_cast<long long (*)[2]>(s_phase);  // [TP][2]
 
-    // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs, so give
-    // each XCD a contiguous band of tiles (neighbouring halos share its L2).
-    const int nt = BATCH ? a.nt_total : P.ntx * P.nty;
-    const int bid = blockIdx.x;
-    int gtile = bid;
-    if (a.tile_order == 0) {
-        const int xcd = bid & 7, kk = bid >> 3;
-        const int per = nt >> 3, rem = nt & 7;
-        gtile = xcd * per + min(xcd, rem) + kk;
-    }
     if constexpr (BATCH) {
         P = a.reps[a.tile_rep[gtile]];
         a.cs += P.cbase;
     }
-    if (a.step_base) a.step += *a.step_base;
     const int tile = BATCH ? gtile - P.tbase : gtile;
     const TileGeom G = tile_geom(P, tile);
     const int cx0 = G.cx0, cy0 = G.cy0, tw = G.tw, th = G.th;
@@ -530,20 +522,20 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 const int b = a.cs[c];
                 const int n = a.cs[c + 1] - b;
                 s_gbeg[lc] = b;
-                big |= (n > kCap) || (n < 0);
-                cnt[h] = min(max(n, 0), kCap);
+                big |= (n > CAP) || (n < 0);
+                cnt[h] = min(max(n, 0), CAP);
                 tcell[h] = (lx >= 1 && lx <= tw && ly >= 1 && ly <= th);
             }
         }
-        // staged counts in the low 16 bits, tile counts in the high 16 (each <= 100 * kCap)
+        // staged counts in the low 16 bits, tile counts in the high 16 (each <= 100 * CAP)
         const int v0 = cnt[0] + (tcell[0] ? cnt[0] << 16 : 0);
         const int v1 = cnt[1] + (tcell[1] ? cnt[1] << 16 : 0);
         int tot;
         const int ex = wave_excl_sum(v0 + v1, tot);
         const int total = tot & 0xFFFF;
         ntile = tot >> 16;
-        const bool fits = !__any(big) && total <= kCap && ntile <= kTP;
-        // (offsets are only used when the tile fits, i.e. below kCap <= 255)
+        const bool fits = !__any(big) && total <= CAP && ntile <= TP;
+        // (offsets are only used when the tile fits, i.e. below CAP <= 255)
         if (2 * lane < nloc) {
             s_ofs[2 * lane] = (unsigned char)(ex & 0xFF);
             s_tofs[2 * lane] = (unsigned char)min(ex >> 16, 255);
@@ -554,7 +546,7 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
         }
         if (lane == 0) s_ofs[nloc] = (unsigned char)(total & 0xFF);
         // S2 (first half): every staged index is "no cell start" (0xFF) ...
-        for (int q = lane; q < kCap; q += kWave) s_lcell[q] = 0xFF;
+        for (int q = lane; q < CAP; q += kWave) s_lcell[q] = 0xFF;
         __syncthreads();
 
         if (fits) {
@@ -567,12 +559,12 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
             __syncthreads();
             // ---- S3: gather in arrival order, by the lane that found the cell
             // (every slot load is issued before the loads that depend on it)
-            float2 xq[kItems], uq[kItems];
-            int idq[kItems], lcq[kItems], pq[kItems];
+            float2 xq[kItemsT], uq[kItemsT];
+            int idq[kItemsT], lcq[kItemsT], pq[kItemsT];
             {
                 int carry = -1;
 #pragma unroll
-                for (int r = 0; r < kItems; ++r) {
+                for (int r = 0; r < kItemsT; ++r) {
                     const int q = r * kWave + lane;
                     const int m = s_lcell[q];
                     lcq[r] = max(wave_incl_max(m == 0xFF ? -1 : m), carry);
@@ -580,7 +572,7 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 }
             }
 #pragma unroll
-            for (int r = 0; r < kItems; ++r) {
+            for (int r = 0; r < kItemsT; ++r) {
                 const int q = r * kWave + lane;
                 pq[r] = P.pbase;
                 if (q < total) {
@@ -590,7 +582,7 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 }
             }
 #pragma unroll
-            for (int r = 0; r < kItems; ++r) {
+            for (int r = 0; r < kItemsT; ++r) {
                 const int q = r * kWave + lane;
                 idq[r] = 0;
                 xq[r] = make_float2(0.f, 0.f);
@@ -610,7 +602,7 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
             __syncthreads();
             // ---- S4: place every particle at its rank by id within its cell
 #pragma unroll
-            for (int r = 0; r < kItems; ++r) {
+            for (int r = 0; r < kItemsT; ++r) {
                 const int q = r * kWave + lane;
                 if (q < total) {
                     const int lc = lcq[r];
@@ -724,7 +716,7 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                     }
                     const unsigned long long msk = __ballot(keep);
                     const int nk = __popcll(msk);
-                    if (E + nk <= kEcap) {
+                    if (E + nk <= ECAP) {
                         if (keep) s_pair[E + lanes_below(msk)] = w;
                     }
                     E += nk;
@@ -739,7 +731,7 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 }
             }
             __syncthreads();
-            ok = fits_cand && (E <= kEcap) && (!keep_list || EL <= kLcap);
+            ok = fits_cand && (E <= ECAP) && (!keep_list || EL <= kLcap);
             if (keep_list) {
                 for (int k = lane; k < ntile; k += kWave) {
                     R->tslot[k] = s_tslot[k];
@@ -759,8 +751,8 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
         // ---- L: between rebuilds: the staged set and the pair list of the record
         const int valid = R->valid;
         if (valid) {
-            ntile = min(R->ntile, kTP);
-            const int total = min(R->total, kCap), nlist = min(R->nlist, kLcap);
+            ntile = min(R->ntile, TP);
+            const int total = min(R->total, CAP), nlist = min(R->nlist, kLcap);
             for (int q = lane; q < total; q += kWave) {
                 int g = R->slot[q];
                 if ((unsigned)(g - P.pbase) >= (unsigned)P.N) {
@@ -790,22 +782,18 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
                 }
                 const unsigned long long msk = __ballot(keep);
                 const int nk = __popcll(msk);
-                if (E + nk <= kEcap) {
+                if (E + nk <= ECAP) {
                     if (keep) s_pair[E + lanes_below(msk)] = w;
                 }
                 E += nk;
             }
             __syncthreads();
-            ok = E <= kEcap;
+            ok = E <= ECAP;
         }
     }
 
     double rv[3] = {0.0, 0.0, 0.0};
-    if (!ok) {
-        // over an LDS capacity: leave the tile to k_pair_overflow
-        if (lane == 0) a.ovf_list[atomicAdd(a.ovf_count, 1)] = gtile;
-        return;
-    }
+    if (!ok) return false;  // over an LDS capacity
     for (int k = lane; k < ntile; k += kWave) {
         s_acc[k][0] = 0;
         s_acc[k][1] = 0;
@@ -851,6 +839,26 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
         finish_particle<MODE, SKIN>(P, a, g, xi, ui, idi, fx, fy, rv, reduce != 0, rebuild);
     }
     if (reduce) tile_reduce(a, gtile, rv);
+    return true;
+}
+
+// The fast pair kernel: one wavefront per tile with the small capacities; a
+// tile over one of them is listed for k_pair_overflow.
+template <int MODE, bool SKIN, bool BATCH>
+__global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int reduce) {
+    // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs, so give
+    // each XCD a contiguous band of tiles (neighbouring halos share its L2).
+    const int nt = BATCH ? a.nt_total : P.ntx * P.nty;
+    const int bid = blockIdx.x;
+    int gtile = bid;
+    if (a.tile_order == 0) {
+        const int xcd = bid & 7, kk = bid >> 3;
+        const int per = nt >> 3, rem = nt & 7;
+        gtile = xcd * per + min(xcd, rem) + kk;
+    }
+    if (a.step_base) a.step += *a.step_base;
+    if (!pair_tile<MODE, SKIN, BATCH, kCap, kTP, kEcap>(P, a, reduce, gtile) && threadIdx.x == 0)
+        a.ovf_list[atomicAdd(a.ovf_count, 1)] = gtile;
 }
 
 // Slow path for a tile that overflows an LDS capacity (dense clusters), one
@@ -984,14 +992,23 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
     }
 }
 
-// The tiles k_pair left over, one 64-lane wavefront per listed tile, through
-// the global-memory path (same results bit for bit).  Launched right after
-// k_pair with a fixed grid; with an empty list every wavefront exits at once.
-template <int MODE, bool REBUILT, bool BATCH>
+// The tiles k_pair left over, one 64-lane wavefront per listed tile (same
+// results bit for bit).  Launched right after k_pair with a fixed grid; with an
+// empty list every wavefront exits at once.  RETRY (handles without a Verlet
+// skin): a listed tile is first run through the tile body with the large LDS
+// capacities, which holds tiles up to about twice the usual load (the uneven
+// cells of a random start, denser systems); only tiles over those go to the
+// global-memory path.
+constexpr int kCapBig = 192, kTPBig = 128, kEcapBig = 384;
+
+template <int MODE, bool REBUILT, bool BATCH, bool RETRY>
 __device__ __forceinline__ void overflow_tiles(const DevParams& P0, const PairArgs& a0, int n,
                                                int reduce) {
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int gtile = a0.ovf_list[i];
+        if constexpr (RETRY) {
+            if (pair_tile<MODE, false, BATCH, kCapBig, kTPBig, kEcapBig>(P0, a0, reduce, gtile)) continue;
+        }
         DevParams P = P0;
         PairArgs a = a0;
         if constexpr (BATCH) {
@@ -1005,14 +1022,14 @@ __device__ __forceinline__ void overflow_tiles(const DevParams& P0, const PairAr
     }
 }
 
-template <int MODE, bool BATCH>
+template <int MODE, bool BATCH, bool RETRY>
 __global__ __launch_bounds__(kWave) void k_pair_overflow(DevParams P, PairArgs a, int reduce) {
     const int n = *a.ovf_count;
     if (a.step_base) a.step += *a.step_base;
     if (MODE == MODE_FORCES || a.rebuild == nullptr || *a.rebuild != 0)
-        overflow_tiles<MODE, true, BATCH>(P, a, n, reduce);
+        overflow_tiles<MODE, true, BATCH, RETRY>(P, a, n, reduce);
     else
-        overflow_tiles<MODE, false, BATCH>(P, a, n, reduce);
+        overflow_tiles<MODE, false, BATCH, false>(P, a, n, reduce);
 }
 
 // ---- binning ------------------------------------------------------------------

@@ -476,6 +476,33 @@ def test_dense_cluster_steps(dpd):
     sim.close()
 
 
+def test_large_capacity_retry_path(dpd):
+    # at 1.6 particles per cell, 8 x 8 tiles hold about 102 tile particles and
+    # 160 staged ones: over the fast kernel's LDS capacities (96 / 128) but
+    # within the large ones its overflow kernel tries first, so nearly every
+    # tile runs there.  Forces match the oracle, and the trajectory is bitwise
+    # the one of 4 x 4 tiles, which stay in the fast kernel.
+    n_agents = 2560
+    cfg = dict(C1, n_agents=n_agents, L=40.0, seed=23, tile=8)
+    x, v = inputs.initial_state(cfg, thermal=True)
+    a = make_sim(dpd, cfg, x, v, step=5)
+    F = host(a.forces())
+    per, glob = force_errors(cfg, x, v, 5, F)
+    assert per.max() <= 1e-5 and glob <= 1e-5, (per.max(), glob)
+    b = make_sim(dpd, dict(cfg, tile=4), x, v, step=5)
+    assert (host(b.forces()) == F).all()
+    pa = host(a.step(60, reduce_every=20))
+    pb = host(b.step(60, reduce_every=20))
+    sa = [host(t) for t in a.get_state()[:3]]
+    sb = [host(t) for t in b.get_state()[:3]]
+    for u, w in zip(sa, sb):
+        assert (u == w).all()
+    # the FP64 reductions run over other tiles, so only to rounding
+    assert pa == pytest.approx(pb, rel=1e-12, abs=1e-12)
+    a.close()
+    b.close()
+
+
 def test_dense_cluster_reductions_run_to_run(dpd):
     # tiles of a dense cluster take the global-memory kernel, whose lanes take
     # the members of each tile in canonical order: the FP64 momentum and
