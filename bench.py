@@ -366,9 +366,13 @@ def _finite(o):
 
 
 def run_closure(args):
-    """The learned closure: DPD-generated training pairs, training on the GPU,
-    then an ensemble of closure rollouts against the same ensemble of DPD runs, timed,
-    with the energy-spectrum and correlation-length errors of the rollout."""
+    """The learned closure: DPD-generated training pairs (independent replicas
+    of every condition), training on the GPU, noise calibrated against the
+    judged condition's training fields, then an ensemble of closure rollouts
+    against an independent ensemble of DPD runs, timed, with the
+    energy-spectrum, correlation-length and mode-autocorrelation errors.  The
+    zero network (persistence, u(t + 50) = u(t)) goes through the same
+    calibration and judge as the control of what the network adds."""
     import torch
 
     from paper_1310_0998_amd import closure, closure_train as ct, inputs
@@ -379,41 +383,54 @@ def run_closure(args):
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     train_idx, test_idx = ct.split(runs)
-    # batches of 32 in training; the judged rollout runs one field per replica
-    net = closure.Closure(ct.M, c_in=4, width=32, layers=4, max_batch=max(32, args.closure_ensemble),
-                          device=dev)
+    E, T = args.closure_ensemble, args.closure_steps
+    mk = lambda: closure.Closure(ct.M, c_in=4, width=32, layers=4, max_batch=max(32, E), device=dev)
+    net = mk()
     net.set_weights(torch.from_numpy(inputs.closure_init(601, 4, 32, 4)).to(dev))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist, n_upd = ct.train(net, runs, train_idx, dev, epochs=args.closure_epochs, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    zero = mk()
+    zero.set_weights(torch.zeros(zero.n_params, dtype=torch.float32, device=dev))
     mse_net, mse_per, _ = ct.evaluate(net, runs, test_idx, dev)
     _, _, res = ct.evaluate(net, runs, train_idx, dev)
     log(f"held-out one-step MSE: network {mse_net:.5e}, persistence {mse_per:.5e}; "
         f"training residual rms {res[0]:.4f} {res[1]:.4f}")
-    for run in runs:
-        run["sim"].close()
     r_judge = 4  # zeta = 0.5, F_p = 1
-    idx_r = [q for q in train_idx if q[0] == r_judge]
-    h0, R0 = ct.residual_filter(net, runs, idx_r, dev)
-    E, T = args.closure_ensemble, args.closure_steps
+    idx_r = [q for q in train_idx if runs[q[0]]["run"] == r_judge]
     cond = torch.tensor(ct.runs_cond(r_judge), dtype=torch.float32, device=dev)
-    cstart, cfields, t_cal = ct.ensemble(r_judge, E, args.closure_warm, T, 1000, dev, log=log)
-    h, _, cal = ct.calibrate_filter(net, cstart, cfields, cond, R0, dev, log=log)
-    del cfields
+    # calibration: rollouts from the judged condition's training fields, against
+    # the spectrum of those fields (no DPD beyond the training data)
+    target = ct.condition_fields(runs, r_judge)
+    cstart = ct.training_starts(runs, r_judge, E)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    filters = {}
+    for name, model in (("network", net), ("zero", zero)):
+        h0, R0 = ct.residual_filter(model, runs, idx_r, dev)
+        h, _, cal = ct.calibrate_filter(model, cstart, target, args.closure_cal_steps, cond, R0, dev, log=log)
+        filters[name] = (h0, h, cal)
+    torch.cuda.synchronize()
+    t_cal = time.perf_counter() - t0
     jstart, jfields, t_dpd = ct.ensemble(r_judge, E, args.closure_warm, T, 2000, dev, log=log)
-    noises = {"calibrated": ((1.0, 1.0), h), "residual": ((1.0, 1.0), h0),
-              "white": ((float(res[0]), float(res[1])), None)}
-    j = ct.judge(net, r_judge, jstart, jfields, t_dpd, noises, dev, log=log)
+    models = {"calibrated": (net, (1.0, 1.0), filters["network"][1]),
+              "residual": (net, (1.0, 1.0), filters["network"][0]),
+              "white": (net, (float(res[0]), float(res[1])), None),
+              "zero_calibrated": (zero, (1.0, 1.0), filters["zero"][1]),
+              "zero_no_noise": (zero, (0.0, 0.0), None)}
+    j = ct.judge(models, r_judge, jstart, jfields, t_dpd, dev, log=log)
     del jfields
     jm = j["models"]["calibrated"]
+    jz = j["models"]["zero_calibrated"]
     valid = jm["max_band_err"] <= 0.05
     speed = j["t_dpd"] / jm["t_closure"]
+    one_time = t_gen + t_train + t_cal
     line = {
         "metric": "closure speedup at <=5% E(k) err",
         "value": speed,
-        "unit": "x (plain DPD wall time / closure wall time, same span)",
+        "unit": "x (plain DPD wall time / closure wall time, same span; one-time costs apart)",
         "n_gpus": 1,
         "steps": args.closure_steps,
         "warmup": 0,
@@ -426,21 +443,22 @@ def run_closure(args):
         "valid": valid,
         "config": {
             "workload": "closure: 200k particles (100k dimers, L=447), gamma=4.5, zeta {0,0.5} x F_p "
-                        "{0.5,1,2}; 64x64 binned velocity every 10 steps; pairs 50 steps apart; "
-                        "4 conv layers, 32 channels, 3x3 periodic; judged at zeta=0.5, F_p=1: "
-                        f"{E} independent replicas (one batch) x {T * ct.INTERVAL} DPD steps against "
-                        f"{E} batched closure rollouts x {T} steps from the same fields, noise filtered "
-                        "to the training residual's spectrum and scaled per shell to a separate "
-                        f"calibration ensemble ({E} replicas x {T * ct.INTERVAL} steps, other seeds)",
+                        f"{{0.5,1,2}}, {ct.REPLICAS} independent replicas per condition; 64x64 binned "
+                        "velocity every 10 steps; pairs 50 steps apart; 4 conv layers, 32 channels, 3x3 "
+                        f"periodic; judged at zeta=0.5, F_p=1: {E} independent DPD replicas (one batch, "
+                        f"own seeds) x {T * ct.INTERVAL} steps against {E} batched closure rollouts x {T} "
+                        "steps from the same fields; rollout noise filtered to the training residual's "
+                        "spectrum, scaled per shell until a rollout reproduces the spectrum of the "
+                        "judged condition's training fields",
             "pairs_train": len(train_idx),
             "pairs_test": len(test_idx),
             "epochs": args.closure_epochs,
             "adam_steps": n_upd,
             "parallelism": "single-gpu",
         },
-        "timing_s": {"generate": t_gen, "train": t_train, "calibration_dpd": t_cal,
-                     "dpd_span": j["t_dpd"],
-                     "closure_span": jm["t_closure"]},
+        "timing_s": {"generate": t_gen, "train": t_train, "calibrate": t_cal,
+                     "dpd_span": j["t_dpd"], "closure_span": jm["t_closure"]},
+        "speedup_with_one_time_costs": j["t_dpd"] / (jm["t_closure"] + one_time),
         "one_step_mse": {"network": mse_net, "persistence": mse_per,
                          "gain_over_persistence": mse_per / mse_net},
         "E_band_err": jm["band_err"],
@@ -448,9 +466,21 @@ def run_closure(args):
         "E_band_ref_rel_se": j["band_ref_se"],
         "max_E_band_err": jm["max_band_err"],
         "L_gv": {"dpd": j["L_gv_ref"], "closure": jm["L_gv_closure"], "rel_err": jm["L_gv_err"]},
-        "calibration_max_shell_dev": cal,
+        "autocorrelation": {"lags_coarse_steps": j["ac_lags"], "dpd": j["ac_ref"], "closure": jm["ac"],
+                            "max_abs_err": jm["max_ac_err"]},
+        "calibration_max_shell_dev": filters["network"][2],
+        "zero_network_control": {
+            "calibrated_noise": {"E_band_err": jz["band_err"], "max_E_band_err": jz["max_band_err"],
+                                 "L_gv_rel_err": jz["L_gv_err"], "autocorrelation": jz["ac"],
+                                 "max_ac_err": jz["max_ac_err"],
+                                 "calibration_max_shell_dev": filters["zero"][2]},
+            "no_noise": {"E_band_err": j["models"]["zero_no_noise"]["band_err"],
+                         "max_E_band_err": j["models"]["zero_no_noise"]["max_band_err"],
+                         "max_ac_err": j["models"]["zero_no_noise"]["max_ac_err"]},
+        },
         "residual_spectrum_noise": {"E_band_err": j["models"]["residual"]["band_err"],
-                                    "L_gv_rel_err": j["models"]["residual"]["L_gv_err"]},
+                                    "L_gv_rel_err": j["models"]["residual"]["L_gv_err"],
+                                    "max_ac_err": j["models"]["residual"]["max_ac_err"]},
         "white_noise": {"noise_std": [float(res[0]), float(res[1])],
                         "E_band_err": j["models"]["white"]["band_err"],
                         "L_gv_rel_err": j["models"]["white"]["L_gv_err"]},
@@ -458,6 +488,7 @@ def run_closure(args):
     }
     print(json.dumps(_finite(line)), flush=True)
     net.close()
+    zero.close()
 
 
 def run_rollout(args):
@@ -589,6 +620,8 @@ def main():
                     help="DPD warm-up steps of each ensemble before its fields are taken")
     ap.add_argument("--closure-steps", type=int, default=2000,
                     help="closure steps of the judged rollout (x50 DPD steps)")
+    ap.add_argument("--closure-cal-steps", type=int, default=1000,
+                    help="closure steps of each calibration rollout")
     ap.add_argument("--rollout-steps", type=int, default=200,
                     help="batched closure steps (workload rollout)")
     ap.add_argument("--grid-steps", type=int, default=10000,

@@ -113,3 +113,39 @@ def integral_length(r, g, L: float, to_first_zero: bool = True) -> float:
             r = np.concatenate([r[:i], [r0]])
             g = np.concatenate([g[:i], [0.0]])
     return float(np.trapezoid(g, r))
+
+
+def band_index(M: int) -> np.ndarray:
+    """Band of every Fourier mode (l, k): 0 for shell 1, 1 for shells 2-3, 2 for
+    4-7, ... (the bands of `bands`), -1 for k = 0 and shells beyond M/2."""
+    s = np.floor(_kmag(M) + 0.5).astype(np.int64)
+    b = np.full(s.shape, -1, np.int64)
+    ok = (s >= 1) & (s <= M // 2)
+    b[ok] = np.floor(np.log2(s[ok])).astype(np.int64)
+    return b
+
+
+def band_autocorrelation(fields: torch.Tensor, lags) -> np.ndarray:
+    """Temporal autocorrelation of the Fourier modes of trajectories
+    fields [T][B][M][M][2] (CUDA FP32), per shell band and lag tau (in field
+    steps): C_b(tau) = sum Re(u^_t conj u^_{t+tau}) / sum (|u^_t|^2 + |u^_{t+tau}|^2) / 2
+    over the modes of band b, both components, t and the B trajectories.
+    The cross term comes from the power spectra of u_t + u_{t+tau} and
+    u_t - u_{t+tau} (polarisation: 4 Re(a conj b) = |a + b|^2 - |a - b|^2),
+    so only the GPU power kernel is used.  Returns [n_bands][len(lags)]."""
+    T, B, M = int(fields.shape[0]), int(fields.shape[1]), int(fields.shape[2])
+    bi = band_index(M)
+    nb = int(bi.max()) + 1
+    out = np.zeros((nb, len(lags)))
+    for j, tau in enumerate(lags):
+        num = np.zeros(nb)
+        den = np.zeros(nb)
+        for q in range(B):
+            a = fields[:T - tau, q]
+            b = fields[tau:, q]
+            Pp = power((a + b).contiguous())
+            Pm = power((a - b).contiguous())
+            num += np.bincount(bi[bi >= 0], (Pp - Pm)[bi >= 0], nb)
+            den += np.bincount(bi[bi >= 0], (Pp + Pm)[bi >= 0], nb)
+        out[:, j] = num / np.maximum(den, 1e-300)
+    return out

@@ -299,6 +299,35 @@ def test_field_power_and_statistics_match_oracle(cl):
     assert fs.integral_length(r, g, L) == pytest.approx(oa.integral_length(ro, go, L, True), rel=1e-4)
 
 
+def test_band_autocorrelation_matches_direct_sum(cl):
+    # the per-band temporal autocorrelation (from power spectra of sums and
+    # differences of fields) against the direct sum of Re(u^_t conj u^_t+tau)
+    # over the oracle's Fourier coefficients, on AR(1) fields
+    from oracle import analysis as oa
+    from paper_1310_0998_amd import fieldstats as fs
+    rng = np.random.default_rng(16)
+    T, B, M = 40, 3, 16
+    f = np.zeros((T, B, M, M, 2))
+    f[0] = rng.normal(size=(B, M, M, 2))
+    for t in range(1, T):
+        f[t] = 0.8 * f[t - 1] + 0.6 * rng.normal(size=(B, M, M, 2))
+    f = f.astype(np.float32)
+    lags = (1, 3, 7)
+    got = fs.band_autocorrelation(dev(f), lags)
+    uh = np.array([[oa.fourier_coefficients(f[t, q].astype(np.float64)) for q in range(B)]
+                   for t in range(T)])
+    s = np.floor(oa.wavenumber_magnitude(M) + 0.5).astype(np.int64)
+    for j, tau in enumerate(lags):
+        num = (uh[:-tau] * np.conj(uh[tau:])).real.sum(axis=(0, 1, 4))
+        den = 0.5 * (np.abs(uh[:-tau]) ** 2 + np.abs(uh[tau:]) ** 2).sum(axis=(0, 1, 4))
+        lo, b = 1, 0
+        while lo <= M // 2:
+            m = (s >= lo) & (s <= min(2 * lo - 1, M // 2))
+            assert got[b, j] == pytest.approx(num[m].sum() / den[m].sum(), abs=1e-6)
+            lo, b = 2 * lo, b + 1
+    assert got.shape == (b, len(lags))
+
+
 def test_closure_beats_persistence_on_dpd_fields(cl):
     # the trained network against the method without it: on held-out pairs of
     # DPD-generated fields (later in time than the training pairs) its one-step
@@ -306,7 +335,7 @@ def test_closure_beats_persistence_on_dpd_fields(cl):
     # correlation of about 0.9 over 50 steps, so even the best linear
     # predictor rho u(t) gains only about 5 % over persistence here.
     from paper_1310_0998_amd import closure_train as ct
-    runs = ct.generate(DEV, pairs_per_run=80, warm=1000, log=print)
+    runs = ct.generate(DEV, pairs_per_run=80, warm=1000, replicas=2, log=print)
     train_idx, test_idx = ct.split(runs)
     net = cl.Closure(ct.M, c_in=4, width=32, layers=4, max_batch=32, device=DEV)
     net.set_weights(dev(inputs.closure_init(601, 4, 32, 4)))
@@ -314,6 +343,4 @@ def test_closure_beats_persistence_on_dpd_fields(cl):
     mse_net, mse_per, res = ct.evaluate(net, runs, test_idx, DEV)
     print(f"held-out one-step MSE: network {mse_net:.4e}, persistence {mse_per:.4e}")
     assert mse_net < 0.98 * mse_per
-    for r in runs:
-        r["sim"].close()
     net.close()
