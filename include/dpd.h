@@ -49,7 +49,7 @@ extern "C" {
 #define DPD_EHIP       -3  /* a HIP runtime call failed                           */
 #define DPD_ENONFINITE -4  /* a non-finite position, velocity or force appeared   */
 #define DPD_ESTATE     -5  /* call needs a state set by dpd_set_state first       */
-#define DPD_EBOND      -6  /* a bond grew longer than one cell width              */
+#define DPD_EBOND      -6  /* a bond grew beyond the cell stencil (1.25 bond_l <= cell width) */
 #define DPD_ERANGE     -7  /* a velocity exceeded the binned-field range          */
 
 /* Model and engine parameters; physics constants in the units of the caller
@@ -59,9 +59,10 @@ typedef struct dpd_params {
     int64_t  n_agents;   /* agents, >= 1; particles N = 2 n_agents <= 2^30           */
     double   L;          /* box side, exactly representable in FP32, >= 3 r_c         */
     double   r_c;        /* pair cutoff (Eq. 2.2), > 0; cells per side
-                            n_c = floor(L / max(r_c + skin, 1.25 bond_l)), >= 3
-                            (a bond longer than r_c keeps its partner within
-                            the 3 x 3 cell stencil)                                   */
+                            n_c = floor(L / (r_c + skin)), >= 3.  A bond that can
+                            reach beyond the 3 x 3 cell stencil (1.25 bond_l >
+                            r_c + skin) has its partner read by particle id
+                            (not with a skin)                                         */
     double   A;          /* conservative amplitude (Eq. 2.3), >= 0                    */
     double   gamma;      /* pair friction (Eq. 2.3), >= 0                             */
     double   kT;         /* thermal energy (Eq. 2.3), >= 0; sigma = sqrt(2 gamma kT)  */
@@ -169,6 +170,36 @@ int dpd_step(dpd_handle* h, int32_t n_steps, int32_t reduce_every, double* pk_ou
 int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode,
                      float* u_out, int32_t* n_out);
 
+/* dpd_bin_velocity with a window width of its own for every replica of a
+ * batch: eps[r] (host array of the batch's replica count) for replica r, with
+ * the meaning of eps above.  Each replica's field is binned once.
+ * Errors: as dpd_bin_velocity. */
+int dpd_bin_velocity_reps(dpd_handle* h, int32_t M, const double* eps, int32_t mode,
+                          float* u_out, int32_t* n_out);
+
+/* Velocity correlation function of the agents (Sec. 5.3, Eqs. 5.5-5.6), as
+ * pair sums by separation.  Agent k's centre of mass is the minimum-image
+ * midpoint of its head 2k and tail 2k+1 (wrapped into [0, L)) and its velocity
+ * V_k = (v_2k + v_2k+1) / 2, in FP64 from the FP32 state.  For every bin
+ * b < n_bins of width dr, over the pairs k < l whose minimum-image separation
+ * r has floor(r / dr) = b:
+ *   sums[b]   = sum of round(2^20 V_k . V_l) (exact integer sums, any order),
+ *   counts[b] = number of pairs.
+ * The caller forms g(r_b) = (sums[b] 2^-20 / counts[b] - |<V>|^2) /
+ * (<|V|^2> - |<V>|^2) with the means over agents (Eq. 5.6), taken from the
+ * velocities left in work.
+ *   x, v: device N x 2 FP32 in id order, N = 2 n_agents (1 <= n_agents <= 2^29);
+ *   work: device FP64 scratch of 4 n_agents + 1 values, caller's; on return
+ *         work[0 .. 2n) holds the centres (x, y per agent) and
+ *         work[2n .. 4n) the velocities V;
+ *   sums, counts: device int64[n_bins], 1 <= n_bins <= 1024, caller's;
+ *   stream: a hipStream_t (NULL = the null stream).
+ * O(n_agents^2) pairs on the GPU.  Synchronises the stream.
+ * Errors: DPD_EINVAL; DPD_ERANGE if some |V_k . V_l| reached 4096 (the sums
+ * would lose exactness); DPD_EHIP. */
+int dpd_agent_vcf(const float* x, const float* v, int64_t n_agents, double L, double dr,
+                  int32_t n_bins, double* work, long long* sums, long long* counts, void* stream);
+
 /* Wait for the stream and return the first device-side failure since the last
  * synchronising call (clearing it), or DPD_OK. */
 int dpd_sync(dpd_handle* h);
@@ -252,8 +283,8 @@ int dpd_forces_noalloc(const dpd_params* p, const float* x, const float* v, int6
  * since).  Synchronises the stream. */
 int dpd_get_cells(dpd_handle* h, int32_t* cell_start_out, int32_t* ids_out);
 
-/* Cells per side of the cell list for p (n_c = floor(L / max(r_c + skin,
- * 1.25 bond_l)), the skin being 0 unless set), or a negative error code. */
+/* Cells per side of the cell list for p (n_c = floor(L / (r_c + skin)), the
+ * skin being 0 unless set), or a negative error code. */
 int64_t dpd_cells_per_side(const dpd_params* p);
 
 /* The generator output for n pairs (i[k], j[k]) at `step` with p's seed,

@@ -57,6 +57,8 @@ struct DevParams {
     int pbase, cbase, tbase;
     double mass_d;
     float w_half;     // half the exponent of the dissipative weight (1: Eq. 2.3)
+    int far_bond;     // a bond may reach beyond the 3 x 3 cell stencil: the partner
+                      // is then read by id (PairArgs::pos_of_id)
 };
 
 // ---- Philox (Salmon, Moraes, Dror & Shaw, SC'11) ---------------------------

@@ -43,6 +43,7 @@ struct Layout {
     size_t off_count2, off_xref, off_rec, off_flags;  // Verlet skin
     size_t off_reps, off_tile_rep, off_stepb;         // batch tables, graph step
     size_t off_Tx, off_Tv, off_TF, off_Tid;           // state saved by the tuner
+    size_t off_posid;                                 // input index by id (far bonds)
     size_t total;
 };
 
@@ -60,6 +61,7 @@ struct Derived {
     int n_scan_blocks = 0;      // chunks of the cell-count scan
     int bin_M_max = 0;
     bool skin = false;
+    bool far_bond = false;  // some replica's bond can reach beyond the cell stencil
     Layout lay;
 };
 
@@ -149,15 +151,20 @@ int derive_one(const dpd_params* p, DevParams& P, std::string* err) {
         *err = "skin must be finite, >= 0 and below L / 2";
         return DPD_EINVAL;
     }
-    // smallest cell width: the cutoff (plus the skin), and room for a bond
-    // longer than the cutoff, whose partner must lie in the 3 x 3 stencil
-    const double width = std::max(p->r_c + (double)p->skin, 1.25 * p->bond_l);
+    // smallest cell width: the cutoff plus the skin.  A bond that can reach
+    // beyond the 3 x 3 stencil (1.25 bond_l, a quarter of stretch to spare,
+    // wider than a cell) has its partner read by id instead.
+    const double width = p->r_c + (double)p->skin;
     const double ncd = std::floor(p->L / width);
     if (!(ncd >= 3.0)) {
-        *err = "L must be at least 3 max(r_c + skin, 1.25 bond_l) (n_c >= 3)";
+        *err = "L must be at least 3 (r_c + skin) (n_c >= 3)";
         return DPD_EINVAL;
     }
     if (ncd > 46340.0) { *err = "too many cells (n_c^2 must fit in int32)"; return DPD_EINVAL; }
+    if (p->skin > 0.0f && 1.25 * p->bond_l > width) {
+        *err = "a Verlet skin needs 1.25 bond_l <= r_c + skin (the bond within the cell stencil)";
+        return DPD_EINVAL;
+    }
     const double vals[] = {p->A, p->gamma, p->kT, p->kappa, p->bond_l, p->gamma_s};
     for (double v : vals)
         if (!finite(v) || v < 0.0) {
@@ -223,6 +230,7 @@ int derive_one(const dpd_params* p, DevParams& P, std::string* err) {
     P.seed_hi = (uint32_t)(p->seed >> 32);
     P.mass_d = p->mass;
     P.w_half = p->w_exp > 0.0f ? 0.5f * p->w_exp : 1.0f;
+    P.far_bond = (1.25 * p->bond_l > width) ? 1 : 0;
     return DPD_OK;
 }
 
@@ -263,6 +271,8 @@ int derive(const dpd_params* p, int n_rep, Derived* d, std::string* err) {
         }
     }
     d->skin = d->reps[0].P.skin_on != 0;
+    d->far_bond = false;
+    for (const Rep& r : d->reps) d->far_bond |= r.P.far_bond != 0;
     assign_offsets(d);
     if (d->N > (int64_t(1) << 30) || d->cells > 2147483647LL) {
         *err = "the batch holds more than 2^30 particles or 2^31 cells";
@@ -321,6 +331,7 @@ int derive(const dpd_params* p, int n_rep, Derived* d, std::string* err) {
         L.off_TF = take(N * 8);
         L.off_Tid = take(N * 4);
     }
+    L.off_posid = d->far_bond ? take(N * 4) : 0;
     L.total = o;
     return DPD_OK;
 }
@@ -358,6 +369,7 @@ struct dpd_handle {
     DevParams* reps_dev;  // parameters of every replica (batch)
     int* tile_rep;        // replica of every tile (batch)
     unsigned* stepb;      // step before a replayed chunk
+    int* posid;           // input index by id (far bonds), or null
     int tile_order;       // 0: bands of tiles per XCD; 1: launch order
     int64_t step;
     bool have_state;
@@ -434,7 +446,7 @@ int upload_tables(dpd_handle* h) {
 // id here (only for the state loaded with a given force, which no pair kernel
 // passes through before it is stored).
 int bin_from_counts(dpd_handle* h, int* count, const int* rebuild, int* moved_clear,
-                    const int* id_of_input) {
+                    const int* id_of_input, const int* ids_in) {
     const int G = h->d.n_scan_blocks;
     const int C = (int)h->d.cells, N = (int)h->d.N;
     hipLaunchKernelGGL(k_scan_reduce, dim3(G), dim3(kBlock), 0, h->stream, (const int*)count, C,
@@ -447,6 +459,10 @@ int bin_from_counts(dpd_handle* h, int* count, const int* rebuild, int* moved_cl
     if (id_of_input)
         hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, C,
                            (const int*)h->cs, h->src, id_of_input);
+    if (h->posid)  // bonds beyond the stencil: where every id sits in the input
+        hipLaunchKernelGGL(k_pos_of_id, dim3(std::min(grid_for(N), 4096)), dim3(kBlock), 0, h->stream,
+                           N, ids_in, h->R > 1 ? (const DevParams*)h->reps_dev : nullptr, h->R,
+                           h->posid, rebuild);
     LAUNCHCHK(h);
     return DPD_OK;
 }
@@ -500,6 +516,7 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
     b.tile_rep = h->tile_rep;
     b.nt_total = (int)h->d.tiles;
     b.tile_order = h->tile_order;
+    b.pos_of_id = h->posid;
     const int red = reduce ? 1 : 0;
     const bool batch = h->R > 1;
     // the Verlet-skin variant of the kernel only where a skin is set (a force
@@ -677,7 +694,7 @@ int run_steps(dpd_handle* h, int64_t n, int reduce_every, double* pk_out, int64_
         const int64_t s = h->step + k;
         const int* rebuild = h->d.skin ? h->flags + ((s - 1) & 1) : nullptr;
         int* moved = h->d.skin ? h->flags + (s & 1) : nullptr;
-        int rc = bin_from_counts(h, counter_of(h, s - 1), rebuild, moved, nullptr);
+        int rc = bin_from_counts(h, counter_of(h, s - 1), rebuild, moved, nullptr, inid);
         if (rc) return rc;
         const bool last = (k == n);
         const bool red = pk_out && reduce_every > 0 && ((k0 + k) % reduce_every == 0);
@@ -719,7 +736,7 @@ int capture_chunk(dpd_handle* h, int K, bool reduce_last, hipGraphExec_t* out) {
     float2 *inx = h->Ax, *inu = h->Au, *outx = h->Bx, *outu = h->Bu;
     int *inid = h->Aid, *outid = h->Bid;
     for (int k = 1; k <= K && rc == DPD_OK; ++k) {
-        rc = bin_from_counts(h, h->count, nullptr, nullptr, nullptr);
+        rc = bin_from_counts(h, h->count, nullptr, nullptr, nullptr, inid);
         if (rc) break;
         const bool last = (k == K);
         PairArgs a = step_args(h, k, last, inx, inu, inid, outx, outu, outid);
@@ -893,6 +910,7 @@ int dpd_create_batch(const dpd_params* p, int32_t n_rep, void* workspace, size_t
         h->Tv = d.skin ? nullptr : (float2*)(w + L.off_Tv);
         h->TF = d.skin ? nullptr : (float2*)(w + L.off_TF);
         h->Tid = d.skin ? nullptr : (int*)(w + L.off_Tid);
+        h->posid = d.far_bond ? (int*)(w + L.off_posid) : nullptr;
         h->tile_order = 0;
         h->step = 0;
         h->have_state = false;
@@ -971,7 +989,7 @@ int dpd_set_state(dpd_handle* h, const float* x, const float* v, int64_t step, c
                                h->Aid + pb, h->key + pb, h->rank + pb, h->count, h->status);
         }
         LAUNCHCHK(h);
-        int rc = bin_from_counts(h, h->count, nullptr, nullptr, F ? h->Aid : nullptr);
+        int rc = bin_from_counts(h, h->count, nullptr, nullptr, F ? h->Aid : nullptr, h->Aid);
         if (rc) return rc;
         if (F) {
             for (const Rep& r : h->d.reps) {
@@ -1082,7 +1100,7 @@ int dpd_forces(dpd_handle* h, float* F_out) {
                                (const float2*)h->Sx + pb, h->key + pb, h->rank + pb, h->count);
         }
         LAUNCHCHK(h);
-        int rc = bin_from_counts(h, h->count, nullptr, nullptr, nullptr);
+        int rc = bin_from_counts(h, h->count, nullptr, nullptr, nullptr, h->Sid);
         if (rc) return rc;
         PairArgs a = {};
         a.cs = h->cs;
@@ -1141,17 +1159,21 @@ int dpd_get_cells(dpd_handle* h, int32_t* cell_start_out, int32_t* ids_out) {
     return read_status(h);
 }
 
-int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode, float* u_out,
-                     int32_t* n_out) {
+// dpd_bin_velocity with window width eps[r] for replica r (host array).
+int bin_velocity_impl(dpd_handle* h, int32_t M, const double* eps_rep, int32_t mode, float* u_out,
+                      int32_t* n_out) {
     if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
     if (!h->have_state) return fail(h, DPD_ESTATE, "dpd_bin_velocity before dpd_set_state");
     if (M < 1 || M > h->d.bin_M_max) return fail(h, DPD_EINVAL, fmt("M = %d outside [1, %d]", M, h->d.bin_M_max));
     if (mode != 0 && mode != 1) return fail(h, DPD_EINVAL, "mode must be 0 or 1");
     if (!u_out || !n_out) return fail(h, DPD_EINVAL, "u_out and n_out must not be NULL");
-    if (!std::isfinite(eps)) return fail(h, DPD_EINVAL, "eps must be finite");
+    if (!eps_rep) return fail(h, DPD_EINVAL, "eps must not be NULL");
+    for (int ri = 0; ri < h->R; ++ri)
+        if (!std::isfinite(eps_rep[ri])) return fail(h, DPD_EINVAL, "eps must be finite");
     try {
-        const bool rows = mode == 0 && eps <= 0.0 && M <= 2048;
-        if (!rows) {
+        bool all_rows = true;
+        for (int ri = 0; ri < h->R; ++ri) all_rows &= mode == 0 && eps_rep[ri] <= 0.0 && M <= 2048;
+        if (!all_rows) {
             // id-order copies of x and v go to the scratch buffers (which may hold
             // the prepared next step)
             int rc0 = unprepare(h);
@@ -1162,6 +1184,8 @@ int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode, float* 
             const Rep& rp = h->d.reps[ri];
             const DevParams& P = rp.P;
             const size_t pb = (size_t)P.pbase;
+            const double eps = eps_rep[ri];
+            const bool rows = mode == 0 && eps <= 0.0 && M <= 2048;
             float2* u = (float2*)u_out + (size_t)ri * nbin;
             int* n = (int*)n_out + (size_t)ri * nbin;
             // 64-bit fixed point: |v| <= 2^16 and <= 2^ceil(log2 n) contributors per bin
@@ -1221,6 +1245,60 @@ int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode, float* 
         return DPD_OK;
     } catch (...) {
         return fail(h, DPD_EINVAL, "internal error");
+    }
+}
+
+int dpd_bin_velocity(dpd_handle* h, int32_t M, double eps, int32_t mode, float* u_out,
+                     int32_t* n_out) {
+    if (!h) return fail(nullptr, DPD_EINVAL, "handle is NULL");
+    try {
+        std::vector<double> e(h->R, eps);
+        return bin_velocity_impl(h, M, e.data(), mode, u_out, n_out);
+    } catch (...) {
+        return fail(h, DPD_EINVAL, "internal error");
+    }
+}
+
+int dpd_bin_velocity_reps(dpd_handle* h, int32_t M, const double* eps, int32_t mode, float* u_out,
+                          int32_t* n_out) {
+    return bin_velocity_impl(h, M, eps, mode, u_out, n_out);
+}
+
+int dpd_agent_vcf(const float* x, const float* v, int64_t n_agents, double L, double dr,
+                  int32_t n_bins, double* work, long long* sums, long long* counts, void* stream) {
+    try {
+        if (!x || !v || !work || !sums || !counts)
+            return fail(nullptr, DPD_EINVAL, "x, v, work, sums and counts must not be NULL");
+        if (n_agents < 1 || n_agents > (int64_t(1) << 29))
+            return fail(nullptr, DPD_EINVAL, fmt("n_agents = %lld outside [1, 2^29]", (long long)n_agents));
+        if (!(L > 0.0) || !std::isfinite(L) || !(dr > 0.0) || !std::isfinite(dr))
+            return fail(nullptr, DPD_EINVAL, "L and dr must be positive and finite");
+        if (n_bins < 1 || n_bins > kVcfMaxBins)
+            return fail(nullptr, DPD_EINVAL, fmt("n_bins = %d outside [1, %d]", n_bins, kVcfMaxBins));
+        hipStream_t s = (hipStream_t)stream;
+        const int n = (int)n_agents;
+        unsigned* status = reinterpret_cast<unsigned*>(work + 4 * (size_t)n);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2LL * n_bins)), dim3(kBlock), 0, s, (int*)sums, 0,
+                           2LL * n_bins);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2LL * n_bins)), dim3(kBlock), 0, s, (int*)counts, 0,
+                           2LL * n_bins);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s, (int*)status, 0, 2LL);
+        hipLaunchKernelGGL(k_agent_com, dim3(grid_for(n)), dim3(kBlock), 0, s, n, L, (const float2*)x,
+                           (const float2*)v, work);
+        const int nt = (n + kVcfTile - 1) / kVcfTile;
+        hipLaunchKernelGGL(k_vcf_pairs, dim3(nt, nt), dim3(kVcfTile), 0, s, n, L, dr, (int)n_bins,
+                           (const double*)work, sums, counts, status);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return fail(nullptr, DPD_EHIP, fmt("kernel launch: %s", hipGetErrorString(err)));
+        unsigned st = 0;
+        err = hipStreamSynchronize(s);
+        if (err == hipSuccess) err = hipMemcpy(&st, status, sizeof st, hipMemcpyDeviceToHost);
+        if (err != hipSuccess) return fail(nullptr, DPD_EHIP, fmt("hip: %s", hipGetErrorString(err)));
+        if (st & kStatusRange)
+            return fail(nullptr, DPD_ERANGE, "an agent velocity product |V_k . V_l| reached 4096");
+        return DPD_OK;
+    } catch (...) {
+        return fail(nullptr, DPD_EINVAL, "internal error");
     }
 }
 

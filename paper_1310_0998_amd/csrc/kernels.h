@@ -86,6 +86,9 @@ struct PairArgs {
     const int* tile_rep;
     int nt_total;
     int tile_order;     // 0: bands of consecutive tiles per XCD; 1: launch order
+    // bonds longer than the cell stencil reaches (far_bond): index in the input
+    // buffers of the particle with id i of the replica at pbase, at pos_of_id[pbase + i]
+    const int* pos_of_id;
 };
 
 // ---- small helpers ----------------------------------------------------------
@@ -821,6 +824,14 @@ __device__ __forceinline__ bool pair_tile(DevParams P, PairArgs a, int reduce, i
         if (jp != 0xFF) {
             const float4 rp = s_rec[jp];
             add_agent_force(P, xi, make_float2(rp.x, rp.y), ui, idi, fx, fy);
+        } else if (P.far_bond) {
+            // the partner lies beyond the staged cells: read it by id
+            int pp = a.pos_of_id[P.pbase + (idi ^ 1)];
+            if ((unsigned)(pp - P.pbase) >= (unsigned)P.N) {
+                atomicOr(a.status, kStatusBinning);
+                pp = P.pbase;
+            }
+            add_agent_force(P, xi, a.xin[pp], ui, idi, fx, fy);
         } else {
             atomicOr(a.status, kStatusBond);
             fx -= P.gamma_s * ui.x;
@@ -979,6 +990,15 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
             }
             if (bad) atomicOr(a.status, kStatusNonFinite);
             float fx = from_fixed(qx), fy = from_fixed(qy);
+            if (!found && P.far_bond) {  // the partner lies beyond the stencil: by id
+                int pp = a.pos_of_id[P.pbase + pid];
+                if ((unsigned)(pp - P.pbase) >= (unsigned)P.N) {
+                    atomicOr(a.status, kStatusBinning);
+                    pp = P.pbase;
+                }
+                xpart = a.xin[pp];
+                found = true;
+            }
             if (found) {
                 add_agent_force(P, xi, xpart, ui, idi, fx, fy);
             } else {
@@ -1160,6 +1180,28 @@ __global__ void k_scatter(int N, const int* __restrict__ key, const int* __restr
     if (rebuild && *rebuild == 0) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
         src[cs[key[i]] + rank[i]] = i;
+}
+
+// Bonds longer than the cell stencil reaches: pos[pbase + id] = index in the
+// input buffers of every particle, its replica found by bisection of the
+// replicas' first slots (reps null: a single system).  Runs with the binning
+// that consumes those buffers (rebuild as for k_scatter).
+__global__ void k_pos_of_id(int N, const int* __restrict__ id, const DevParams* __restrict__ reps,
+                            int R, int* pos, const int* rebuild) {
+    if (rebuild && *rebuild == 0) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        int base = 0;
+        if (reps) {
+            int lo = 0, hi = R - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (reps[mid].pbase <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            base = reps[lo].pbase;
+        }
+        pos[base + id[i]] = i;
+    }
 }
 
 // Order each cell's slots by particle id.  Cells hold about one particle:
@@ -1527,6 +1569,103 @@ __global__ void k_bin_finalize(int nbin, const long long* __restrict__ acc, doub
         u[k] = make_float2((float)((double)acc[3 * k + 0] * inv), (float)((double)acc[3 * k + 1] * inv));
     } else {
         u[k] = make_float2(0.f, 0.f);
+    }
+}
+
+// ---- velocity correlation of the agents (Sec. 5.3) ----------------------------
+
+// Agent centres of mass and velocities in FP64 from the FP32 state in id
+// order: d = x_head - x_tail under the minimum image, centre = (x_tail + d/2)
+// wrapped into [0, L), V = (v_head + v_tail) / 2.  work holds the centres
+// [n][2], then the velocities [n][2].
+__global__ void k_agent_com(int n, double L, const float2* __restrict__ x, const float2* __restrict__ v,
+                            double* work) {
+#pragma clang fp contract(off)
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float2 xh = x[2 * k], xt = x[2 * k + 1], vh = v[2 * k], vt = v[2 * k + 1];
+    double c[2];
+    const double h[2] = {(double)xh.x, (double)xh.y}, t[2] = {(double)xt.x, (double)xt.y};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        double d = h[a] - t[a];
+        d = d - L * rint(d / L);
+        double y = t[a] + 0.5 * d;
+        y = y - L * floor(y / L);
+        c[a] = y;
+    }
+    work[2 * k] = c[0];
+    work[2 * k + 1] = c[1];
+    work[2 * n + 2 * k] = 0.5 * ((double)vh.x + (double)vt.x);
+    work[2 * n + 2 * k + 1] = 0.5 * ((double)vh.y + (double)vt.y);
+}
+
+// Pair sums of V_k . V_l over the pairs k < l binned by their minimum-image
+// separation, floor(r / dr) < nb, and the pair counts.  A block of 256 threads
+// takes the 256 x 256 pairs of one tile of the upper triangle (row tile
+// blockIdx.y, column tile blockIdx.x >= blockIdx.y; lower tiles exit), the
+// column tile staged in LDS.  The separation and the bin follow the plain
+// FP64 sequence d - L rint(d / L), sqrt(dx dx + dy dy), floor(r / dr); every
+// dot product enters in 64-bit fixed point (scale 2^20, exact integer sums, so
+// the result does not depend on the order), the block's bins then go to the
+// global sums with integer atomics.
+constexpr int kVcfTile = 256;
+constexpr int kVcfMaxBins = 1024;
+constexpr double kVcfScale = 1048576.0;  // 2^20
+
+__global__ __launch_bounds__(kVcfTile) void k_vcf_pairs(int n, double L, double dr, int nb,
+                                                        const double* __restrict__ work,
+                                                        long long* sums, long long* counts,
+                                                        unsigned* status) {
+#pragma clang fp contract(off)
+    if (blockIdx.x < blockIdx.y) return;
+    __shared__ double s_pos[kVcfTile][2];
+    __shared__ double s_vel[kVcfTile][2];
+    __shared__ long long s_sum[kVcfMaxBins];
+    __shared__ int s_cnt[kVcfMaxBins];
+    const int t = threadIdx.x;
+    for (int b = t; b < nb; b += kVcfTile) {
+        s_sum[b] = 0;
+        s_cnt[b] = 0;
+    }
+    const int l0 = blockIdx.x * kVcfTile, k = blockIdx.y * kVcfTile + t;
+    const double* pos = work;
+    const double* vel = work + 2 * (size_t)n;
+    if (l0 + t < n) {
+        s_pos[t][0] = pos[2 * (l0 + t)];
+        s_pos[t][1] = pos[2 * (l0 + t) + 1];
+        s_vel[t][0] = vel[2 * (l0 + t)];
+        s_vel[t][1] = vel[2 * (l0 + t) + 1];
+    }
+    __syncthreads();
+    bool big = false;
+    if (k < n) {
+        const double px = pos[2 * k], py = pos[2 * k + 1];
+        const double vx = vel[2 * k], vy = vel[2 * k + 1];
+        const int lend = min(kVcfTile, n - l0);
+        for (int j = 0; j < lend; ++j) {
+            if (l0 + j <= k) continue;
+            double dx = s_pos[j][0] - px;
+            double dy = s_pos[j][1] - py;
+            dx = dx - L * rint(dx / L);
+            dy = dy - L * rint(dy / L);
+            const double r = sqrt(dx * dx + dy * dy);
+            const double bf = floor(r / dr);
+            if (!(bf < (double)nb)) continue;
+            const int b = (int)bf;
+            const double dot = s_vel[j][0] * vx + s_vel[j][1] * vy;
+            big |= !(fabs(dot) < 4096.0);
+            atomicAdd((unsigned long long*)&s_sum[b], (unsigned long long)llrint(dot * kVcfScale));
+            atomicAdd(&s_cnt[b], 1);
+        }
+    }
+    if (big) atomicOr(status, kStatusRange);
+    __syncthreads();
+    for (int b = t; b < nb; b += kVcfTile) {
+        if (s_cnt[b]) {
+            atomicAdd((unsigned long long*)&sums[b], (unsigned long long)s_sum[b]);
+            atomicAdd((unsigned long long*)&counts[b], (unsigned long long)s_cnt[b]);
+        }
     }
 }
 

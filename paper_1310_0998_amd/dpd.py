@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
             "dpd_cell_list_rebuilds": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
             "dpd_copy_kernel": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
             "dpd_forces_noalloc": (ctypes.c_int, [P, vp, vp, i64, vp, vp]),
+            "dpd_bin_velocity_reps": (ctypes.c_int, [vp, i32, ctypes.POINTER(f64), i32, vp, vp]),
+            "dpd_agent_vcf": (ctypes.c_int, [vp, vp, i64, f64, f64, i32, vp, vp, vp, vp]),
             "dpd_batch_workspace_bytes": (ctypes.c_int, [P, i32, ctypes.POINTER(ctypes.c_size_t)]),
             "dpd_create_batch": (ctypes.c_int, [P, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
             "dpd_set_graph_chunk": (ctypes.c_int, [vp, i32]),
@@ -256,6 +258,18 @@ class Sim:
         else:
             u, n = out
         self._c(lib().dpd_bin_velocity(self._h, int(M), float(eps), int(mode), _ptr(u), _ptr(n)))
+        return u, n
+
+    def bin_velocity_reps(self, M: int, eps, mode: int = 0, out=None):
+        """bin_velocity with window width eps[r] for replica r of a batch."""
+        if out is None:
+            lead = (self.R,) if self.batch else ()
+            u = torch.empty(lead + (M, M, 2), dtype=torch.float32, device=self.device)
+            n = torch.empty(lead + (M, M), dtype=torch.int32, device=self.device)
+        else:
+            u, n = out
+        e = (ctypes.c_double * self.R)(*[float(x) for x in eps])
+        self._c(lib().dpd_bin_velocity_reps(self._h, int(M), e, int(mode), _ptr(u), _ptr(n)))
         return u, n
 
     def cells(self):

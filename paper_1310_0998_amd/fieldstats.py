@@ -149,3 +149,36 @@ def band_autocorrelation(fields: torch.Tensor, lags) -> np.ndarray:
             den += np.bincount(bi[bi >= 0], (Pp + Pm)[bi >= 0], nb)
         out[:, j] = num / np.maximum(den, 1e-300)
     return out
+
+
+VCF_SCALE = 2.0 ** 20  # fixed-point scale of the pair sums of dpd_agent_vcf
+
+
+def agent_vcf(x: torch.Tensor, v: torch.Tensor, L: float, dr: float):
+    """Velocity correlation function of the agents (Sec. 5.3, Eqs. 5.5-5.6)
+    from the state x, v (CUDA FP32 (N, 2), id order): pair sums by separation
+    on the GPU (dpd_agent_vcf) in bins of width dr out to L/2, normalised with
+    the mean and mean square of the agent velocities.  Returns
+    (r_centres, g, counts) with g(0) := 1 and count 0 prepended at r = 0."""
+    n = int(x.shape[0]) // 2
+    nb = int(np.floor(0.5 * L / dr))
+    dev = x.device
+    work = torch.empty(4 * n + 1, dtype=torch.float64, device=dev)
+    sums = torch.empty(nb, dtype=torch.int64, device=dev)
+    counts = torch.empty(nb, dtype=torch.int64, device=dev)
+    vp = ctypes.c_void_p
+    rc = dpd.lib().dpd_agent_vcf(vp(x.data_ptr()), vp(v.data_ptr()), n, float(L), float(dr), nb,
+                                 vp(work.data_ptr()), vp(sums.data_ptr()), vp(counts.data_ptr()),
+                                 vp(torch.cuda.current_stream(dev).cuda_stream))
+    if rc != 0:
+        raise dpd.DPDError(rc, dpd.lib().dpd_last_error(None).decode())
+    V = work[2 * n:4 * n].view(n, 2).cpu().numpy()
+    mean = V.mean(axis=0)
+    mean2 = float(mean @ mean)
+    var = float((V * V).sum(axis=1).mean()) - mean2
+    S = sums.cpu().numpy().astype(np.float64) / VCF_SCALE
+    c = counts.cpu().numpy()
+    with np.errstate(invalid="ignore", divide="ignore"):
+        g = (S / c - mean2) / var
+    rc_ = (np.arange(nb) + 0.5) * dr
+    return np.concatenate([[0.0], rc_]), np.concatenate([[1.0], g]), np.concatenate([[0], c])

@@ -61,8 +61,11 @@ def test_workspace_and_cells(dpd):
     assert dpd.cells_per_side(big) == 2000
     assert dpd.workspace_bytes(big) < 2 * 1024 ** 3
     assert dpd.cells_per_side(dict(cfg, L=7.25, r_c=1.1)) == 6
-    # a bond longer than the cutoff widens the cells to 1.25 bond_l
-    assert dpd.cells_per_side(dict(cfg, L=100.0, r_c=0.5, bond_l=1.0)) == 80
+    # a bond longer than the cutoff keeps cells of width r_c (its partner is
+    # read by id), but refuses a Verlet skin too narrow to hold it
+    assert dpd.cells_per_side(dict(cfg, L=100.0, r_c=0.5, bond_l=1.0)) == 200
+    with pytest.raises(dpd.DPDError):
+        dpd.workspace_bytes(dict(cfg, L=100.0, r_c=0.5, bond_l=1.0, skin=0.2))
 
 
 @pytest.mark.parametrize("bad", [

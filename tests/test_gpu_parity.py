@@ -153,7 +153,7 @@ FORCE_CASES = [
     ("w_exp-0.5", dict(C1, w_exp=0.5, seed=19), "random", True),
     ("w_exp-1", dict(C1, w_exp=1.0, seed=20), "edge", True),
     ("w_exp-3", dict(C1, w_exp=3.0, seed=21), "random", True),
-    # the paper's own geometry: bond l = 1 longer than r_c = 0.5 (cells 1.25 l wide)
+    # the paper's own geometry: bond l = 1 longer than r_c = 0.5 (partner read by id)
     ("l>rc", dict(C1, r_c=0.5, bond_l=1.0, A=1.5, kT=0.05, seed=22), "random", True),
 ]
 
@@ -500,6 +500,37 @@ def test_large_capacity_retry_path(dpd):
     # the FP64 reductions run over other tiles, so only to rounding
     assert pa == pytest.approx(pb, rel=1e-12, abs=1e-12)
     a.close()
+    b.close()
+
+
+def test_far_bond_partner_by_id(dpd):
+    # the paper's geometry: the bond (l = 1) reaches beyond the 3 x 3 stencil
+    # of r_c-wide cells (r_c = 0.5), so the partner is read by id.  Forces match
+    # the oracle for a random state (fast kernel) and for a dense cluster (the
+    # overflow kernel's paths), and a batch of both steps bitwise like two
+    # single handles
+    base = dict(C1, r_c=0.5, bond_l=1.0, A=1.5, kT=0.05, dt=0.003, L=40.0)
+    cases = [(dict(base, n_agents=800, seed=31), "random"), (dict(base, n_agents=1200, seed=32), "clustered")]
+    singles = []
+    for cfg, kind in cases:
+        x, v = inputs.initial_state(cfg, kind=kind, thermal=True)
+        sim = make_sim(dpd, cfg, x, v, step=4)
+        F = host(sim.forces())
+        per, glob = force_errors(cfg, x, v, 4, F)
+        print(f"far bond, {kind}: max per-particle error {per.max():.2e}, global {glob:.2e}")
+        assert per.max() <= 1e-5 and glob <= 1e-5, (kind, per.max(), glob)
+        sim.step(40)
+        singles.append([host(t) for t in sim.get_state()[:3]])
+        sim.close()
+    states = [inputs.initial_state(c, kind=k, thermal=True) for c, k in cases]
+    b = dpd.Sim([c for c, _ in cases], device=DEV)
+    b.set_state(dev(np.concatenate([s_[0] for s_ in states])), dev(np.concatenate([s_[1] for s_ in states])), 4)
+    b.step(40)
+    got = [host(t) for t in b.get_state()[:3]]
+    n0 = 2 * cases[0][0]["n_agents"]
+    for q, sl in enumerate((slice(0, n0), slice(n0, None))):
+        for u, w in zip(got, singles[q]):
+            assert (u[sl] == w).all()
     b.close()
 
 

@@ -122,3 +122,28 @@ def test_energy_spectrum_and_correlation_length_match_oracle():
         if dev > tol:
             bad.append(name)
     assert not bad, bad
+
+
+@pytest.mark.parametrize("n_agents,L,kind", [(800, 40.0, "random"), (420, 29.25, "edge"),
+                                             (3000, 60.0, "random")])
+def test_agent_vcf_matches_oracle_pair_loop(n_agents, L, kind):
+    # the GPU pair sums of dpd_agent_vcf against the oracle's pair loop over
+    # the same state: every bin's pair count exactly, g within what the
+    # fixed-point pair sums allow (half a step of 2^-20 per pair, over the
+    # velocity variance)
+    import torch
+    from oracle import analysis
+    from paper_1310_0998_amd import dpd, fieldstats, inputs
+    cfg = dict(inputs.physics(inputs.WORKLOADS["dimers_1600"]), n_agents=n_agents, L=L, seed=n_agents)
+    x, v = inputs.initial_state(cfg, kind=kind, thermal=True)
+    dr = 0.25
+    r, g, c = fieldstats.agent_vcf(torch.from_numpy(x).cuda(), torch.from_numpy(v).cuda(), L, dr)
+    com, V = analysis.agent_com(x, v, L)
+    ro, go, co = analysis.vcf_bruteforce(com, V, L, dr)
+    assert np.array_equal(r, ro)
+    assert np.array_equal(c, co)
+    var = float((V * V).sum(axis=1).mean() - V.mean(axis=0) @ V.mean(axis=0))
+    ok = co > 0
+    assert np.abs(g[ok] - go[ok]).max() <= 2.0 ** -21 / var + 1e-12
+    assert fieldstats.integral_length(r, g, L, to_first_zero=False) == pytest.approx(
+        analysis.integral_length(ro, go, L), rel=1e-6)
