@@ -287,7 +287,7 @@ static int partners_of(const oracle_params* p, const double* x, const cells_t* c
             }
         }
     }
-    qsort(out->a, (size_t)out->n, sizeof(int64_t), cmp_i64);
+    if (out->n > 1) qsort(out->a, (size_t)out->n, sizeof(int64_t), cmp_i64);
     return 0;
 }
 
