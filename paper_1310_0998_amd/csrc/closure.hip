@@ -8,8 +8,11 @@
 //
 // Forward and input-gradient convolutions are implicit GEMMs on the matrix
 // cores: one 64-lane wavefront computes 16 pixels x 16 output channels per
-// v_mfma_f32_16x16x16_bf16 accumulator, running over K = 9 c_in in chunks of
-// 16 (4 per lane: 4 consecutive channels of one tap, one 8-byte load).
+// accumulator, running over K = 9 c_in.  The LDS-staged forward kernel and
+// the input-gradient kernel take K in chunks of 32 (v_mfma_f32_16x16x32_bf16,
+// 8 values per lane); the general forward kernels for other shapes take
+// chunks of 16 (v_mfma_f32_16x16x16_bf16, 4 consecutive channels of one tap
+// per lane, one 8-byte load).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +39,7 @@ constexpr int kWgOutMax = 9 * kMaxC * kMaxC + kMaxC;  // weights + biases of one
 constexpr int kWgPerThread = (kWgOutMax + kThreads - 1) / kThreads;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest even (NaN stays NaN).
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_c(Conv cv, int M, int npi
     }
 }
 
-// The convolution for CIN in {16, 32} on grids with M in {16, 32, 64}, with
+// The convolution for CIN in {4, 16, 32} on grids with M in {16, 32, 64}, with
 // its operands staged in LDS: a block of 4 wavefronts computes kLdsPix
 // consecutive pixels (kLdsPix / M whole rows of one field).  It stages those
 // rows and one halo row on each side (periodic), all M columns, and the
@@ -271,7 +275,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_c(Conv cv, int M, int npi
 // output channel so that the 16 pixels (or channels) a matrix-core operand
 // load spans fall in different LDS banks.  Each wavefront then computes
 // kLdsPix / 64 tiles from LDS, with its weight operands held in registers.
-// Same products and accumulation order as k_conv_fwd.
+// Same products as k_conv_fwd, accumulated over K in chunks of 32.
 constexpr int kLdsPix = 128;
 template <int CIN, int NCT, bool LAST>
 __global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npix,
@@ -280,10 +284,15 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npi
                                                           const float* __restrict__ bias,
                                                           unsigned short* Xnext,
                                                           const float* __restrict__ u, float* pred) {
-    static_assert((CIN == 4 || CIN % 16 == 0) && (NCT == 1 || NCT == 2), "unsupported shape");
-    constexpr int CH = CIN >= 16 ? CIN / 16 : 1;
-    constexpr int NK = CIN >= 16 ? 9 * CH : 3;  // chunks of 16 K values (K = 36 padded to 48 at CIN = 4)
-    constexpr int K = NK * 16;                  // weights per output channel, padding included
+    static_assert((CIN == 4 || CIN == 16 || CIN == 32) && (NCT == 1 || NCT == 2), "unsupported shape");
+    // K = 9 CIN in chunks of 32 for v_mfma_f32_16x16x32_bf16: lane group g holds
+    // the K values 8 g .. 8 g + 7 of a chunk (K index = tap CIN + channel):
+    //   CIN = 32: one tap per chunk, channels 8 g .. 8 g + 7;
+    //   CIN = 16: taps 2 i (g = 0, 1) and 2 i + 1 (g = 2, 3), channels 8 (g & 1) ..;
+    //   CIN = 4:  taps 8 i + 2 g and 8 i + 2 g + 1, 4 channels each.
+    // Taps past 8 contribute zeros (the padding of K to a multiple of 32).
+    constexpr int NK = (9 * CIN + 31) / 32;
+    constexpr int K = NK * 32;                  // weights per output channel, padding included
     // staged elements per pixel: 4 channels at CIN = 4 (16 consecutive pixels
     // then fill consecutive banks), else padded by 8
     constexpr int XS = CIN == 4 ? 4 : CIN + 8;
@@ -321,22 +330,24 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npi
             *reinterpret_cast<uint4*>(sx + pix * XS + c) = v;
         }
     }
-    // the weights of the NCT * 16 output channels (rows of Wf, K = Kpad here)
+    // the weights of the NCT * 16 output channels (rows of Wf, Kpad long, then
+    // zeros up to K)
     const int wvec = NCT * 16 * K / 8;
     for (int t = threadIdx.x; t < wvec; t += kThreads) {
         const int e = t * 8, o = e / K, k = e - o * K;
-        *reinterpret_cast<uint4*>(sw + o * WS + k) =
-            *reinterpret_cast<const uint4*>(Wf + (size_t)o * cv.Kpad + k);
+        uint4 w = make_uint4(0u, 0u, 0u, 0u);
+        if (k < cv.Kpad) w = *reinterpret_cast<const uint4*>(Wf + (size_t)o * cv.Kpad + k);
+        *reinterpret_cast<uint4*>(sw + o * WS + k) = w;
     }
     __syncthreads();
     const int wave = threadIdx.x / kWaveN, lane = threadIdx.x & (kWaveN - 1);
     const int r16 = lane & 15, g = lane >> 4;
-    bf16x4 wb[NCT][NK];
+    bf16x8 wb[NCT][NK];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
         for (int i = 0; i < NK; ++i)
-            wb[ct][i] = *reinterpret_cast<const bf16x4*>(sw + (ct * 16 + r16) * WS + i * 16 + 4 * g);
+            wb[ct][i] = *reinterpret_cast<const bf16x8*>(sw + (ct * 16 + r16) * WS + i * 32 + 8 * g);
     float bo[NCT];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
@@ -350,27 +361,34 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npi
         const int lp = (wave * TPW + tt) * 16 + r16;  // pixel within the block
         const int ly = lp / M, x = lp - ly * M;
         const int xs[3] = {x == 0 ? M - 1 : x - 1, x, x == M - 1 ? 0 : x + 1};
-        bf16x4 a[NK];
-        if constexpr (CIN == 4) {
-            // chunk i, lane group g: the 4 channels of tap 4 i + g (zero past tap 8)
+        // staged pixel of tap t (staged row ly + dy + 1)
+        auto tap_pix = [&](int t) {
+            const int ty = t / 3, tx = t - 3 * ty;
+            return (ly + ty) * M + (tx == 0 ? xs[0] : (tx == 1 ? xs[1] : xs[2]));
+        };
+        bf16x8 a[NK];
 #pragma unroll
-            for (int i = 0; i < NK; ++i) {
-                const int tap = 4 * i + g;
-                a[i] = bf16x4{0, 0, 0, 0};
-                if (tap < 9) {
-                    const int ty = tap / 3, tx = tap - 3 * ty;
-                    const int xx = tx == 0 ? xs[0] : (tx == 1 ? xs[1] : xs[2]);
-                    a[i] = *reinterpret_cast<const bf16x4*>(sx + ((ly + ty) * M + xx) * XS);
+        for (int i = 0; i < NK; ++i) {
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if constexpr (CIN == 32) {
+                v = *reinterpret_cast<const uint4*>(sx + tap_pix(i) * XS + 8 * g);
+            } else if constexpr (CIN == 16) {
+                const int t = 2 * i + (g >> 1);
+                if (t < 9) v = *reinterpret_cast<const uint4*>(sx + tap_pix(t) * XS + 8 * (g & 1));
+            } else {
+                const int t = 8 * i + 2 * g;
+                if (t < 9) {
+                    const uint2 lo = *reinterpret_cast<const uint2*>(sx + tap_pix(t) * XS);
+                    v.x = lo.x;
+                    v.y = lo.y;
+                }
+                if (t + 1 < 9) {
+                    const uint2 hi = *reinterpret_cast<const uint2*>(sx + tap_pix(t + 1) * XS);
+                    v.z = hi.x;
+                    v.w = hi.y;
                 }
             }
-        } else {
-#pragma unroll
-            for (int tap = 0; tap < 9; ++tap) {
-                const int pix = (ly + tap / 3) * M + xs[tap % 3];  // staged row ly + dy + 1
-#pragma unroll
-                for (int h = 0; h < CH; ++h)
-                    a[tap * CH + h] = *reinterpret_cast<const bf16x4*>(sx + pix * XS + h * 16 + 4 * g);
-            }
+            a[i] = __builtin_bit_cast(bf16x8, v);
         }
         f32x4 acc[NCT];
 #pragma unroll
@@ -379,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npi
         for (int i = 0; i < NK; ++i)
 #pragma unroll
             for (int ct = 0; ct < NCT; ++ct)
-                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], wb[ct][i], acc[ct], 0, 0, 0);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], wb[ct][i], acc[ct], 0, 0, 0);
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
             const int o = ct * 16 + r16;
@@ -454,20 +472,33 @@ __global__ __launch_bounds__(kThreads) void k_conv_bwd(Conv cv, int M, int npix,
     const int lane = threadIdx.x & (kWaveN - 1), r16 = lane & 15, g = lane >> 4;
     const int qa = tile * 16 + r16;
     const int nct = cv.cin16 / 16;
+    // K = 9 cout4 in chunks of 32 (v_mfma_f32_16x16x32_bf16): lane group g
+    // holds K values k0 + 8 g .. + 7 as two runs of 4, each inside one tap
+    // (cout4 is a multiple of 4); values past Kb (and past the row of Wb)
+    // are zeros
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < cv.Kbpad; k0 += 16) {
-        const int k = k0 + 4 * g;
-        bf16x4 a = {0, 0, 0, 0};
-        if (k < cv.Kb) {
-            const int tap = k / cv.cout4, o = k - tap * cv.cout4;
-            const int p = shifted(qa, tap, -1, M);
-            a = *reinterpret_cast<const bf16x4*>(dZb + (size_t)p * cv.cout4 + o);
+    for (int k0 = 0; k0 < cv.Kbpad; k0 += 32) {
+        bf16x4 ah[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, bh0[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}},
+               bh1[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            const int k = k0 + 8 * g + 4 * hf;
+            if (k < cv.Kb) {
+                const int tap = k / cv.cout4, o = k - tap * cv.cout4;
+                const int p = shifted(qa, tap, -1, M);
+                ah[hf] = *reinterpret_cast<const bf16x4*>(dZb + (size_t)p * cv.cout4 + o);
+            }
+            if (k < cv.Kbpad) {
+                bh0[hf] = *reinterpret_cast<const bf16x4*>(Wb + (size_t)r16 * cv.Kbpad + k);
+                if (nct > 1) bh1[hf] = *reinterpret_cast<const bf16x4*>(Wb + (size_t)(16 + r16) * cv.Kbpad + k);
+            }
         }
-        const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(Wb + (size_t)r16 * cv.Kbpad + k);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b0, acc0, 0, 0, 0);
+        const bf16x8 a = __builtin_bit_cast(bf16x8, __builtin_shufflevector(ah[0], ah[1], 0, 1, 2, 3, 4, 5, 6, 7));
+        const bf16x8 b0 = __builtin_bit_cast(bf16x8, __builtin_shufflevector(bh0[0], bh0[1], 0, 1, 2, 3, 4, 5, 6, 7));
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc0, 0, 0, 0);
         if (nct > 1) {
-            const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(Wb + (size_t)(16 + r16) * cv.Kbpad + k);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b1, acc1, 0, 0, 0);
+            const bf16x8 b1 = __builtin_bit_cast(bf16x8, __builtin_shufflevector(bh1[0], bh1[1], 0, 1, 2, 3, 4, 5, 6, 7));
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc1, 0, 0, 0);
         }
     }
     for (int ct = 0; ct < nct; ++ct) {
