@@ -93,6 +93,30 @@ struct PairArgs {
 
 // ---- small helpers ----------------------------------------------------------
 
+// The pair kernels take (DevParams, PairArgs, int) by value; the kernel-argument
+// segment holds them in that order at their natural alignment.  Reading an
+// argument again from that segment behind a compiler barrier gives the same
+// values in fresh scalar registers: the compiler can then no longer keep the
+// first copies live from the prologue to the last phase, which overflows the
+// scalar registers and spills them into vector-register lanes (one vector
+// instruction per spill and per reload).
+constexpr int kArgOffPairArgs =
+    (int)((sizeof(DevParams) + alignof(PairArgs) - 1) / alignof(PairArgs) * alignof(PairArgs));
+
+template <class T>
+__device__ __forceinline__ T kernel_arg_again(int offset) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const char __attribute__((address_space(4)))* seg_ptr;
+    typedef const T __attribute__((address_space(4)))* arg_ptr;
+    seg_ptr p = (seg_ptr)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(arg_ptr)(p + offset);
+#else
+    (void)offset;  // the host pass only parses device code
+    return T{};
+#endif
+}
+
 __device__ __forceinline__ int wrap_cell(int c, int nc) {
     c += (c < 0) ? nc : 0;
     return c - ((c >= nc) ? nc : 0);
@@ -811,6 +835,10 @@ __device__ __forceinline__ bool pair_tile(DevParams P, PairArgs a, int reduce, i
     __syncthreads();
 
     // ---- C: agent forces and integration, tile particles in canonical order
+    // (the parameters and pointers this phase uses, read again: see
+    // kernel_arg_again; a batch's parameters come from its replica table)
+    if constexpr (!BATCH) P = kernel_arg_again<DevParams>(0);
+    a = kernel_arg_again<PairArgs>(kArgOffPairArgs);
     const int rounds = (ntile + kWave - 1) / kWave;
     for (int r = 0; r < rounds; ++r) {
         const int k = r * kWave + lane;
