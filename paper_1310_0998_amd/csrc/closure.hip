@@ -415,6 +415,204 @@ __global__ __launch_bounds__(kThreads) void k_conv_fwd_l(Conv cv, int M, int npi
     }
 }
 
+// ---- the whole network of a rollout step -------------------------------------
+// All L convolutions of a network with c_in = 4 and width 32 in one kernel, on
+// fields of side M in {32, 64}.  A block of kBandWaves wavefronts owns a band
+// of R = kBandPix / M output rows of one field.  It stages the input rows of
+// the band plus L rows on each side (periodic), then computes each layer on
+// the rows the layers after it need - the band plus one row more on each side
+// per layer still to come - with the activations kept in LDS; only the input
+// X_1 and the prediction touch global memory.  Every output element is the
+// same sequence of matrix-core operations as in k_conv_fwd_l (K in chunks of
+// 32, the same operand layout, bias, ReLU and BF16 rounding), so the result
+// is bitwise that of the layer-by-layer kernels.  The halo rows are computed
+// by both neighbouring bands: 1.34x the matrix-core work of the layer-by-layer
+// kernels at M = 64, L = 4, in exchange for no intermediate global traffic and
+// one launch instead of L.
+constexpr int kBandPix = 512;    // output pixels per band
+constexpr int kBandWaves = 8;
+constexpr int kBandMaxL = 4;
+constexpr int kBandXS = 40;      // staged elements per pixel of a 32-channel activation
+
+struct BandNet {
+    const unsigned short* wf[kBandMaxL];  // BF16 weights [cout16][kpad]
+    const float* bias[kBandMaxL];
+    int kpad[kBandMaxL];
+    int cout[kBandMaxL];
+};
+
+// The weight operands of one layer for this lane (rows of Wf, kpad long, zeros
+// up to NK 32) and the biases of the output channels it holds: loaded a layer
+// ahead, so that their latency overlaps the layer before.
+template <int NCT, int NK>
+struct BandW {
+    bf16x8 w[NCT][NK];
+    float bo[NCT][4];
+};
+
+template <int NCT, int NK>
+__device__ __forceinline__ void band_weights(BandW<NCT, NK>& W, const unsigned short* __restrict__ Wf,
+                                             int kpad, const float* __restrict__ bias, int cout) {
+    const int lane = threadIdx.x & (kWaveN - 1), r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+        const int o = ct * 16 + r16;
+#pragma unroll
+        for (int i = 0; i < NK; ++i) {
+            const int k = i * 32 + 8 * g;
+            uint4 w = make_uint4(0u, 0u, 0u, 0u);
+            if (k < kpad) w = *reinterpret_cast<const uint4*>(Wf + (size_t)o * kpad + k);
+            W.w[ct][i] = __builtin_bit_cast(bf16x8, w);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int oc = ct * 16 + 4 * g + i;
+            W.bo[ct][i] = oc < cout ? bias[oc] : 0.f;
+        }
+    }
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values to packed BF16, round to nearest even (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
+}
+
+// One layer of the band: rows_out rows of M output pixels from the staged
+// input (rows_out + 2 rows, XSI elements per pixel).  The matrix cores take
+// the weights as the first operand and the activations as the second, so
+// each lane ends with four consecutive output channels of one pixel: hidden
+// layers write them, ReLU and BF16 applied, as one 8-byte store into sout
+// (kBandXS elements per pixel); the last layer writes pred = u + z at the
+// global pixels pix0 + local pixel.
+template <int M, int CIN, int NCT, bool LAST>
+__device__ __forceinline__ void band_layer(int rows_out, const unsigned short* sin, unsigned short* sout,
+                                           const BandW<NCT, (9 * CIN + 31) / 32>& W, int cout, size_t pix0,
+                                           const float* __restrict__ u, float* pred) {
+    constexpr int NK = (9 * CIN + 31) / 32;
+    constexpr int XSI = CIN == 4 ? 4 : kBandXS;
+    const int wave = threadIdx.x / kWaveN, lane = threadIdx.x & (kWaveN - 1);
+    const int r16 = lane & 15, g = lane >> 4;
+    const int ntile = rows_out * M / 16;
+    for (int t = wave; t < ntile; t += kBandWaves) {
+        const int lp = t * 16 + r16;  // this lane's pixel
+        const int ly = lp / M, x = lp - ly * M;
+        const int xs[3] = {x == 0 ? M - 1 : x - 1, x, x == M - 1 ? 0 : x + 1};
+        auto tap_pix = [&](int tp) {
+            const int ty = tp / 3, tx = tp - 3 * ty;
+            return (ly + ty) * M + (tx == 0 ? xs[0] : (tx == 1 ? xs[1] : xs[2]));
+        };
+        bf16x8 a[NK];
+#pragma unroll
+        for (int i = 0; i < NK; ++i) {
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if constexpr (CIN == 32) {
+                v = *reinterpret_cast<const uint4*>(sin + tap_pix(i) * XSI + 8 * g);
+            } else {
+                const int tp = 8 * i + 2 * g;
+                if (tp < 9) {
+                    const uint2 lo = *reinterpret_cast<const uint2*>(sin + tap_pix(tp) * XSI);
+                    v.x = lo.x;
+                    v.y = lo.y;
+                }
+                if (tp + 1 < 9) {
+                    const uint2 hi = *reinterpret_cast<const uint2*>(sin + tap_pix(tp + 1) * XSI);
+                    v.z = hi.x;
+                    v.w = hi.y;
+                }
+            }
+            a[i] = __builtin_bit_cast(bf16x8, v);
+        }
+        f32x4 acc[NCT];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < NK; ++i)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w[ct][i], a[i], acc[ct], 0, 0, 0);
+        // acc[ct][i]: output channel ct 16 + 4 g + i of pixel lp
+        if constexpr (LAST) {
+            const size_t p = pix0 + (size_t)lp;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = 4 * g + i;
+                if (o < cout) pred[2 * p + o] = u[2 * p + o] + (acc[0][i] + W.bo[0][i]);
+            }
+        } else {
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+                float z[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) z[i] = fmaxf(acc[ct][i] + W.bo[ct][i], 0.f);
+                *reinterpret_cast<uint2*>(sout + lp * kBandXS + ct * 16 + 4 * g) =
+                    make_uint2(pack_bf16(z[0], z[1]), pack_bf16(z[2], z[3]));
+            }
+        }
+    }
+}
+
+template <int L, int M>
+__global__ __launch_bounds__(kBandWaves * kWaveN) void k_net_band(BandNet net,
+                                                                  const unsigned short* __restrict__ X,
+                                                                  const float* __restrict__ u,
+                                                                  float* pred) {
+    static_assert(L >= 2 && L <= kBandMaxL, "2 to 4 layers");
+    static_assert(M == 32 || M == 64, "M in {32, 64}");
+    constexpr int R = kBandPix / M, bands = M / R, M2 = M * M;
+    // input band: R + 2 L rows of 4 channels; layer l writes R + 2 (L - 1 - l)
+    // rows, the even layers into sa, the odd ones into sb
+    __shared__ __align__(16) unsigned short sx[(R + 2 * L) * M * 4];
+    __shared__ __align__(16) unsigned short sa[(R + 2 * (L - 1)) * M * kBandXS];
+    __shared__ __align__(16) unsigned short sb[L >= 3 ? (R + 2 * (L - 2)) * M * kBandXS : 8];
+    const int b = blockIdx.x / bands, y0 = (blockIdx.x - b * bands) * R;
+    BandW<2, 2> w0;
+    band_weights(w0, net.wf[0], net.kpad[0], net.bias[0], net.cout[0]);
+    constexpr int npx = (R + 2 * L) * M;
+    for (int pix = threadIdx.x; pix < npx; pix += kBandWaves * kWaveN) {
+        const int rr = pix / M, xx = pix - rr * M;
+        int yy = y0 - L + rr;
+        yy += (yy < 0) ? M : 0;
+        yy -= (yy >= M) ? M : 0;
+        *reinterpret_cast<uint2*>(sx + pix * 4) =
+            *reinterpret_cast<const uint2*>(X + ((size_t)b * M2 + (size_t)yy * M + xx) * 4);
+    }
+    const size_t pix0 = (size_t)b * M2 + (size_t)y0 * M;
+    if constexpr (L == 2) {
+        BandW<1, 9> w1;
+        band_weights(w1, net.wf[1], net.kpad[1], net.bias[1], net.cout[1]);
+        __syncthreads();
+        band_layer<M, 4, 2, false>(R + 2, sx, sa, w0, net.cout[0], 0, nullptr, nullptr);
+        __syncthreads();
+        band_layer<M, 32, 1, true>(R, sa, nullptr, w1, net.cout[1], pix0, u, pred);
+    } else {
+        BandW<2, 9> w1;
+        band_weights(w1, net.wf[1], net.kpad[1], net.bias[1], net.cout[1]);
+        __syncthreads();
+        band_layer<M, 4, 2, false>(R + 2 * (L - 1), sx, sa, w0, net.cout[0], 0, nullptr, nullptr);
+        __syncthreads();
+        if constexpr (L == 3) {
+            BandW<1, 9> w2;
+            band_weights(w2, net.wf[2], net.kpad[2], net.bias[2], net.cout[2]);
+            band_layer<M, 32, 2, false>(R + 2, sa, sb, w1, net.cout[1], 0, nullptr, nullptr);
+            __syncthreads();
+            band_layer<M, 32, 1, true>(R, sb, nullptr, w2, net.cout[2], pix0, u, pred);
+        } else {
+            BandW<2, 9> w2;
+            band_weights(w2, net.wf[2], net.kpad[2], net.bias[2], net.cout[2]);
+            band_layer<M, 32, 2, false>(R + 4, sa, sb, w1, net.cout[1], 0, nullptr, nullptr);
+            __syncthreads();
+            BandW<1, 9> w3;
+            band_weights(w3, net.wf[3], net.kpad[3], net.bias[3], net.cout[3]);
+            band_layer<M, 32, 2, false>(R + 2, sb, sa, w2, net.cout[2], 0, nullptr, nullptr);
+            __syncthreads();
+            band_layer<M, 32, 1, true>(R, sa, nullptr, w3, net.cout[3], pix0, u, pred);
+        }
+    }
+}
+
 // ---- loss --------------------------------------------------------------------------
 
 // d = pred - target; loss partials sum d^2 (FP64, per block); the gradient of
@@ -1004,6 +1202,32 @@ int forward(dpd_nn* h, const float* u, const float* cond, int B, float* pred, bo
     return DPD_OK;
 }
 
+// The forward pass of a rollout step as one kernel (k_net_band) where the
+// network's shape allows it: c_in = 4, width 32, 2 to 4 layers, M in {32, 64}.
+// Needs the BF16 weights and the first input in place, as forward(prepared).
+bool band_fits(const Net& n) {
+    return n.p.c_in == 4 && n.p.width == 32 && n.p.layers >= 2 && n.p.layers <= kBandMaxL &&
+           (n.p.M == 32 || n.p.M == 64);
+}
+
+int forward_band(dpd_nn* h, const float* u, int B, float* pred) {
+    const Net& n = h->net;
+    BandNet bn = {};
+    for (int l = 0; l < n.p.layers; ++l) {
+        bn.wf[l] = at<unsigned short>(h, n.o_wf[l]);
+        bn.bias[l] = at<float>(h, n.o_w + 4 * n.boff[l]);
+        bn.kpad[l] = n.conv[l].Kpad;
+        bn.cout[l] = n.conv[l].cout;
+    }
+    const int M = n.p.M, L = n.p.layers, grid = B * (M * M / kBandPix);
+    const unsigned short* X = at<unsigned short>(h, n.o_x[0]);
+    auto kern = M == 64 ? (L == 2 ? k_net_band<2, 64> : (L == 3 ? k_net_band<3, 64> : k_net_band<4, 64>))
+                        : (L == 2 ? k_net_band<2, 32> : (L == 3 ? k_net_band<3, 32> : k_net_band<4, 32>));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBandWaves * kWaveN), 0, h->stream, bn, X, u, pred);
+    NLAUNCH(h);
+    return DPD_OK;
+}
+
 int gradient(dpd_nn* h, const float* u, const float* cond, const float* target, int B,
              float* grad, double* loss) {
     const Net& n = h->net;
@@ -1225,8 +1449,9 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
                                noise_filter, Hh);
             NLAUNCH(nn);
         }
+        const bool band = band_fits(n);
         for (int s = 1; s <= steps; ++s) {
-            rc = forward(nn, ucur, nullptr, B, pred, true);
+            rc = band ? forward_band(nn, ucur, B, pred) : forward(nn, ucur, nullptr, B, pred, true);
             if (rc) return rc;
             float* save = (s % save_every == 0) ? traj + (size_t)(s / save_every - 1) * nf : nullptr;
             if (noise_filter) {
