@@ -433,12 +433,23 @@ constexpr int kBandPix = 512;    // output pixels per band
 constexpr int kBandWaves = 8;
 constexpr int kBandMaxL = 4;
 constexpr int kBandXS = 40;      // staged elements per pixel of a 32-channel activation
+constexpr int kNoiseAhead = 8;   // rollout steps whose noise is drawn in one pass
 
 struct BandNet {
     const unsigned short* wf[kBandMaxL];  // BF16 weights [cout16][kpad]
     const float* bias[kBandMaxL];
     int kpad[kBandMaxL];
     int cout[kBandMaxL];
+};
+
+// What the last layer of a rollout step writes: u <- (u + z) + noise (in
+// place), its copy into save (if not null) and its BF16 values into channels
+// 0 and 1 of the next input (4 channels per pixel; the others stay).
+struct BandOut {
+    float* u;
+    const float* noise;   // this step's noise, same layout as u
+    float* save;
+    unsigned short* xnext;
 };
 
 // The weight operands of one layer for this lane (rows of Wf, kpad long, zeros
@@ -480,17 +491,15 @@ __device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
     return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
 }
 
-// One layer of the band: rows_out rows of M output pixels from the staged
-// input (rows_out + 2 rows, XSI elements per pixel).  The matrix cores take
-// the weights as the first operand and the activations as the second, so
-// each lane ends with four consecutive output channels of one pixel: hidden
-// layers write them, ReLU and BF16 applied, as one 8-byte store into sout
-// (kBandXS elements per pixel); the last layer writes pred = u + z at the
-// global pixels pix0 + local pixel.
-template <int M, int CIN, int NCT, bool LAST>
+// A hidden layer of the band: rows_out rows of M output pixels from the
+// staged input (rows_out + 2 rows, XSI elements per pixel).  The matrix cores
+// take the weights as the first operand and the activations as the second,
+// so each lane ends with four consecutive output channels of one pixel, and
+// writes them, ReLU and BF16 applied, as one 8-byte store into sout
+// (kBandXS elements per pixel).
+template <int M, int CIN, int NCT>
 __device__ __forceinline__ void band_layer(int rows_out, const unsigned short* sin, unsigned short* sout,
-                                           const BandW<NCT, (9 * CIN + 31) / 32>& W, int cout, size_t pix0,
-                                           const float* __restrict__ u, float* pred) {
+                                           const BandW<NCT, (9 * CIN + 31) / 32>& W) {
     constexpr int NK = (9 * CIN + 31) / 32;
     constexpr int XSI = CIN == 4 ? 4 : kBandXS;
     const int wave = threadIdx.x / kWaveN, lane = threadIdx.x & (kWaveN - 1);
@@ -534,22 +543,56 @@ __device__ __forceinline__ void band_layer(int rows_out, const unsigned short* s
             for (int ct = 0; ct < NCT; ++ct)
                 acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w[ct][i], a[i], acc[ct], 0, 0, 0);
         // acc[ct][i]: output channel ct 16 + 4 g + i of pixel lp
-        if constexpr (LAST) {
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            float z[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z[i] = fmaxf(acc[ct][i] + W.bo[ct][i], 0.f);
+            *reinterpret_cast<uint2*>(sout + lp * kBandXS + ct * 16 + 4 * g) =
+                make_uint2(pack_bf16(z[0], z[1]), pack_bf16(z[2], z[3]));
+        }
+    }
+}
+
+// The last layer (32 -> 2 channels) of the band: R rows, kLastTPW tiles per
+// wavefront.  u and the noise of this lane's pixels were loaded at the start
+// of the kernel (ul, nl; lanes of group 0 hold output channels 0 and 1), so
+// the layer does not wait on global memory:
+// u <- (u + z) + noise, the same roundings as the prediction followed by
+// k_noise or k_colour_out; the field is updated in place (each value is read
+// and written by this lane only), copied to save, and its BF16 values go to
+// channels 0 and 1 of the next input.
+constexpr int kLastTPW = kBandPix / 16 / kBandWaves;
+
+template <int M>
+__device__ __forceinline__ void band_last(const unsigned short* sin, const BandW<1, 9>& W, size_t pix0,
+                                          const float2 (&ul)[kLastTPW], const float2 (&nl)[kLastTPW],
+                                          const BandOut& out) {
+    const int wave = threadIdx.x / kWaveN, lane = threadIdx.x & (kWaveN - 1);
+    const int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < kLastTPW; ++j) {
+        const int t = wave + kBandWaves * j;
+        const int lp = t * 16 + r16;
+        const int ly = lp / M, x = lp - ly * M;
+        const int xs[3] = {x == 0 ? M - 1 : x - 1, x, x == M - 1 ? 0 : x + 1};
+        bf16x8 a[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int ty = i / 3, tx = i - 3 * ty;
+            const int pix = (ly + ty) * M + (tx == 0 ? xs[0] : (tx == 1 ? xs[1] : xs[2]));
+            a[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sin + pix * kBandXS + 8 * g));
+        }
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 9; ++i) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w[0][i], a[i], acc, 0, 0, 0);
+        if (g == 0) {
             const size_t p = pix0 + (size_t)lp;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int o = 4 * g + i;
-                if (o < cout) pred[2 * p + o] = u[2 * p + o] + (acc[0][i] + W.bo[0][i]);
-            }
-        } else {
-#pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) {
-                float z[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) z[i] = fmaxf(acc[ct][i] + W.bo[ct][i], 0.f);
-                *reinterpret_cast<uint2*>(sout + lp * kBandXS + ct * 16 + 4 * g) =
-                    make_uint2(pack_bf16(z[0], z[1]), pack_bf16(z[2], z[3]));
-            }
+            const float vx = (ul[j].x + (acc[0] + W.bo[0][0])) + nl[j].x;
+            const float vy = (ul[j].y + (acc[1] + W.bo[0][1])) + nl[j].y;
+            *reinterpret_cast<float2*>(out.u + 2 * p) = make_float2(vx, vy);
+            if (out.save) *reinterpret_cast<float2*>(out.save + 2 * p) = make_float2(vx, vy);
+            *reinterpret_cast<unsigned*>(out.xnext + 4 * p) = (unsigned)to_bf16(vx) | ((unsigned)to_bf16(vy) << 16);
         }
     }
 }
@@ -557,8 +600,7 @@ __device__ __forceinline__ void band_layer(int rows_out, const unsigned short* s
 template <int L, int M>
 __global__ __launch_bounds__(kBandWaves * kWaveN) void k_net_band(BandNet net,
                                                                   const unsigned short* __restrict__ X,
-                                                                  const float* __restrict__ u,
-                                                                  float* pred) {
+                                                                  BandOut out) {
     static_assert(L >= 2 && L <= kBandMaxL, "2 to 4 layers");
     static_assert(M == 32 || M == 64, "M in {32, 64}");
     constexpr int R = kBandPix / M, bands = M / R, M2 = M * M;
@@ -568,6 +610,21 @@ __global__ __launch_bounds__(kBandWaves * kWaveN) void k_net_band(BandNet net,
     __shared__ __align__(16) unsigned short sa[(R + 2 * (L - 1)) * M * kBandXS];
     __shared__ __align__(16) unsigned short sb[L >= 3 ? (R + 2 * (L - 2)) * M * kBandXS : 8];
     const int b = blockIdx.x / bands, y0 = (blockIdx.x - b * bands) * R;
+    const size_t pix0 = (size_t)b * M2 + (size_t)y0 * M;
+    // the last layer's u and noise, loaded now (lanes of group 0)
+    float2 ul[kLastTPW], nl[kLastTPW];
+    {
+        const int wave = threadIdx.x / kWaveN, lane = threadIdx.x & (kWaveN - 1);
+#pragma unroll
+        for (int j = 0; j < kLastTPW; ++j) {
+            ul[j] = nl[j] = make_float2(0.f, 0.f);
+            if (lane < 16) {
+                const size_t p = pix0 + (size_t)((wave + kBandWaves * j) * 16 + lane);
+                ul[j] = *reinterpret_cast<const float2*>(out.u + 2 * p);
+                nl[j] = *reinterpret_cast<const float2*>(out.noise + 2 * p);
+            }
+        }
+    }
     BandW<2, 2> w0;
     band_weights(w0, net.wf[0], net.kpad[0], net.bias[0], net.cout[0]);
     constexpr int npx = (R + 2 * L) * M;
@@ -579,36 +636,35 @@ __global__ __launch_bounds__(kBandWaves * kWaveN) void k_net_band(BandNet net,
         *reinterpret_cast<uint2*>(sx + pix * 4) =
             *reinterpret_cast<const uint2*>(X + ((size_t)b * M2 + (size_t)yy * M + xx) * 4);
     }
-    const size_t pix0 = (size_t)b * M2 + (size_t)y0 * M;
     if constexpr (L == 2) {
         BandW<1, 9> w1;
         band_weights(w1, net.wf[1], net.kpad[1], net.bias[1], net.cout[1]);
         __syncthreads();
-        band_layer<M, 4, 2, false>(R + 2, sx, sa, w0, net.cout[0], 0, nullptr, nullptr);
+        band_layer<M, 4, 2>(R + 2, sx, sa, w0);
         __syncthreads();
-        band_layer<M, 32, 1, true>(R, sa, nullptr, w1, net.cout[1], pix0, u, pred);
+        band_last<M>(sa, w1, pix0, ul, nl, out);
     } else {
         BandW<2, 9> w1;
         band_weights(w1, net.wf[1], net.kpad[1], net.bias[1], net.cout[1]);
         __syncthreads();
-        band_layer<M, 4, 2, false>(R + 2 * (L - 1), sx, sa, w0, net.cout[0], 0, nullptr, nullptr);
+        band_layer<M, 4, 2>(R + 2 * (L - 1), sx, sa, w0);
         __syncthreads();
         if constexpr (L == 3) {
             BandW<1, 9> w2;
             band_weights(w2, net.wf[2], net.kpad[2], net.bias[2], net.cout[2]);
-            band_layer<M, 32, 2, false>(R + 2, sa, sb, w1, net.cout[1], 0, nullptr, nullptr);
+            band_layer<M, 32, 2>(R + 2, sa, sb, w1);
             __syncthreads();
-            band_layer<M, 32, 1, true>(R, sb, nullptr, w2, net.cout[2], pix0, u, pred);
+            band_last<M>(sb, w2, pix0, ul, nl, out);
         } else {
             BandW<2, 9> w2;
             band_weights(w2, net.wf[2], net.kpad[2], net.bias[2], net.cout[2]);
-            band_layer<M, 32, 2, false>(R + 4, sa, sb, w1, net.cout[1], 0, nullptr, nullptr);
+            band_layer<M, 32, 2>(R + 4, sa, sb, w1);
             __syncthreads();
             BandW<1, 9> w3;
             band_weights(w3, net.wf[3], net.kpad[3], net.bias[3], net.cout[3]);
-            band_layer<M, 32, 2, false>(R + 2, sb, sa, w2, net.cout[2], 0, nullptr, nullptr);
+            band_layer<M, 32, 2>(R + 2, sb, sa, w2);
             __syncthreads();
-            band_layer<M, 32, 1, true>(R, sa, nullptr, w3, net.cout[3], pix0, u, pred);
+            band_last<M>(sa, w3, pix0, ul, nl, out);
         }
     }
 }
@@ -843,14 +899,16 @@ __global__ __launch_bounds__(kThreads) void k_filter_hat(int M, const float* __r
     Hhat[t] = make_float2(re, im);
 }
 
-// Row j of field b: white numbers w[j][i][c] = alpha(b M^2 + j M + i, c, step)
-// (Philox4x32-10 and Box-Muller, as k_noise), then A[b][j][k][c] =
-// sum_i w[j][i][c] tw[k i mod M] for k <= M / 2 (the rest of a real field's
-// spectrum is conjugate to it).
-__global__ void k_colour_rows(int M, uint32_t step, uint32_t k0, uint32_t k1, float2* A) {
+// Row j of field b at step step0 + q (blockIdx.y = q B + b): white numbers
+// w[j][i][c] = alpha(b M^2 + j M + i, c, step) (Philox4x32-10 and Box-Muller,
+// as k_noise), then A[q B + b][j][k][c] = sum_i w[j][i][c] tw[k i mod M] for
+// k <= M / 2 (the rest of a real field's spectrum is conjugate to it).
+__global__ void k_colour_rows(int M, int B, uint32_t step0, uint32_t k0, uint32_t k1, float2* A) {
     __shared__ float2 tw[kColourMaxM];
     __shared__ float sw[2 * kColourMaxM];
-    const int j = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    const int j = blockIdx.x, bq = blockIdx.y, t = threadIdx.x;
+    const int q = bq / B, b = bq - q * B;
+    const uint32_t step = step0 + (uint32_t)q;
     twiddle_table(M, tw);
     const uint32_t point = (uint32_t)(((size_t)b * M + j) * M + (t >> 1));
     const uint4 r = dpd::philox4x32_10(make_uint4(point, (uint32_t)(t & 1), step, 0u), k0, k1);
@@ -867,7 +925,7 @@ __global__ void k_colour_rows(int M, uint32_t step, uint32_t k0, uint32_t k1, fl
         m += k;
         m -= (m >= M) ? M : 0;
     }
-    A[(((size_t)b * M + j) * M + k) * 2 + c] = make_float2(re, im);
+    A[(((size_t)bq * M + j) * M + k) * 2 + c] = make_float2(re, im);
 }
 
 // Column k <= M / 2 of field b: the column DFT, times Hhat, and the inverse
@@ -939,6 +997,45 @@ __global__ void k_colour_out(int M, const float2* __restrict__ A, const float* _
     unext[2 * p + c] = v;
     if (save) save[2 * p + c] = v;
     X[p * cin + c] = to_bf16(v);
+}
+
+// The noise of S steps ahead, for the rollout kernel that adds it: noise[q][t]
+// = s_c alpha(t / 2, c, step0 + q) (t = 2 point + component; as k_noise) and,
+// filtered, noise[q B + b][p][c] = s_c (the inverse row transform's real part
+// over M^2) (as k_colour_out); the sums are the same as there.
+__global__ void k_noise_steps(int nf, int S, uint32_t step0, uint32_t k0, uint32_t k1, float s0, float s1,
+                              float* noise) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)nf * S) return;
+    const int q = (int)(t / nf), tt = (int)(t - (long long)q * nf);
+    const uint4 w = dpd::philox4x32_10(make_uint4((uint32_t)(tt >> 1), (uint32_t)(tt & 1), step0 + (uint32_t)q, 0u),
+                                       k0, k1);
+    const float alpha = dpd::alpha_from_words(0, make_uint2(w.x, w.y));
+    noise[t] = ((tt & 1) ? s1 : s0) * alpha;
+}
+
+__global__ void k_colour_noise(int M, const float2* __restrict__ A, float s0, float s1, float* noise) {
+    __shared__ float2 tw[kColourMaxM];
+    __shared__ float2 sa[2 * kColourMaxM];
+    const int j = blockIdx.x, bq = blockIdx.y, t = threadIdx.x;
+    twiddle_table(M, tw);
+    {
+        const int k = t >> 1, c = t & 1;
+        const int kk = k <= M / 2 ? k : M - k;
+        const float2 z = A[(((size_t)bq * M + j) * M + kk) * 2 + c];
+        sa[t] = k <= M / 2 ? z : make_float2(z.x, -z.y);
+    }
+    __syncthreads();
+    const int i = t >> 1, c = t & 1;
+    float re = 0.f;
+    for (int k = 0, m = 0; k < M; ++k) {  // m = k i mod M
+        const float2 e = tw[m], z = sa[2 * k + c];
+        re = fmaf(z.x, e.x, fmaf(z.y, e.y, re));
+        m += i;
+        m -= (m >= M) ? M : 0;
+    }
+    const float inv = 1.0f / (float)(M * M);
+    noise[(((size_t)bq * M + j) * M + i) * 2 + c] = (c ? s1 : s0) * (re * inv);
 }
 
 // ---- field statistics ------------------------------------------------------------
@@ -1210,7 +1307,10 @@ bool band_fits(const Net& n) {
            (n.p.M == 32 || n.p.M == 64);
 }
 
-int forward_band(dpd_nn* h, const float* u, int B, float* pred) {
+// One rollout step of the whole network as one kernel: reads the BF16 input
+// X, writes u <- (u + net) + noise, save and the next input Xn.
+int band_step(dpd_nn* h, int B, const unsigned short* X, unsigned short* Xn, float* u, const float* noise,
+              float* save) {
     const Net& n = h->net;
     BandNet bn = {};
     for (int l = 0; l < n.p.layers; ++l) {
@@ -1219,11 +1319,11 @@ int forward_band(dpd_nn* h, const float* u, int B, float* pred) {
         bn.kpad[l] = n.conv[l].Kpad;
         bn.cout[l] = n.conv[l].cout;
     }
+    const BandOut out = {u, noise, save, Xn};
     const int M = n.p.M, L = n.p.layers, grid = B * (M * M / kBandPix);
-    const unsigned short* X = at<unsigned short>(h, n.o_x[0]);
     auto kern = M == 64 ? (L == 2 ? k_net_band<2, 64> : (L == 3 ? k_net_band<3, 64> : k_net_band<4, 64>))
                         : (L == 2 ? k_net_band<2, 32> : (L == 3 ? k_net_band<3, 32> : k_net_band<4, 32>));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBandWaves * kWaveN), 0, h->stream, bn, X, u, pred);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBandWaves * kWaveN), 0, h->stream, bn, X, out);
     NLAUNCH(h);
     return DPD_OK;
 }
@@ -1441,6 +1541,52 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
                            n.p.c_in, (const float*)ucur, cond, X0);
         NLAUNCH(nn);
         const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+        if (band_fits(n)) {
+            // the whole network per step as one kernel, which also adds the
+            // noise; the noise of up to S steps is drawn ahead in one pass.
+            // Buffers free during a rollout: spectra [S][B][M][M][2] complex in
+            // dz[0], noise [S][B][M][M][2] in dz[1], DFT(h) in dzb[0], the
+            // second input buffer (the kernel reads one, writes the other) in
+            // dzb[1]
+            const int cmax = std::max(n.p.width, 4);
+            const int S = std::max(1, std::min(std::min(kNoiseAhead, cmax / 4), 65535 / B));
+            float2* Aw = at<float2>(nn, n.o_dz[0]);
+            float* noise = at<float>(nn, n.o_dz[1]);
+            float2* Hh = at<float2>(nn, n.o_dzb[0]);
+            unsigned short* X1 = at<unsigned short>(nn, n.o_dzb[1]);
+            hipLaunchKernelGGL(k_input, dim3(blocks(B * M2)), dim3(kThreads), 0, nn->stream, B * M2, M2,
+                               n.p.c_in, (const float*)ucur, cond, X1);
+            if (noise_filter)
+                hipLaunchKernelGGL(k_filter_hat, dim3(blocks(M2)), dim3(kThreads), 0, nn->stream, n.p.M,
+                                   noise_filter, Hh);
+            NLAUNCH(nn);
+            unsigned short *Xc = X0, *Xo = X1;
+            for (int s = 1; s <= steps; ++s) {
+                const int q = (s - 1) % S;
+                if (q == 0) {
+                    const int ns = std::min(S, steps - s + 1);
+                    if (noise_filter) {
+                        hipLaunchKernelGGL(k_colour_rows, dim3(n.p.M, B * ns), dim3(2 * n.p.M), 0, nn->stream,
+                                           n.p.M, B, (uint32_t)s, k0, k1, Aw);
+                        hipLaunchKernelGGL(k_colour_cols, dim3(n.p.M / 2 + 1, B * ns), dim3(2 * n.p.M), 0,
+                                           nn->stream, n.p.M, (const float2*)Hh, Aw);
+                        hipLaunchKernelGGL(k_colour_noise, dim3(n.p.M, B * ns), dim3(2 * n.p.M), 0,
+                                           nn->stream, n.p.M, (const float2*)Aw, noise_std[0], noise_std[1],
+                                           noise);
+                    } else {
+                        hipLaunchKernelGGL(k_noise_steps, dim3(blocks((long long)nf * ns)), dim3(kThreads), 0,
+                                           nn->stream, nf, ns, (uint32_t)s, k0, k1, noise_std[0],
+                                           noise_std[1], noise);
+                    }
+                    NLAUNCH(nn);
+                }
+                float* save = (s % save_every == 0) ? traj + (size_t)(s / save_every - 1) * nf : nullptr;
+                rc = band_step(nn, B, Xc, Xo, ucur, noise + (size_t)q * nf, save);
+                if (rc) return rc;
+                std::swap(Xc, Xo);
+            }
+            return DPD_OK;
+        }
         // filtered noise: DFT(h) once; the fields' spectra in a free buffer
         float2* Aw = at<float2>(nn, n.o_dz[0]);  // [B][M][M][2] complex
         float2* Hh = at<float2>(nn, n.o_dz[1]);  // [M][M] complex
@@ -1449,13 +1595,12 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
                                noise_filter, Hh);
             NLAUNCH(nn);
         }
-        const bool band = band_fits(n);
         for (int s = 1; s <= steps; ++s) {
-            rc = band ? forward_band(nn, ucur, B, pred) : forward(nn, ucur, nullptr, B, pred, true);
+            rc = forward(nn, ucur, nullptr, B, pred, true);
             if (rc) return rc;
             float* save = (s % save_every == 0) ? traj + (size_t)(s / save_every - 1) * nf : nullptr;
             if (noise_filter) {
-                hipLaunchKernelGGL(k_colour_rows, dim3(n.p.M, B), dim3(2 * n.p.M), 0, nn->stream, n.p.M,
+                hipLaunchKernelGGL(k_colour_rows, dim3(n.p.M, B), dim3(2 * n.p.M), 0, nn->stream, n.p.M, B,
                                    (uint32_t)s, k0, k1, Aw);
                 hipLaunchKernelGGL(k_colour_cols, dim3(n.p.M / 2 + 1, B), dim3(2 * n.p.M), 0, nn->stream,
                                    n.p.M, (const float2*)Hh, Aw);

@@ -132,11 +132,14 @@ def test_adam_matches_oracle(cl):
     net.close()
 
 
-def test_rollout_zero_network(cl):
+@pytest.mark.parametrize("width", [16, 32])
+def test_rollout_zero_network(cl, width):
     # zero parameters: without noise the field stays the start exactly; with
-    # noise each step adds independent N(0, s_c^2) per point and component
+    # noise each step adds independent N(0, s_c^2) per point and component.
+    # Width 32 takes the one-kernel step, with the noise drawn 8 steps ahead
+    # (the 100 steps cross 13 such batches)
     M = 64
-    net = cl.Closure(M, c_in=4, width=16, layers=2, max_batch=1, device=DEV)
+    net = cl.Closure(M, c_in=4, width=width, layers=2, max_batch=1, device=DEV)
     rng = np.random.default_rng(13)
     u0 = rng.normal(size=(M, M, 2)).astype(np.float32)
     cond = np.array([0.5, 1.0], np.float32)
@@ -221,14 +224,46 @@ def test_rollout_band_kernel_equals_layer_kernels(cl, M, layers, B):
     net.close()
 
 
-@pytest.mark.parametrize("M", [20, 64])
-def test_coloured_noise_is_the_periodic_convolution(cl, M):
+@pytest.mark.parametrize("filtered", [False, True])
+def test_rollout_band_kernel_adds_the_noise(cl, filtered):
+    # the one-kernel step adds noise drawn ahead of it: the first step of a
+    # noisy rollout is the layer-by-layer prediction plus the noise that a
+    # zero network of the same shape adds to a field at rest (0 + n = n),
+    # bit for bit, every field of the batch
+    M, B, layers = 64, 3, 3
+    rng = np.random.default_rng(23)
+    net = cl.Closure(M, c_in=4, width=32, layers=layers, max_batch=B, device=DEV)
+    net.set_weights(dev(inputs.closure_init(43, 4, 32, layers, out_scale=0.3)))
+    zero = cl.Closure(M, c_in=4, width=32, layers=layers, max_batch=B, device=DEV)
+    u0 = rng.normal(size=(B, M, M, 2)).astype(np.float32)
+    cond = rng.normal(size=(B, 2)).astype(np.float32)
+    ii = np.arange(M)
+    d = np.minimum(ii, M - ii).astype(np.float64)
+    h = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / 4.0).astype(np.float32)
+    kw = dict(seed=9, noise_filter=dev(h)) if filtered else dict(seed=9)
+    s = (0.2, 0.05)
+    got = host(net.rollout(dev(u0), dev(cond), 1, s, **kw))[0]
+    n = host(zero.rollout(dev(np.zeros_like(u0)), dev(cond), 1, s, **kw))[0]
+    pred = host(net.forward(dev(u0), dev(cond)))
+    assert np.abs(n).max() > 0
+    want = (pred.astype(np.float32) + n.astype(np.float32)).astype(np.float64)  # the FP32 sum
+    bad = np.argwhere(got != want)
+    assert len(bad) == 0, (len(bad), float(np.abs(got - want).max()),
+                           [(tuple(t), repr(got[tuple(t)]), repr(pred[tuple(t)]), repr(n[tuple(t)]))
+                            for t in bad[:4]])
+    net.close()
+    zero.close()
+
+
+@pytest.mark.parametrize("M,width,layers", [(20, 16, 1), (64, 16, 1), (64, 32, 2)])
+def test_coloured_noise_is_the_periodic_convolution(cl, M, width, layers):
     # one step of the zero network from rest: with unit noise_std the white
     # rollout gives w itself, and the filtered one h * w (periodic, per field
     # and component), here against an FP64 FFT convolution with a random,
-    # non-symmetric h; M = 20 is not a power of two
+    # non-symmetric h; M = 20 is not a power of two; width 32 takes the
+    # one-kernel step with the noise drawn ahead
     B = 2
-    net = cl.Closure(M, c_in=4, width=16, layers=1, max_batch=B, device=DEV)
+    net = cl.Closure(M, c_in=4, width=width, layers=layers, max_batch=B, device=DEV)
     rng = np.random.default_rng(15)
     h = rng.normal(size=(M, M)).astype(np.float32)
     u0 = np.zeros((B, M, M, 2), np.float32)
