@@ -1038,6 +1038,119 @@ __global__ void k_colour_noise(int M, const float2* __restrict__ A, float s0, fl
     noise[(((size_t)bq * M + j) * M + i) * 2 + c] = (c ? s1 : s0) * (re * inv);
 }
 
+// The same three passes for the rollout's noise drawn ahead, with each
+// length-M transform (M = kRadixP Q, a power of two) in two stages instead
+// of M-term sums: for n = Q n1 + n2 and k = k1 + P k2,
+//   X[k1 + P k2] = sum_{n2 < Q} W^(P n2 k2) [W^(n2 k1) sum_{n1 < P} x[Q n1 + n2] W^(Q n1 k1)],
+// W = e^{-2 pi i / M} (conjugated for the inverse transforms): P + Q + 1
+// complex products per output instead of M.  Stage outputs go through LDS.
+constexpr int kRadixP = 8;
+
+// The product of z and w (inv: of z and conj(w)).
+__device__ __forceinline__ float2 cmul(float2 z, float2 w, bool inv) {
+    if (inv) w.y = -w.y;
+    return make_float2(z.x * w.x - z.y * w.y, z.x * w.y + z.y * w.x);
+}
+
+// Stage 1 for slot idx = n2 P + k1 of component c: x holds M complex values
+// [n][c] (or M real values [n][c] with REAL).
+template <bool REAL>
+__device__ __forceinline__ float2 radix_stage1(const void* xv, int c, int idx, int M, const float2* tw, bool inv) {
+    const int Q = M / kRadixP, n2 = idx / kRadixP, k1 = idx - n2 * kRadixP;
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int n1 = 0; n1 < kRadixP; ++n1) {
+        float2 e = tw[(Q * n1 * k1) & (M - 1)];
+        if (inv) e.y = -e.y;
+        if constexpr (REAL) {
+            const float v = reinterpret_cast<const float*>(xv)[2 * (Q * n1 + n2) + c];
+            re = fmaf(v, e.x, re);
+            im = fmaf(v, e.y, im);
+        } else {
+            const float2 z = reinterpret_cast<const float2*>(xv)[2 * (Q * n1 + n2) + c];
+            re = fmaf(z.x, e.x, fmaf(-z.y, e.y, re));
+            im = fmaf(z.y, e.x, fmaf(z.x, e.y, im));
+        }
+    }
+    return cmul(make_float2(re, im), tw[(n2 * k1) & (M - 1)], inv);
+}
+
+// Stage 2 for output k (k1 = k mod P, k2 = k / P) of component c from the
+// stage-1 values y [n2 P + k1][c].
+__device__ __forceinline__ float2 radix_stage2(const float2* y, int c, int k, int M, const float2* tw, bool inv) {
+    const int Q = M / kRadixP, k1 = k & (kRadixP - 1), k2 = k / kRadixP;
+    float re = 0.f, im = 0.f;
+    for (int n2 = 0; n2 < Q; ++n2) {
+        float2 e = tw[(kRadixP * n2 * k2) & (M - 1)];
+        if (inv) e.y = -e.y;
+        const float2 z = y[2 * (n2 * kRadixP + k1) + c];
+        re = fmaf(z.x, e.x, fmaf(-z.y, e.y, re));
+        im = fmaf(z.y, e.x, fmaf(z.x, e.y, im));
+    }
+    return make_float2(re, im);
+}
+
+// k_colour_rows in two stages: white numbers of row j of field b at step
+// step0 + q (blockIdx.y = q B + b), then their half spectrum.
+__global__ void k_colour_rows_r(int M, int B, uint32_t step0, uint32_t k0, uint32_t k1, float2* A) {
+    __shared__ float2 tw[kColourMaxM];
+    __shared__ float sw[2 * kColourMaxM];
+    __shared__ float2 sy[2 * kColourMaxM];
+    const int j = blockIdx.x, bq = blockIdx.y, t = threadIdx.x;
+    const int q = bq / B, b = bq - q * B;
+    twiddle_table(M, tw);
+    const uint32_t point = (uint32_t)(((size_t)b * M + j) * M + (t >> 1));
+    const uint4 r = dpd::philox4x32_10(make_uint4(point, (uint32_t)(t & 1), step0 + (uint32_t)q, 0u), k0, k1);
+    sw[t] = dpd::alpha_from_words(0, make_uint2(r.x, r.y));
+    __syncthreads();
+    const int idx = t >> 1, c = t & 1;
+    sy[t] = radix_stage1<true>(sw, c, idx, M, tw, false);
+    __syncthreads();
+    if (idx > M / 2) return;
+    A[(((size_t)bq * M + j) * M + idx) * 2 + c] = radix_stage2(sy, c, idx, M, tw, false);
+}
+
+// k_colour_cols in two stages: column k <= M / 2 of field bq, forward
+// transform, times Hhat, inverse transform (without its 1/M), in place.
+__global__ void k_colour_cols_r(int M, const float2* __restrict__ Hhat, float2* A) {
+    __shared__ float2 tw[kColourMaxM];
+    __shared__ float2 sa[2 * kColourMaxM], sy[2 * kColourMaxM];
+    const int k = blockIdx.x, bq = blockIdx.y, t = threadIdx.x;
+    const int idx = t >> 1, c = t & 1;
+    twiddle_table(M, tw);
+    float2* col = A + ((size_t)bq * M * M + k) * 2 + c;  // + 2 M row
+    sa[t] = col[(size_t)2 * M * idx];
+    __syncthreads();
+    sy[t] = radix_stage1<false>(sa, c, idx, M, tw, false);
+    __syncthreads();
+    sa[t] = cmul(radix_stage2(sy, c, idx, M, tw, false), Hhat[idx * M + k], false);  // l = idx
+    __syncthreads();
+    sy[t] = radix_stage1<false>(sa, c, idx, M, tw, true);
+    __syncthreads();
+    col[(size_t)2 * M * idx] = radix_stage2(sy, c, idx, M, tw, true);  // j = idx
+}
+
+// k_colour_noise in two stages: row j of field bq, the inverse row transform
+// of the Hermitian-extended half spectrum, real part over M^2, times s_c.
+__global__ void k_colour_noise_r(int M, const float2* __restrict__ A, float s0, float s1, float* noise) {
+    __shared__ float2 tw[kColourMaxM];
+    __shared__ float2 sa[2 * kColourMaxM], sy[2 * kColourMaxM];
+    const int j = blockIdx.x, bq = blockIdx.y, t = threadIdx.x;
+    const int idx = t >> 1, c = t & 1;
+    twiddle_table(M, tw);
+    {
+        const int kk = idx <= M / 2 ? idx : M - idx;
+        const float2 z = A[(((size_t)bq * M + j) * M + kk) * 2 + c];
+        sa[t] = idx <= M / 2 ? z : make_float2(z.x, -z.y);
+    }
+    __syncthreads();
+    sy[t] = radix_stage1<false>(sa, c, idx, M, tw, true);
+    __syncthreads();
+    const float re = radix_stage2(sy, c, idx, M, tw, true).x;  // i = idx
+    const float inv = 1.0f / (float)(M * M);
+    noise[(((size_t)bq * M + j) * M + idx) * 2 + c] = (c ? s1 : s0) * (re * inv);
+}
+
 // ---- field statistics ------------------------------------------------------------
 
 // Row transforms A[f][j][k][c] = sum_i u[f][j][i][c] e^{-2 pi i k i / M}
@@ -1565,12 +1678,12 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
                 const int q = (s - 1) % S;
                 if (q == 0) {
                     const int ns = std::min(S, steps - s + 1);
-                    if (noise_filter) {
-                        hipLaunchKernelGGL(k_colour_rows, dim3(n.p.M, B * ns), dim3(2 * n.p.M), 0, nn->stream,
+                    if (noise_filter) {  // M is 32 or 64: two-stage transforms
+                        hipLaunchKernelGGL(k_colour_rows_r, dim3(n.p.M, B * ns), dim3(2 * n.p.M), 0, nn->stream,
                                            n.p.M, B, (uint32_t)s, k0, k1, Aw);
-                        hipLaunchKernelGGL(k_colour_cols, dim3(n.p.M / 2 + 1, B * ns), dim3(2 * n.p.M), 0,
+                        hipLaunchKernelGGL(k_colour_cols_r, dim3(n.p.M / 2 + 1, B * ns), dim3(2 * n.p.M), 0,
                                            nn->stream, n.p.M, (const float2*)Hh, Aw);
-                        hipLaunchKernelGGL(k_colour_noise, dim3(n.p.M, B * ns), dim3(2 * n.p.M), 0,
+                        hipLaunchKernelGGL(k_colour_noise_r, dim3(n.p.M, B * ns), dim3(2 * n.p.M), 0,
                                            nn->stream, n.p.M, (const float2*)Aw, noise_std[0], noise_std[1],
                                            noise);
                     } else {
