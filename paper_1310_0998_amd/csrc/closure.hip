@@ -497,15 +497,20 @@ __device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
 // so each lane ends with four consecutive output channels of one pixel, and
 // writes them, ReLU and BF16 applied, as one 8-byte store into sout
 // (kBandXS elements per pixel).
-template <int M, int CIN, int NCT>
-__device__ __forceinline__ void band_layer(int rows_out, const unsigned short* sin, unsigned short* sout,
+template <int M, int CIN, int NCT, int ROWS>
+__device__ __forceinline__ void band_layer(const unsigned short* sin, unsigned short* sout,
                                            const BandW<NCT, (9 * CIN + 31) / 32>& W) {
     constexpr int NK = (9 * CIN + 31) / 32;
     constexpr int XSI = CIN == 4 ? 4 : kBandXS;
+    constexpr int ntile = ROWS * M / 16, trips = (ntile + kBandWaves - 1) / kBandWaves;
     const int wave = threadIdx.x / kWaveN, lane = threadIdx.x & (kWaveN - 1);
     const int r16 = lane & 15, g = lane >> 4;
-    const int ntile = rows_out * M / 16;
-    for (int t = wave; t < ntile; t += kBandWaves) {
+    // a known trip count, unrolled by two: the loads of one tile can overlap
+    // the matrix-core work of the one before
+#pragma unroll 2
+    for (int j = 0; j < trips; ++j) {
+        const int t = wave + kBandWaves * j;
+        if (ntile % kBandWaves != 0 && t >= ntile) break;
         const int lp = t * 16 + r16;  // this lane's pixel
         const int ly = lp / M, x = lp - ly * M;
         const int xs[3] = {x == 0 ? M - 1 : x - 1, x, x == M - 1 ? 0 : x + 1};
@@ -611,9 +616,10 @@ __global__ __launch_bounds__(kBandWaves * kWaveN) void k_net_band(BandNet net,
     __shared__ __align__(16) unsigned short sb[L >= 3 ? (R + 2 * (L - 2)) * M * kBandXS : 8];
     const int b = blockIdx.x / bands, y0 = (blockIdx.x - b * bands) * R;
     const size_t pix0 = (size_t)b * M2 + (size_t)y0 * M;
-    // the last layer's u and noise, loaded now (lanes of group 0)
+    // the last layer's u and noise (lanes of group 0), loaded a layer or more
+    // ahead of it
     float2 ul[kLastTPW], nl[kLastTPW];
-    {
+    auto load_last = [&]() {
         const int wave = threadIdx.x / kWaveN, lane = threadIdx.x & (kWaveN - 1);
 #pragma unroll
         for (int j = 0; j < kLastTPW; ++j) {
@@ -624,7 +630,7 @@ __global__ __launch_bounds__(kBandWaves * kWaveN) void k_net_band(BandNet net,
                 nl[j] = *reinterpret_cast<const float2*>(out.noise + 2 * p);
             }
         }
-    }
+    };
     BandW<2, 2> w0;
     band_weights(w0, net.wf[0], net.kpad[0], net.bias[0], net.cout[0]);
     constexpr int npx = (R + 2 * L) * M;
@@ -639,33 +645,42 @@ __global__ __launch_bounds__(kBandWaves * kWaveN) void k_net_band(BandNet net,
     if constexpr (L == 2) {
         BandW<1, 9> w1;
         band_weights(w1, net.wf[1], net.kpad[1], net.bias[1], net.cout[1]);
+        load_last();
         __syncthreads();
-        band_layer<M, 4, 2>(R + 2, sx, sa, w0);
+        band_layer<M, 4, 2, R + 2>(sx, sa, w0);
         __syncthreads();
         band_last<M>(sa, w1, pix0, ul, nl, out);
+    } else if constexpr (L == 3) {
+        BandW<2, 9> w1;
+        band_weights(w1, net.wf[1], net.kpad[1], net.bias[1], net.cout[1]);
+        load_last();
+        __syncthreads();
+        band_layer<M, 4, 2, R + 4>(sx, sa, w0);
+        __syncthreads();
+        BandW<1, 9> w2;
+        band_weights(w2, net.wf[2], net.kpad[2], net.bias[2], net.cout[2]);
+        band_layer<M, 32, 2, R + 2>(sa, sb, w1);
+        __syncthreads();
+        band_last<M>(sb, w2, pix0, ul, nl, out);
     } else {
+        // registers: the weights of the next layer are loaded while the
+        // current one runs, except during layer 1, where two tiles' operands
+        // and both 32-channel weight sets would not fit
         BandW<2, 9> w1;
         band_weights(w1, net.wf[1], net.kpad[1], net.bias[1], net.cout[1]);
         __syncthreads();
-        band_layer<M, 4, 2>(R + 2 * (L - 1), sx, sa, w0);
+        band_layer<M, 4, 2, R + 6>(sx, sa, w0);
         __syncthreads();
-        if constexpr (L == 3) {
-            BandW<1, 9> w2;
-            band_weights(w2, net.wf[2], net.kpad[2], net.bias[2], net.cout[2]);
-            band_layer<M, 32, 2>(R + 2, sa, sb, w1);
-            __syncthreads();
-            band_last<M>(sb, w2, pix0, ul, nl, out);
-        } else {
-            BandW<2, 9> w2;
-            band_weights(w2, net.wf[2], net.kpad[2], net.bias[2], net.cout[2]);
-            band_layer<M, 32, 2>(R + 4, sa, sb, w1);
-            __syncthreads();
-            BandW<1, 9> w3;
-            band_weights(w3, net.wf[3], net.kpad[3], net.bias[3], net.cout[3]);
-            band_layer<M, 32, 2>(R + 2, sb, sa, w2);
-            __syncthreads();
-            band_last<M>(sa, w3, pix0, ul, nl, out);
-        }
+        band_layer<M, 32, 2, R + 4>(sa, sb, w1);
+        BandW<2, 9> w2;
+        band_weights(w2, net.wf[2], net.kpad[2], net.bias[2], net.cout[2]);
+        __syncthreads();
+        BandW<1, 9> w3;
+        band_weights(w3, net.wf[3], net.kpad[3], net.bias[3], net.cout[3]);
+        load_last();
+        band_layer<M, 32, 2, R + 2>(sb, sa, w2);
+        __syncthreads();
+        band_last<M>(sa, w3, pix0, ul, nl, out);
     }
 }
 
