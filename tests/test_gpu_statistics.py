@@ -124,6 +124,61 @@ def test_energy_spectrum_and_correlation_length_match_oracle():
     assert not bad, bad
 
 
+def test_transient_4m_statistics_match_oracle():
+    """The 4M-particle workload over t <= 10 from its random start (PROTOCOL_4M:
+    seeds 301-304, u_M on 256 x 256 every 20 steps): band energies and the
+    integral length of the gridded field's correlation per 400-step window,
+    against the oracle's stored values (stats_dimers_4M_transient.json,
+    written by make_stats_golden_4m.py from the oracle alone), within
+    max(2 %, 3 sigma) of the combined standard error over the four seeds.
+    Both sides start from the same states and draw the same noise, so the
+    per-seed differences are printed as well."""
+    import torch
+
+    from paper_1310_0998_amd import dpd
+    from stats_protocol import PROTOCOL_4M, WindowAccumulator, window_ensemble
+
+    path = os.path.join(HERE, "golden", "stats_dimers_4M_transient.json")
+    if not os.path.exists(path):
+        pytest.skip("stats_dimers_4M_transient.json not written")
+    with open(path) as f:
+        ref = json.load(f)
+    P = PROTOCOL_4M
+    assert ref["protocol"] == json.loads(json.dumps(P))
+    per_seed = []
+    for seed in P["seeds"]:
+        cfg = dict(inputs.physics(inputs.WORKLOADS[P["workload"]]), seed=seed, bin_M_max=P["M"])
+        x, v = inputs.initial_state(cfg)
+        sim = dpd.Sim(cfg, device="cuda:0")
+        sim.set_state(torch.from_numpy(x).cuda(), torch.from_numpy(v).cuda(), 0)
+        acc = WindowAccumulator(cfg["L"])
+        for _ in range(P["steps"] // P["every"]):
+            sim.step(P["every"])
+            u, _ = sim.bin_velocity(P["M"], 0.0, 0)
+            acc.add(u.cpu().numpy())
+        sim.close()
+        per_seed.append(acc.result())
+    gpu = window_ensemble(per_seed)
+    bad = []
+    nw = P["steps"] // P["window"]
+    for w in range(nw):
+        rows = [(f"w{w} E {a}-{b}", gpu["E_bands"][w][i], gpu["E_bands_sem"][w][i], ref["E_bands"][w][i],
+                 ref["E_bands_sem"][w][i],
+                 max(abs(s["E_bands"][w][i] / o["E_bands"][w][i] - 1) for s, o in zip(per_seed, ref["per_seed"])))
+                for i, (a, b) in enumerate(P["bands"])]
+        rows.append((f"w{w} L_gv", gpu["L_gv"][w], gpu["L_gv_sem"][w], ref["L_gv"][w], ref["L_gv_sem"][w],
+                     max(abs(s["L_gv"][w] / o["L_gv"][w] - 1) for s, o in zip(per_seed, ref["per_seed"]))))
+        for name, gv, gs, o, os_, seedmax in rows:
+            sig = np.hypot(gs, os_) / abs(o)
+            tol = max(0.02, 3.0 * sig)
+            dev = abs(gv - o) / abs(o)
+            print(f"{name:12s} gpu {gv:.5g}  oracle {o:.5g}  diff {100 * dev:.3f} %  sigma {100 * sig:.2f} %  "
+                  f"tolerance {100 * tol:.2f} %  largest per-seed diff {100 * seedmax:.3f} %")
+            if dev > tol:
+                bad.append(name)
+    assert not bad, bad
+
+
 @pytest.mark.parametrize("n_agents,L,kind", [(800, 40.0, "random"), (420, 29.25, "edge"),
                                              (3000, 60.0, "random")])
 def test_agent_vcf_matches_oracle_pair_loop(n_agents, L, kind):

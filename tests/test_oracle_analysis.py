@@ -138,3 +138,32 @@ def test_stats_protocol_helpers_match_oracle_routines():
     got = band_energies_batch(u)
     for f in range(3):
         assert np.allclose(got[f], band_energies(analysis.energy_spectrum(u[f])), rtol=1e-13)
+
+
+def test_transient_window_accumulator():
+    # the 4M protocol's windows: snapshots of window w scaled by (w + 1) give
+    # (w + 1)^2 times one snapshot's band energies in that window and the same
+    # correlation length (the normalised correlation is scale-free); the
+    # ensemble's standard error is the spread over seeds / sqrt(seeds)
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    from stats_protocol import PROTOCOL_4M, WindowAccumulator, band_energies_of, window_ensemble
+    rng = np.random.default_rng(22)
+    M, L = 32, 250.0
+    u = rng.normal(size=(M, M, 2)) + 0.1
+    acc = WindowAccumulator(L)
+    k = PROTOCOL_4M["window"] // PROTOCOL_4M["every"]
+    nw = PROTOCOL_4M["steps"] // PROTOCOL_4M["window"]
+    for n in range(k * nw):
+        acc.add((n // k + 1) * u)
+    res = acc.result()
+    E1 = band_energies_of(analysis.energy_spectrum(u), PROTOCOL_4M["bands"])
+    r, g = analysis.vcf_grid(u, L, L / PROTOCOL_4M["M"])
+    L1 = analysis.integral_length(r, g, L)
+    for w in range(nw):
+        assert np.allclose(res["E_bands"][w], (w + 1) ** 2 * E1, rtol=1e-12)
+        assert res["L_gv"][w] == pytest.approx(L1, rel=1e-12)
+    e = window_ensemble([res, dict(res, E_bands=(2 * np.array(res["E_bands"])).tolist())])
+    assert np.allclose(e["E_bands"], 1.5 * np.array(res["E_bands"]))
+    assert np.allclose(e["E_bands_sem"], np.abs(np.array(res["E_bands"])) * np.sqrt(0.5) / np.sqrt(2))
