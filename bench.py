@@ -293,6 +293,7 @@ def run_grid200k(args):
     K = 50
     red_every = 100 if steps % 100 == 0 else 0
     points = []
+    finals = []
     t_total = 0.0
     n_total = 0
     for k, (g, z) in enumerate(inputs.GAMMA_ZETA_GRID_200K):
@@ -311,6 +312,8 @@ def run_grid200k(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         sim.sync()
+        xs_, vs_, _, _ = sim.get_state()
+        finals.append((xs_.cpu().numpy(), vs_.cpu().numpy()))
         sim.set_graph_chunk(0)
         sim.set_profiling(True)
         sim.step(200)
@@ -328,6 +331,37 @@ def run_grid200k(args):
         n_total += N * steps
         log(f"gamma={g} zeta={z}: {p['ms_per_step']:.4f} ms/step, pair kernel {avg_us:.2f} us, "
             f"{p['pair_kernel_GBps_alg']:.0f} GB/s (32 B/particle)")
+    # the same nine points as the replicas of one batch: one launch per step
+    # kernel for 1.8 M particles instead of nine launch-latency-bound systems;
+    # every replica must end bitwise where its own run ended
+    import numpy as np
+    cfgs = [dict(base, gamma=g, gamma_s=z, seed=201 + k) for k, (g, z) in enumerate(inputs.GAMMA_ZETA_GRID_200K)]
+    sts = [inputs.initial_state(c) for c in cfgs]
+    xb = np.concatenate([st[0] for st in sts])
+    vb = np.concatenate([st[1] for st in sts])
+    bat = dpd.Sim(cfgs, device=dev)
+    bat.set_state(torch.from_numpy(xb).to(dev), torch.from_numpy(vb).to(dev), 0)
+    bat.set_graph_chunk(K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if red_every:
+        bat.step(steps, reduce_every=red_every)
+    else:
+        bat.step(steps)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    bat.sync()
+    xe, ve, _, _ = bat.get_state()
+    xe, ve = xe.cpu().numpy(), ve.cpu().numpy()
+    bat.close()
+    off = np.cumsum([0] + [len(st[0]) for st in sts])
+    equal = all(np.array_equal(xe[off[q]:off[q + 1]], finals[q][0]) and np.array_equal(ve[off[q]:off[q + 1]], finals[q][1])
+                for q in range(len(cfgs)))
+    batched = {"ms_per_step": 1e3 * t_bat / steps, "particle_steps_per_s": len(xb) * steps / t_bat,
+               "speedup_vs_points": t_total / t_bat, "bitwise_equal_to_points": bool(equal)}
+    log(f"the nine points as one batch: {batched['ms_per_step']:.4f} ms/step, "
+        f"{batched['particle_steps_per_s']:.3e} particle-steps/s, {batched['speedup_vs_points']:.2f}x, "
+        f"bitwise equal: {equal}")
     line = {
         "metric": "200k grid: particle-steps/s over the gamma x zeta grid; pair kernel GB/s",
         "value": n_total / t_total,
@@ -350,6 +384,7 @@ def run_grid200k(args):
             "parallelism": "single-gpu",
         },
         "points": points,
+        "batched": batched,
         "pair_kernel_GBps_alg_mean": sum(p["pair_kernel_GBps_alg"] for p in points) / len(points),
         "cache_note": "working set about 12 MB: L2 / Infinity-Cache resident, not an HBM figure",
         "cpu_baseline": None,
