@@ -41,10 +41,11 @@ def log(*a):
 
 
 def pair_pass_bytes(n_particles: int, n_cells: int) -> int:
-    """Algorithmic HBM bytes of one pair-force pass as the hot-path survey
-    counts them: per particle the sorted x (8), u (8) and id (4) read and the
+    """Algorithmic HBM bytes of one pair-force pass (Eqs. 2.2-2.4 over the
+    sorted state): per particle the sorted x (8), u (8) and id (4) read and the
     force (8) written, plus cell_start (4 per cell, n_cells + 1 entries);
-    32 B per particle at one particle per cell."""
+    32 B per particle at one particle per cell.  Halo re-reads are the
+    implementation's, not the pass's."""
     return n_particles * (8 + 8 + 4 + 8) + 4 * (n_cells + 1)
 
 
