@@ -100,8 +100,9 @@ int dpd_nn_train_step(dpd_nn* nn, const float* u, const float* cond, const float
  * in stream order.  For c_in = 4, width 32, 2 to 4 layers and M in {32, 64}
  * a step is one kernel (the whole network on bands of rows in LDS, the noise
  * added in its last layer) and the noise of up to 8 steps is drawn ahead, in
- * the workspace's gradient buffers; the results are those of the
- * layer-by-layer network plus the same noise.  Errors: DPD_EINVAL, DPD_EHIP. */
+ * the workspace's gradient buffers (filtered noise through two-stage
+ * transforms); the network's part of every step is bitwise that of the
+ * layer-by-layer kernels.  Errors: DPD_EINVAL, DPD_EHIP. */
 int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, int32_t steps,
                    const float* noise_std, const float* noise_filter, uint64_t seed,
                    int32_t save_every, float* traj);
