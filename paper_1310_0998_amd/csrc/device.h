@@ -15,6 +15,7 @@ constexpr unsigned kStatusNonFinite = 1u;
 constexpr unsigned kStatusBond = 2u;
 constexpr unsigned kStatusRange = 4u;
 constexpr unsigned kStatusBinning = 8u;  // cell counts inconsistent with N (internal error)
+constexpr unsigned kStatusScan = 16u;    // the cell scan's look-back waited too long (internal error)
 
 // Everything a kernel needs to know about the model, by value.
 struct DevParams {

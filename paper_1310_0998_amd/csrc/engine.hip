@@ -39,8 +39,8 @@ struct Layout {
     size_t off_Sx, off_Sv, off_SF, off_Sid;
     size_t off_Ax, off_Au, off_Aid, off_Bx, off_Bu, off_Bid;
     size_t off_key, off_rank, off_src, off_count, off_cs;
-    size_t off_scan_part, off_red, off_Fs, off_binacc, off_status, off_ovf;
-    size_t off_count2, off_xref, off_rec, off_flags;  // Verlet skin
+    size_t off_scan, off_red, off_Fs, off_binacc, off_status, off_ovf;
+    size_t off_count2, off_xref, off_rec, off_flags;  // second counter array; Verlet skin
     size_t off_reps, off_tile_rep, off_stepb;         // batch tables, graph step
     size_t off_Tx, off_Tv, off_TF, off_Tid;           // state saved by the tuner
     size_t off_posid;                                 // input index by id (far bonds)
@@ -308,24 +308,24 @@ int derive(const dpd_params* p, int n_rep, Derived* d, std::string* err) {
     L.off_rank = take(N * 4);
     L.off_src = take(N * 4);
     L.off_count = take(C * 4);
+    L.off_count2 = take(C * 4);
     L.off_cs = take((C + 1) * 4);
     L.off_red = take((T + kRedParts) * 3 * 8);  // per tile, then per part
     L.off_Fs = take(N * 8);
     L.off_binacc = take((size_t)d->bin_M_max * d->bin_M_max * 3 * 8);
     L.off_status = take(16);
     L.off_ovf = take((T + 1) * 4);
-    L.off_scan_part = take((size_t)d->n_scan_blocks * 4);
+    L.off_scan = take(((size_t)d->n_scan_blocks + 1) * 8);  // chunk descriptors, ticket counter
     L.off_flags = take(64);  // two displacement flags (by step parity), rebuild count
     L.off_stepb = take(64);
     L.off_reps = take((size_t)n_rep * sizeof(DevParams));
     L.off_tile_rep = take(n_rep > 1 ? T * 4 : 4);
     if (d->skin) {
-        L.off_count2 = take(C * 4);
         L.off_xref = take(N * 8);
         L.off_rec = take(T * kRecStride);
         L.off_Tx = L.off_Tv = L.off_TF = L.off_Tid = 0;
     } else {
-        L.off_count2 = L.off_xref = L.off_rec = 0;
+        L.off_xref = L.off_rec = 0;
         L.off_Tx = take(N * 8);
         L.off_Tv = take(N * 8);
         L.off_TF = take(N * 8);
@@ -358,8 +358,9 @@ struct dpd_handle {
     int* Tid;
     unsigned* status;
     int* ovf;  // [0]: count of tiles left to the overflow kernel, then their indices
-    int* scan_part;
-    // Verlet skin: second counter array, rebuild positions, tile records, flags
+    unsigned long long* scan_desc;  // per chunk of the cell scan, then its ticket counter
+    // second counter array (see counter_of); Verlet skin: rebuild positions,
+    // tile records, flags
     int* count2;
     float2* xref;
     unsigned char* rec;
@@ -445,14 +446,13 @@ int upload_tables(dpd_handle* h) {
 // members by id itself.  With id_of_input != NULL every cell is also ordered by
 // id here (only for the state loaded with a given force, which no pair kernel
 // passes through before it is stored).
-int bin_from_counts(dpd_handle* h, int* count, const int* rebuild, int* moved_clear,
+int bin_from_counts(dpd_handle* h, int* count, bool clear, const int* rebuild, int* moved_clear,
                     const int* id_of_input, const int* ids_in) {
     const int G = h->d.n_scan_blocks;
     const int C = (int)h->d.cells, N = (int)h->d.N;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(G), dim3(kBlock), 0, h->stream, (const int*)count, C,
-                       h->scan_part, rebuild, moved_clear, h->flags + 2);
-    hipLaunchKernelGGL(k_scan_final, dim3(G), dim3(kBlock), 0, h->stream, count, C,
-                       (const int*)h->scan_part, h->cs, h->ovf, rebuild);
+    hipLaunchKernelGGL(k_scan, dim3(G), dim3(kScanThreads), 0, h->stream, count, C, clear ? 1 : 0,
+                       h->cs, h->scan_desc,
+                       h->scan_desc + G, h->status, h->ovf, rebuild, moved_clear, h->flags + 2);
     hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(N), 4096)), dim3(kBlock), 0, h->stream,
                        N, (const int*)h->key, (const int*)h->rank, (const int*)h->cs, h->src,
                        rebuild);
@@ -467,11 +467,20 @@ int bin_from_counts(dpd_handle* h, int* count, const int* rebuild, int* moved_cl
     return DPD_OK;
 }
 
-// Per-cell counter array of step s (with a Verlet skin the two arrays alternate
-// by step parity: step s fills the one for the keys of x_{s+1} while the other,
-// consumed by the binning of step s, is cleared tile by tile).
+// Per-cell counter array of step s.  With a Verlet skin the two arrays
+// alternate by step parity: step s fills the one for the keys of x_{s+1} while
+// the other, consumed by the binning of step s, is cleared tile by tile.
 int* counter_of(dpd_handle* h, int64_t s) {
-    return (h->count2 && (s & 1)) ? h->count2 : h->count;
+    return (s & 1) ? h->count2 : h->count;
+}
+
+// Without a skin each array belongs to one of the ping-pong position buffers:
+// the launch that writes positions into A fills `count`, into B `count2`.  A
+// step's binning consumes the array of its input buffer without clearing it;
+// its pair launch clears that array tile by tile while it fills the other.
+// Whenever no step is prepared both arrays are zero.
+int* counter_of_buffer(dpd_handle* h, const float2* x) {
+    return x == h->Ax ? h->count : h->count2;
 }
 
 template <int MODE, bool SKIN, bool BATCH>
@@ -598,6 +607,8 @@ int read_status(dpd_handle* h) {
         return fail(h, DPD_ERANGE, "a velocity exceeded the range of the binned field");
     if (st[0] & kStatusBinning)
         return fail(h, DPD_EHIP, "internal error: cell counts inconsistent with the particle count");
+    if (st[0] & kStatusScan)
+        return fail(h, DPD_EHIP, "internal error: the cell scan waited too long for a chunk's sum");
     return DPD_OK;
 }
 
@@ -607,8 +618,7 @@ int unprepare(dpd_handle* h) {
     if (!h->prepared) return DPD_OK;
     const long long C = h->d.cells;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, h->count, 0, C);
-    if (h->count2)
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, h->count2, 0, C);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, h->count2, 0, C);
     LAUNCHCHK(h);
     h->prepared = false;
     return DPD_OK;
@@ -617,7 +627,7 @@ int unprepare(dpd_handle* h) {
 // First half kick and drift of a dpd_step call from the stored state, into the
 // A buffers (with a skin this step rebuilds).
 int kick_drift(dpd_handle* h) {
-    int* count = counter_of(h, h->step);
+    int* count = h->d.skin ? counter_of(h, h->step) : counter_of_buffer(h, h->Ax);
     for (const Rep& r : h->d.reps) {
         const DevParams& P = r.P;
         const size_t pb = (size_t)P.pbase;
@@ -654,13 +664,16 @@ PairArgs step_args(dpd_handle* h, int64_t k, bool last, float2* inx, float2* inu
     a.step = (uint32_t)((uint64_t)s & 0xffffffffu);
     a.keyout = h->key;
     a.rankout = h->rank;
-    a.count = counter_of(h, s);
     if (h->d.skin) {
+        a.count = counter_of(h, s);
         a.rebuild = h->flags + ((s - 1) & 1);
         a.rec = h->rec;
         a.xref = h->xref;
         a.moved = h->flags + (s & 1);
         a.count_clear = counter_of(h, s - 1);
+    } else {
+        a.count = counter_of_buffer(h, outx);
+        a.count_clear = counter_of_buffer(h, inx);
     }
     if (last) {
         a.xout = h->Sx;
@@ -694,7 +707,8 @@ int run_steps(dpd_handle* h, int64_t n, int reduce_every, double* pk_out, int64_
         const int64_t s = h->step + k;
         const int* rebuild = h->d.skin ? h->flags + ((s - 1) & 1) : nullptr;
         int* moved = h->d.skin ? h->flags + (s & 1) : nullptr;
-        int rc = bin_from_counts(h, counter_of(h, s - 1), rebuild, moved, nullptr, inid);
+        int* counts = h->d.skin ? counter_of(h, s - 1) : counter_of_buffer(h, inx);
+        int rc = bin_from_counts(h, counts, h->d.skin, rebuild, moved, nullptr, inid);
         if (rc) return rc;
         const bool last = (k == n);
         const bool red = pk_out && reduce_every > 0 && ((k0 + k) % reduce_every == 0);
@@ -736,7 +750,7 @@ int capture_chunk(dpd_handle* h, int K, bool reduce_last, hipGraphExec_t* out) {
     float2 *inx = h->Ax, *inu = h->Au, *outx = h->Bx, *outu = h->Bu;
     int *inid = h->Aid, *outid = h->Bid;
     for (int k = 1; k <= K && rc == DPD_OK; ++k) {
-        rc = bin_from_counts(h, h->count, nullptr, nullptr, nullptr, inid);
+        rc = bin_from_counts(h, counter_of_buffer(h, inx), false, nullptr, nullptr, nullptr, inid);
         if (rc) break;
         const bool last = (k == K);
         PairArgs a = step_args(h, k, last, inx, inu, inid, outx, outu, outid);
@@ -898,12 +912,12 @@ int dpd_create_batch(const dpd_params* p, int32_t n_rep, void* workspace, size_t
         h->binacc = (long long*)(w + L.off_binacc);
         h->status = (unsigned*)(w + L.off_status);
         h->ovf = (int*)(w + L.off_ovf);
-        h->scan_part = (int*)(w + L.off_scan_part);
+        h->scan_desc = (unsigned long long*)(w + L.off_scan);
         h->flags = (int*)(w + L.off_flags);
         h->stepb = (unsigned*)(w + L.off_stepb);
         h->reps_dev = (DevParams*)(w + L.off_reps);
         h->tile_rep = (int*)(w + L.off_tile_rep);
-        h->count2 = d.skin ? (int*)(w + L.off_count2) : nullptr;
+        h->count2 = (int*)(w + L.off_count2);
         h->xref = d.skin ? (float2*)(w + L.off_xref) : nullptr;
         h->rec = d.skin ? (unsigned char*)(w + L.off_rec) : nullptr;
         h->Tx = d.skin ? nullptr : (float2*)(w + L.off_Tx);
@@ -928,11 +942,14 @@ int dpd_create_batch(const dpd_params* p, int32_t n_rep, void* workspace, size_t
         // clear the counters the kernels rely on
         const long long C = d.cells;
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, h->count, 0, C);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, h->count2, 0, C);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, (int*)h->status, 0, 4LL);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, h->ovf, 0, 1LL);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, h->flags, 0, 16LL);
+        const long long scan_words = 2LL * (d.n_scan_blocks + 1);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(scan_words)), dim3(kBlock), 0, h->stream,
+                           (int*)h->scan_desc, 0, scan_words);
         if (d.skin) {
-            hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, h->count2, 0, C);
             // no tile record is valid before the first rebuild
             const long long words = d.tiles_alloc * (long long)(kRecStride / 4);
             hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(words)), dim3(kBlock), 0, h->stream,
@@ -989,7 +1006,7 @@ int dpd_set_state(dpd_handle* h, const float* x, const float* v, int64_t step, c
                                h->Aid + pb, h->key + pb, h->rank + pb, h->count, h->status);
         }
         LAUNCHCHK(h);
-        int rc = bin_from_counts(h, h->count, nullptr, nullptr, F ? h->Aid : nullptr, h->Aid);
+        int rc = bin_from_counts(h, h->count, true, nullptr, nullptr, F ? h->Aid : nullptr, h->Aid);
         if (rc) return rc;
         if (F) {
             for (const Rep& r : h->d.reps) {
@@ -1100,7 +1117,7 @@ int dpd_forces(dpd_handle* h, float* F_out) {
                                (const float2*)h->Sx + pb, h->key + pb, h->rank + pb, h->count);
         }
         LAUNCHCHK(h);
-        int rc = bin_from_counts(h, h->count, nullptr, nullptr, nullptr, h->Sid);
+        int rc = bin_from_counts(h, h->count, true, nullptr, nullptr, nullptr, h->Sid);
         if (rc) return rc;
         PairArgs a = {};
         a.cs = h->cs;

@@ -76,7 +76,8 @@ struct PairArgs {
     unsigned char* rec; // tile records, kRecStride bytes each
     float2* xref;       // position of every slot at the last rebuild
     int* moved;         // set when a particle has moved more than skin / 2 since then
-    int* count_clear;   // the other per-cell counter array, cleared cell by cell
+    int* count_clear;   // STEP: the counter array this step's binning consumed, cleared
+                        // tile by tile (null: none)
     uint32_t step;      // step number of the force evaluation (mod 2^32), or its
                         // offset from *step_base when that is set
     const uint32_t* step_base;  // null, or the step before a replayed graph chunk
@@ -523,9 +524,9 @@ __device__ __forceinline__ bool pair_tile(DevParams P, PairArgs a, int reduce, i
     const bool rebuild = !SKIN || (MODE == MODE_FORCES) || a.rebuild == nullptr || *a.rebuild != 0;
     const bool keep_list = SKIN && MODE != MODE_FORCES;
     TileRec* R = SKIN ? reinterpret_cast<TileRec*>(a.rec + (size_t)tile * kRecStride) : nullptr;
-    if (SKIN && a.count_clear) {  // the counters this step does not fill: this tile's cells
-        const int row = lane >> 3, col = lane & 7;
-        if (col < tw && row < th) a.count_clear[(cy0 + row) * P.nc + cx0 + col] = 0;
+    if (a.count_clear) {  // the counters this step's binning consumed: this tile's cells
+        const int row = lane >> 3, col = lane & 7;  // tile sides <= kTileMax = 8
+        if (col < tw && row < th) a.count_clear[P.cbase + (cy0 + row) * P.nc + cx0 + col] = 0;
     }
 
     int ntile = 0, E = 0;
@@ -1110,97 +1111,214 @@ __global__ void k_key_rank(DevParams P, const float2* __restrict__ x, int* key, 
     rank[i] = atomicAdd(&count[k], 1);
 }
 
-// Exclusive scan of the per-cell counts -> cell_start, in two passes over
-// chunks of kScanTile cells: k_scan_reduce writes each chunk's sum; in
-// k_scan_final every block adds up the sums of the chunks before its own (a few
-// KB read from L2, in a fixed order), scans its chunk and clears the counts for
-// the next binning.  The last block writes the grand total to cell_start[n].
-// k_scan_final also clears the pair kernel's tile overflow counter (the
-// previous pair launch has finished).
-constexpr int kScanPer = 8;
-constexpr int kScanTile = kBlock * kScanPer;  // cells per chunk
+// Exclusive scan of the per-cell counts -> cell_start in one pass over chunks
+// of kScanTile cells (decoupled look-back: Merrill & Garland, "Single-pass
+// parallel prefix scan with decoupled look-back", NVIDIA tech. report 2016).
+// Each block draws a ticket from a counter, so the chunks are taken in order
+// and a block only ever waits for chunks taken before its own, whose blocks are
+// already running.  A block publishes its chunk's sum at once, then its
+// prefix: it adds up the sums published to its left until it meets a chunk
+// whose inclusive prefix is known, publishes its own inclusive prefix and
+// writes its cell_start values.  The last block writes the grand total to
+// cell_start[n] and resets the ticket counter.  With `clear` the block also
+// zeroes its counts for the next binning (the stepping path leaves that to the
+// pair kernel, tile by tile).
+//
+// A chunk is kScanRows rows of kScanThreads groups of 4 cells in row-major
+// order, thread t holding group t of every row: each load and store of a
+// wavefront covers 1 KB of consecutive cells.  The chunks are large (a few
+// hundred for millions of cells, about one per compute unit) and one
+// wavefront reads kScanWindow descriptors per round of the look-back: the
+// blocks run side by side and publish their sums at about the same time, so a
+// round that reaches back over every earlier chunk at once keeps the look-back
+// to one round trip.
+//
+// A descriptor is one 64-bit word, written and read whole: bits 0-31 the
+// value, bit 32 set when the value is the inclusive prefix (clear: the chunk's
+// own sum), bits 33-63 the launch's epoch.  A descriptor of another epoch is
+// not yet written in this launch, so no descriptor is ever cleared; the
+// counter word holds the epoch in its high half and the next ticket in its
+// low half (all zero at creation: the first launch has epoch 1).  The sums are
+// exact integers, so the result is the same as any other order of addition.
+// A look-back that waits past kScanSpin polls sets kStatusScan and goes on,
+// which ends the kernel in any case.
+//
+// The launch also clears the pair kernel's tile overflow counter and, with a
+// Verlet skin, the displacement flag the coming pair launch sets
+// (`moved_clear`) and counts the rebuilds; the scan itself runs only on
+// rebuild steps (`rebuild` null: always).
+constexpr int kScanThreads = 1024;
+constexpr int kScanRows = 4;
+constexpr int kScanTile = kScanThreads * 4 * kScanRows;  // cells per chunk
+constexpr int kScanLook = 4;                             // descriptors per lane and round
+constexpr int kScanWindow = kWave * kScanLook;           // chunks per round of the look-back
+constexpr int kScanSpin = 1 << 20;
 
-// With a Verlet skin the binning kernels run only on rebuild steps: `rebuild`
-// (null: always) says whether this one is; k_scan_reduce also clears the flag
-// the coming pair launch will set (`moved_clear`) and counts the rebuilds.
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ count, int n,
-                                                        int* partial, const int* rebuild,
-                                                        int* moved_clear, int* rebuilds) {
-    __shared__ int s_wave[kBlock / kWave];
-    if (moved_clear && blockIdx.x == 0 && threadIdx.x == 0) {
-        *moved_clear = 0;
-        if (rebuild && *rebuild) atomicAdd(rebuilds, 1);
-    }
-    if (rebuild && *rebuild == 0) return;
-    const int base = blockIdx.x * kScanTile;
-    int s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        const int idx = base + k * kBlock + threadIdx.x;
-        if (idx < n) s += count[idx];
-    }
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kWave);
-    if (lane == 0) s_wave[w] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = ((s_wave[0] + s_wave[1]) + s_wave[2]) + s_wave[3];
+__device__ __forceinline__ uint64_t scan_desc(uint32_t epoch, bool inclusive, uint32_t v) {
+    return ((uint64_t)(epoch & 0x7FFFFFFFu) << 33) | ((uint64_t)inclusive << 32) | v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_final(int* count, int n, const int* __restrict__ partial,
-                                                       int* cs, int* ovf_count, const int* rebuild) {
-    __shared__ int s_v[kScanTile + kScanTile / 32];
-    __shared__ int s_tsum[2 * kBlock + 1];
-    __shared__ int s_wave[kBlock / kWave];
-    __shared__ int s_red[kBlock / kWave];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *ovf_count = 0;
-    if (rebuild && *rebuild == 0) return;
-    // sum of the chunks before this one
-    int before = 0;
-    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kBlock) before += partial[k];
-    {
-        const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) before += __shfl_down(before, o, kWave);
-        if (lane == 0) s_red[w] = before;
-    }
-    const int base = blockIdx.x * kScanTile;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        const int li = k * kBlock + threadIdx.x;
-        const int idx = base + li;
-        s_v[li + (li >> 5)] = (idx < n) ? count[idx] : 0;
-    }
-    __syncthreads();
-    const int prefix = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
-    int loc[kScanPer];
-    int sum = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        const int li = threadIdx.x * kScanPer + k;
-        loc[k] = sum;
-        sum += s_v[li + (li >> 5)];
-    }
-    s_tsum[threadIdx.x] = sum;
-    __syncthreads();
-    const int agg = block_scan_excl_512(s_tsum, kBlock, s_wave);
-    const int off = prefix + s_tsum[threadIdx.x];
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        const int li = threadIdx.x * kScanPer + k;
-        s_v[li + (li >> 5)] = off + loc[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        const int li = k * kBlock + threadIdx.x;
-        const int idx = base + li;
-        if (idx < n) {
-            cs[idx] = s_v[li + (li >> 5)];
-            count[idx] = 0;
+__global__ __launch_bounds__(kScanThreads) void k_scan(int* count, int n, int clear, int* cs,
+                                                       unsigned long long* desc,
+                                                       unsigned long long* ticket,
+                                                       unsigned* status, int* ovf_count,
+                                                       const int* rebuild, int* moved_clear,
+                                                       int* rebuilds) {
+    constexpr int kWaves = kScanThreads / kWave;
+    __shared__ int s_wave[kScanRows][kWaves];
+    __shared__ uint32_t s_ticket[2];
+    __shared__ int s_prefix;
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    if (blockIdx.x == 0 && t == 0) {
+        *ovf_count = 0;
+        if (moved_clear) {
+            *moved_clear = 0;
+            if (rebuild && *rebuild) atomicAdd(rebuilds, 1);
         }
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) cs[n] = prefix + agg;
+    if (rebuild && *rebuild == 0) return;
+    if (t == 0) {
+        const unsigned long long old = atomicAdd(ticket, 1ull);
+        s_ticket[0] = (uint32_t)old;
+        s_ticket[1] = (uint32_t)(old >> 32) + 1u;
+    }
+    __syncthreads();
+    const int chunk = (int)s_ticket[0];
+    const uint32_t epoch = s_ticket[1];
+    const uint32_t etag = epoch & 0x7FFFFFFFu;
+    if (chunk == (int)gridDim.x - 1 && t == 0)  // every ticket of this launch is taken
+        __hip_atomic_store(ticket, (unsigned long long)epoch << 32, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+
+    // group t of every row: 4 consecutive cells
+    const int base = chunk * kScanTile;
+    int4 v[kScanRows];
+#pragma unroll
+    for (int k = 0; k < kScanRows; ++k) {
+        const int c = base + (k * kScanThreads + t) * 4;
+        if (c + 4 <= n) {
+            v[k] = *reinterpret_cast<const int4*>(count + c);
+        } else {  // the ragged end: c + 3 >= n
+            v[k] = make_int4(c < n ? count[c] : 0, c + 1 < n ? count[c + 1] : 0,
+                             c + 2 < n ? count[c + 2] : 0, 0);
+        }
+    }
+    // exclusive prefix of every group within the chunk
+    int ex[kScanRows];
+#pragma unroll
+    for (int k = 0; k < kScanRows; ++k) {
+        const int g = (v[k].x + v[k].y) + (v[k].z + v[k].w);
+        int incl = g;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += y;
+        }
+        if (lane == kWave - 1) s_wave[k][w] = incl;
+        ex[k] = incl - g;
+    }
+    __syncthreads();
+    int agg = 0;
+#pragma unroll
+    for (int k = 0; k < kScanRows; ++k) {
+        int wofs = 0, row = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            wofs += (q < w) ? s_wave[k][q] : 0;
+            row += s_wave[k][q];
+        }
+        ex[k] += agg + wofs;
+        agg += row;
+    }
+
+    if (w == 0) {
+        if (lane == 0)
+            __hip_atomic_store(desc + chunk, scan_desc(epoch, chunk == 0, (uint32_t)agg),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t prefix = 0;
+        int p = chunk - 1;  // nearest chunk not yet added
+        bool timed_out = false;
+        while (p >= 0) {
+            // lane l looks at chunks p - kScanLook l - j, j = 0 .. kScanLook - 1
+            // (nearest first); left of chunk 0 reads as an inclusive 0
+            uint64_t d[kScanLook];
+#pragma unroll
+            for (int j = 0; j < kScanLook; ++j) {
+                const int q = p - kScanLook * lane - j;
+                d[j] = (q >= 0) ? __hip_atomic_load(desc + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : scan_desc(epoch, true, 0u);
+            }
+            for (int spin = 0;;) {  // poll the ones not yet written in this launch
+                bool ready = true;
+#pragma unroll
+                for (int j = 0; j < kScanLook; ++j) ready = ready && (uint32_t)(d[j] >> 33) == etag;
+                if (ready) break;
+                if (++spin >= kScanSpin) {
+                    timed_out = true;
+#pragma unroll
+                    for (int j = 0; j < kScanLook; ++j)
+                        if ((uint32_t)(d[j] >> 33) != etag) d[j] = scan_desc(epoch, true, 0u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int j = 0; j < kScanLook; ++j) {
+                    const int q = p - kScanLook * lane - j;
+                    if ((uint32_t)(d[j] >> 33) != etag)  // q >= 0 here
+                        d[j] = __hip_atomic_load(desc + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            // this lane's sum up to and including its nearest inclusive prefix
+            uint32_t all = 0, upto = 0;
+            bool has = false;
+#pragma unroll
+            for (int j = 0; j < kScanLook; ++j) {
+                all += (uint32_t)d[j];
+                if (!has) upto += (uint32_t)d[j];
+                has = has || ((d[j] >> 32) & 1u);
+            }
+            const uint64_t with_incl = __ballot(has);
+            uint32_t x = all;
+            if (with_incl) {
+                const int first = __builtin_ctzll(with_incl);  // nearest lane with one
+                x = (lane < first) ? all : (lane == first ? upto : 0u);
+            }
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+            prefix += x;
+            if (with_incl) break;
+            p -= kScanWindow;
+        }
+        if (__ballot(timed_out) && lane == 0) atomicOr(status, kStatusScan);
+        if (lane == 0) {
+            if (chunk > 0)
+                __hip_atomic_store(desc + chunk, scan_desc(epoch, true, prefix + (uint32_t)agg),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_prefix = (int)prefix;
+        }
+    }
+    __syncthreads();
+    const int pre = s_prefix;
+#pragma unroll
+    for (int k = 0; k < kScanRows; ++k) {
+        const int c = base + (k * kScanThreads + t) * 4;
+        const int o = pre + ex[k];
+        const int4 r = make_int4(o, o + v[k].x, o + v[k].x + v[k].y, o + v[k].x + v[k].y + v[k].z);
+        if (c + 4 <= n) {
+            *reinterpret_cast<int4*>(cs + c) = r;
+            if (clear) *reinterpret_cast<int4*>(count + c) = make_int4(0, 0, 0, 0);
+        } else {
+            if (c < n) cs[c] = r.x;
+            if (c + 1 < n) cs[c + 1] = r.y;
+            if (c + 2 < n) cs[c + 2] = r.z;
+            if (clear) {
+                if (c < n) count[c] = 0;
+                if (c + 1 < n) count[c + 1] = 0;
+                if (c + 2 < n) count[c + 2] = 0;
+            }
+        }
+    }
+    if (chunk == (int)gridDim.x - 1 && t == 0) cs[n] = pre + agg;
 }
 
 __global__ void k_scatter(int N, const int* __restrict__ key, const int* __restrict__ rank,

@@ -203,11 +203,16 @@ def test_forces_full_size_sampled(dpd):
     cs, ids = sim.cells()
     cso, idso = oracle.bin_cells(cfg, x)
     assert (host(cs) == cso).all() and (host(ids) == idso).all()
-    # after stepping in the benchmark's configuration the state stays sane
+    # after stepping in the benchmark's configuration the state stays sane and
+    # its cell list (a scan over hundreds of chunks, many launches later) is
+    # still bit-exact
     sim.step(20)
     sim.sync()
     xs = host(sim.get_state()[0])
     assert np.isfinite(xs).all() and (xs >= 0).all() and (xs < cfg["L"]).all()
+    cs, ids = sim.cells()
+    cso, idso = oracle.bin_cells(cfg, xs)
+    assert (host(cs) == cso).all() and (host(ids) == idso).all()
     sim.close()
 
 
