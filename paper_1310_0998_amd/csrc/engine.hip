@@ -791,6 +791,21 @@ int copy_state(dpd_handle* h, bool save) {
     return DPD_OK;
 }
 
+// Bin the stored state S again (nothing prepared): after S was copied back
+// from the tuner's save area, cell_start holds a later binning.  S is in the
+// slot order of the binning of its own positions, which this repeats, so the
+// cell list read with S (dpd_get_cells, the row binning of velocities) matches
+// it again.
+int rebin_stored(dpd_handle* h) {
+    for (const Rep& r : h->d.reps) {
+        const size_t pb = (size_t)r.P.pbase;
+        hipLaunchKernelGGL(k_key_rank, dim3(grid_for(r.P.N)), dim3(kBlock), 0, h->stream, r.P,
+                           (const float2*)h->Sx + pb, h->key + pb, h->rank + pb, h->count);
+    }
+    LAUNCHCHK(h);
+    return bin_from_counts(h, h->count, true, nullptr, nullptr, nullptr, h->Sid);
+}
+
 // The handle's replicas under schedule s (tile sides clamped per replica).
 Derived with_schedule(const Derived& d, const Sched& s) {
     Derived nd = d;
@@ -1476,6 +1491,7 @@ int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* t
         h->tile_order = best_order;
         rc = upload_tables(h);
         if (!rc) rc = copy_state(h, false);
+        if (!rc) rc = rebin_stored(h);
         if (rc) return rc;
         h->step = step0;
         h->prepared = false;
@@ -1519,9 +1535,9 @@ int dpd_forces_noalloc(const dpd_params* p, const float* x, const float* v, int6
         if (d.lay.total > kNoAllocScratchBytes)
             return fail(nullptr, DPD_EWORKSPACE,
                         fmt("%lld particles need %zu bytes of scratch; the static scratch of "
-                            "dpd_forces_noalloc holds %zu (about %lld particles at one per cell)",
+                            "dpd_forces_noalloc holds %zu (about %lld particles at this density)",
                             (long long)d.N, d.lay.total, kNoAllocScratchBytes,
-                            (long long)(kNoAllocScratchBytes / 128)));
+                            (long long)((double)kNoAllocScratchBytes * (double)d.N / (double)d.lay.total)));
         void* ws = nullptr;
         rc = noalloc_scratch(&ws);
         if (rc) return rc;

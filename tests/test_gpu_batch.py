@@ -213,6 +213,12 @@ def test_autotune_keeps_state(dpd, batch):
     assert a[3] == b2[3] == 5
     for k in range(3):
         assert (host(a[k]) == host(b2[k])).all()
+    # the cell list read with the stored state (and the row binning of the
+    # velocities that uses it) belongs to that state again, not to a trial
+    for u, w in zip(ref.cells(), t.cells()):
+        assert (host(u) == host(w)).all()
+    for u, w in zip(ref.bin_velocity(32, 0.0, 0), t.bin_velocity(32, 0.0, 0)):
+        assert (host(u) == host(w)).all()
     ref.step(11)
     t.step(11)
     a, b2 = ref.get_state(), t.get_state()
