@@ -53,8 +53,10 @@ def fused_kernel_bytes(n_particles: int, n_cells: int) -> int:
     """What the fused step kernel itself must move: reads slot->index (4),
     x (8), u (8), id (4) per particle and cell_start (4 per cell + 1); writes
     the next x (8), u (8), id (4), cell key (4) and rank (4); one 4-byte atomic
-    read-modify-write of a cell counter (8).  60 B per particle + 4 per cell."""
-    return n_particles * (4 + 8 + 8 + 4 + 8 + 8 + 4 + 4 + 4 + 8) + 4 * (n_cells + 1)
+    read-modify-write of a cell counter (8); clears the counter its own binning
+    consumed (4 per cell).  60 B per particle + 8 per cell."""
+    return (n_particles * (4 + 8 + 8 + 4 + 8 + 8 + 4 + 4 + 4 + 8) + 4 * (n_cells + 1)
+            + 4 * n_cells)
 
 
 def kernel_source_hash() -> str:

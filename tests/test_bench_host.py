@@ -17,8 +17,9 @@ def test_pair_pass_bytes():
 
 
 def test_fused_kernel_bytes():
-    # 60 B per particle of the fused step kernel plus the cell_start entries
-    assert bench.fused_kernel_bytes(4_000_000, 4_000_000) == 256_000_004
+    # 60 B per particle of the fused step kernel, the cell_start entries and
+    # the clear of the consumed counter array
+    assert bench.fused_kernel_bytes(4_000_000, 4_000_000) == 272_000_004
     assert bench.fused_kernel_bytes(0, 0) == 4
 
 
