@@ -347,36 +347,45 @@ __device__ __forceinline__ int wave_scan_excl(int v, int& total) {
 }
 
 // Inclusive prefix sum and prefix maximum over the 64 lanes with DPP lane
-// moves (no LDS round trip): sums within rows of 16 lanes by shifts of 1, 2,
-// 4 and 8, then each row adds the last lane of the rows before it (row_bcast
-// of lanes 15 and 31).  A lane whose source lies outside its row takes the
-// identity (0 for the sum; for the maximum, callers pass values >= 0 and -1
-// as "none", and 0 <= any value keeps the maximum).
+// moves (no LDS round trip): within rows of 16 lanes by shifts of 1, 2, 4 and
+// 8, then each row combines the last lane of the rows before it (row_bcast of
+// lanes 15 and 31).  The shifts set bound_ctrl: a lane whose source lies
+// before the start of its row reads 0, which must be the identity of the
+// operation; every lane is written, so each shift step is one DPP-sourced add
+// or max.  The broadcasts write only the rows of their mask; the other rows
+// keep the combined value's 0 operand, the identity again.
 __device__ __forceinline__ int wave_incl_sum(int v) {
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
     v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
     v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return v;
 }
 
+// The maximum's identity is INT_MIN: a lane the DPP move leaves out keeps it
+// (no bound_ctrl), so every step folds into one DPP-sourced max as well.
 __device__ __forceinline__ int wave_incl_max(int v) {
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));
+    constexpr int kLow = (int)0x80000000u;
+    v = max(v, __builtin_amdgcn_update_dpp(kLow, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(kLow, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(kLow, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(kLow, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(kLow, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(kLow, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
     return v;
 }
 
-// Exclusive prefix sum over the lanes; total = the sum of all 64.
+// Exclusive prefix sum over the lanes; total = the sum of all 64.  The
+// exclusive value is the inclusive one of the lane before (wave_shr:1, lane 0
+// reads 0), which keeps each shift step of the inclusive scan a single
+// DPP-sourced add (written as incl - v, the compiler rebuilds the difference
+// from the shifted values and keeps every one of them).
 __device__ __forceinline__ int wave_excl_sum(int v, int& total) {
     const int incl = wave_incl_sum(v);
     total = __builtin_amdgcn_readlane(incl, kWave - 1);
-    return incl - v;
+    return __builtin_amdgcn_update_dpp(0, incl, 0x138, 0xf, 0xf, true);  // wave_shr:1
 }
 
 __device__ __forceinline__ int wave_max(int v) {
