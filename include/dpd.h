@@ -46,7 +46,9 @@ extern "C" {
 #define DPD_OK          0
 #define DPD_EINVAL     -1  /* bad argument or parameter                          */
 #define DPD_EWORKSPACE -2  /* workspace missing, misaligned or too small          */
-#define DPD_EHIP       -3  /* a HIP runtime call failed                           */
+#define DPD_EHIP       -3  /* a HIP runtime call failed, or an internal device
+                              check of the cell binning did (inconsistent counts,
+                              a scan whose look-back exceeded its poll limit)    */
 #define DPD_ENONFINITE -4  /* a non-finite position, velocity or force appeared   */
 #define DPD_ESTATE     -5  /* call needs a state set by dpd_set_state first       */
 #define DPD_EBOND      -6  /* a bond grew beyond the cell stencil (1.25 bond_l <= cell width) */
