@@ -1125,24 +1125,39 @@ __global__ void k_colour_rows_r(int M, int B, uint32_t step0, uint32_t k0, uint3
     A[(((size_t)bq * M + j) * M + idx) * 2 + c] = radix_stage2(sy, c, idx, M, tw, false);
 }
 
-// k_colour_cols in two stages: column k <= M / 2 of field bq, forward
-// transform, times Hhat, inverse transform (without its 1/M), in place.
-__global__ void k_colour_cols_r(int M, const float2* __restrict__ Hhat, float2* A) {
+// k_colour_cols in two stages: columns k <= M / 2 of field bq, forward
+// transform, times Hhat, inverse transform (without its 1/M), in place.  A
+// block holds kColGroupThreads / (2 M) adjacent columns: thread t owns
+// component t & 1 of row (t >> 1) / G of its block's column (t >> 1) mod G, so
+// that a wavefront reads and writes whole runs of adjacent columns of a row
+// rather than one 16-byte piece per row.  In LDS every column's 2 M values are
+// padded by one, so the columns of a wavefront fall on different banks.
+constexpr int kColGroupThreads = 1024;
+
+__global__ __launch_bounds__(kColGroupThreads) void k_colour_cols_r(int M, const float2* __restrict__ Hhat,
+                                                                    float2* A) {
     __shared__ float2 tw[kColourMaxM];
-    __shared__ float2 sa[2 * kColourMaxM], sy[2 * kColourMaxM];
-    const int k = blockIdx.x, bq = blockIdx.y, t = threadIdx.x;
-    const int idx = t >> 1, c = t & 1;
+    __shared__ float2 sa[kColGroupThreads + kColGroupThreads / 4], sy[kColGroupThreads + kColGroupThreads / 4];
+    const int G = kColGroupThreads / (2 * M), CS = 2 * M + 1;
+    const int bq = blockIdx.y, t = threadIdx.x;
+    const int c = t & 1, g = (t >> 1) % G, idx = (t >> 1) / G;
+    const int k = blockIdx.x * G + g;
+    const bool valid = k <= M / 2;
     twiddle_table(M, tw);
-    float2* col = A + ((size_t)bq * M * M + k) * 2 + c;  // + 2 M row
-    sa[t] = col[(size_t)2 * M * idx];
+    float2* ca = sa + g * CS;
+    float2* cy = sy + g * CS;
+    const size_t at = (((size_t)bq * M + idx) * M + k) * 2 + c;  // row idx, column k
+    ca[2 * idx + c] = valid ? A[at] : make_float2(0.f, 0.f);
     __syncthreads();
-    sy[t] = radix_stage1<false>(sa, c, idx, M, tw, false);
+    cy[2 * idx + c] = radix_stage1<false>(ca, c, idx, M, tw, false);
     __syncthreads();
-    sa[t] = cmul(radix_stage2(sy, c, idx, M, tw, false), Hhat[idx * M + k], false);  // l = idx
+    const float2 hh = valid ? Hhat[idx * M + k] : make_float2(0.f, 0.f);
+    ca[2 * idx + c] = cmul(radix_stage2(cy, c, idx, M, tw, false), hh, false);  // l = idx
     __syncthreads();
-    sy[t] = radix_stage1<false>(sa, c, idx, M, tw, true);
+    cy[2 * idx + c] = radix_stage1<false>(ca, c, idx, M, tw, true);
     __syncthreads();
-    col[(size_t)2 * M * idx] = radix_stage2(sy, c, idx, M, tw, true);  // j = idx
+    const float2 out = radix_stage2(cy, c, idx, M, tw, true);  // j = idx
+    if (valid) A[at] = out;
 }
 
 // k_colour_noise in two stages: row j of field bq, the inverse row transform
@@ -1696,8 +1711,10 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
                     if (noise_filter) {  // M is 32 or 64: two-stage transforms
                         hipLaunchKernelGGL(k_colour_rows_r, dim3(n.p.M, B * ns), dim3(2 * n.p.M), 0, nn->stream,
                                            n.p.M, B, (uint32_t)s, k0, k1, Aw);
-                        hipLaunchKernelGGL(k_colour_cols_r, dim3(n.p.M / 2 + 1, B * ns), dim3(2 * n.p.M), 0,
-                                           nn->stream, n.p.M, (const float2*)Hh, Aw);
+                        const int G = kColGroupThreads / (2 * n.p.M);
+                        hipLaunchKernelGGL(k_colour_cols_r, dim3((n.p.M / 2 + G) / G, B * ns),
+                                           dim3(kColGroupThreads), 0, nn->stream, n.p.M,
+                                           (const float2*)Hh, Aw);
                         hipLaunchKernelGGL(k_colour_noise_r, dim3(n.p.M, B * ns), dim3(2 * n.p.M), 0,
                                            nn->stream, n.p.M, (const float2*)Aw, noise_std[0], noise_std[1],
                                            noise);
