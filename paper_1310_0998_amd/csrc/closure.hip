@@ -1105,80 +1105,87 @@ __device__ __forceinline__ float2 radix_stage2(const float2* y, int c, int k, in
     return make_float2(re, im);
 }
 
-// k_colour_rows in two stages: white numbers of row j of field b at step
-// step0 + q (blockIdx.y = q B + b), then their half spectrum.
-__global__ void k_colour_rows_r(int M, int B, uint32_t step0, uint32_t k0, uint32_t k1, float2* A) {
+constexpr int kColGroupThreads = 1024;  // threads of a filtered-noise block
+
+// The filtered noise of k_colour_rows, k_colour_cols and k_colour_noise by
+// two-stage transforms, one field-step per block, with the half spectrum
+// [j][k <= M/2][c] held in LDS between the passes: white numbers and the
+// forward row transforms; the forward column transforms, the filter and the
+// inverse column transforms; the inverse row transforms of the
+// Hermitian-extended rows, real part over M^2, times s_c.  The block takes
+// G = kColGroupThreads / (2 M) rows or columns at a time.  In the column pass
+// thread t owns component t & 1 of row (t >> 1) / G of column (t >> 1) mod G,
+// and every column's 2 M values are padded by one in LDS, so that the columns
+// a wavefront works on fall on different banks.  Only the noise goes to
+// global memory.
+__global__ __launch_bounds__(kColGroupThreads) void k_colour_fused_r(int M, int B, uint32_t step0,
+                                                                     uint32_t k0, uint32_t k1,
+                                                                     const float2* __restrict__ Hhat,
+                                                                     float s0, float s1, float* noise) {
+    constexpr int kHalfMax = kColourMaxM / 2 + 1;
     __shared__ float2 tw[kColourMaxM];
-    __shared__ float sw[2 * kColourMaxM];
-    __shared__ float2 sy[2 * kColourMaxM];
-    const int j = blockIdx.x, bq = blockIdx.y, t = threadIdx.x;
+    __shared__ float2 S[kColourMaxM * kHalfMax * 2];
+    __shared__ float rw[kColGroupThreads];
+    __shared__ float2 ry[kColGroupThreads];
+    __shared__ float2 sa[kColGroupThreads + kColGroupThreads / 4], sy[kColGroupThreads + kColGroupThreads / 4];
+    const int G = kColGroupThreads / (2 * M), CS = 2 * M + 1, H = M / 2 + 1;
+    const int bq = blockIdx.x, t = threadIdx.x;
     const int q = bq / B, b = bq - q * B;
     twiddle_table(M, tw);
-    const uint32_t point = (uint32_t)(((size_t)b * M + j) * M + (t >> 1));
-    const uint4 r = dpd::philox4x32_10(make_uint4(point, (uint32_t)(t & 1), step0 + (uint32_t)q, 0u), k0, k1);
-    sw[t] = dpd::alpha_from_words(0, make_uint2(r.x, r.y));
-    __syncthreads();
-    const int idx = t >> 1, c = t & 1;
-    sy[t] = radix_stage1<true>(sw, c, idx, M, tw, false);
-    __syncthreads();
-    if (idx > M / 2) return;
-    A[(((size_t)bq * M + j) * M + idx) * 2 + c] = radix_stage2(sy, c, idx, M, tw, false);
-}
-
-// k_colour_cols in two stages: columns k <= M / 2 of field bq, forward
-// transform, times Hhat, inverse transform (without its 1/M), in place.  A
-// block holds kColGroupThreads / (2 M) adjacent columns: thread t owns
-// component t & 1 of row (t >> 1) / G of its block's column (t >> 1) mod G, so
-// that a wavefront reads and writes whole runs of adjacent columns of a row
-// rather than one 16-byte piece per row.  In LDS every column's 2 M values are
-// padded by one, so the columns of a wavefront fall on different banks.
-constexpr int kColGroupThreads = 1024;
-
-__global__ __launch_bounds__(kColGroupThreads) void k_colour_cols_r(int M, const float2* __restrict__ Hhat,
-                                                                    float2* A) {
-    __shared__ float2 tw[kColourMaxM];
-    __shared__ float2 sa[kColGroupThreads + kColGroupThreads / 4], sy[kColGroupThreads + kColGroupThreads / 4];
-    const int G = kColGroupThreads / (2 * M), CS = 2 * M + 1;
-    const int bq = blockIdx.y, t = threadIdx.x;
-    const int c = t & 1, g = (t >> 1) % G, idx = (t >> 1) / G;
-    const int k = blockIdx.x * G + g;
-    const bool valid = k <= M / 2;
-    twiddle_table(M, tw);
-    float2* ca = sa + g * CS;
-    float2* cy = sy + g * CS;
-    const size_t at = (((size_t)bq * M + idx) * M + k) * 2 + c;  // row idx, column k
-    ca[2 * idx + c] = valid ? A[at] : make_float2(0.f, 0.f);
-    __syncthreads();
-    cy[2 * idx + c] = radix_stage1<false>(ca, c, idx, M, tw, false);
-    __syncthreads();
-    const float2 hh = valid ? Hhat[idx * M + k] : make_float2(0.f, 0.f);
-    ca[2 * idx + c] = cmul(radix_stage2(cy, c, idx, M, tw, false), hh, false);  // l = idx
-    __syncthreads();
-    cy[2 * idx + c] = radix_stage1<false>(ca, c, idx, M, tw, true);
-    __syncthreads();
-    const float2 out = radix_stage2(cy, c, idx, M, tw, true);  // j = idx
-    if (valid) A[at] = out;
-}
-
-// k_colour_noise in two stages: row j of field bq, the inverse row transform
-// of the Hermitian-extended half spectrum, real part over M^2, times s_c.
-__global__ void k_colour_noise_r(int M, const float2* __restrict__ A, float s0, float s1, float* noise) {
-    __shared__ float2 tw[kColourMaxM];
-    __shared__ float2 sa[2 * kColourMaxM], sy[2 * kColourMaxM];
-    const int j = blockIdx.x, bq = blockIdx.y, t = threadIdx.x;
-    const int idx = t >> 1, c = t & 1;
-    twiddle_table(M, tw);
-    {
-        const int kk = idx <= M / 2 ? idx : M - idx;
-        const float2 z = A[(((size_t)bq * M + j) * M + kk) * 2 + c];
-        sa[t] = idx <= M / 2 ? z : make_float2(z.x, -z.y);
+    {  // rows: white numbers, forward transform, half spectrum into S
+        const int g = t / (2 * M), lt = t - g * 2 * M, idx = lt >> 1, c = lt & 1;
+        float* w = rw + g * 2 * M;
+        float2* y = ry + g * 2 * M;
+        for (int j0 = 0; j0 < M; j0 += G) {
+            const int j = j0 + g;
+            const uint32_t point = (uint32_t)(((size_t)b * M + j) * M + idx);
+            const uint4 r = dpd::philox4x32_10(make_uint4(point, (uint32_t)c, step0 + (uint32_t)q, 0u), k0, k1);
+            w[lt] = dpd::alpha_from_words(0, make_uint2(r.x, r.y));
+            __syncthreads();
+            y[lt] = radix_stage1<true>(w, c, idx, M, tw, false);
+            __syncthreads();
+            if (idx <= M / 2) S[(j * H + idx) * 2 + c] = radix_stage2(y, c, idx, M, tw, false);
+        }
     }
     __syncthreads();
-    sy[t] = radix_stage1<false>(sa, c, idx, M, tw, true);
+    {  // columns k <= M / 2: forward transform, times Hhat, inverse, in place
+        const int c = t & 1, g = (t >> 1) % G, idx = (t >> 1) / G;
+        float2* ca = sa + g * CS;
+        float2* cy = sy + g * CS;
+        for (int kb = 0; kb < H; kb += G) {
+            const int k = kb + g;
+            const bool valid = k < H;
+            ca[2 * idx + c] = valid ? S[(idx * H + k) * 2 + c] : make_float2(0.f, 0.f);
+            __syncthreads();
+            cy[2 * idx + c] = radix_stage1<false>(ca, c, idx, M, tw, false);
+            __syncthreads();
+            const float2 hh = valid ? Hhat[idx * M + k] : make_float2(0.f, 0.f);
+            ca[2 * idx + c] = cmul(radix_stage2(cy, c, idx, M, tw, false), hh, false);  // l = idx
+            __syncthreads();
+            cy[2 * idx + c] = radix_stage1<false>(ca, c, idx, M, tw, true);
+            __syncthreads();
+            const float2 out = radix_stage2(cy, c, idx, M, tw, true);  // j = idx
+            if (valid) S[(idx * H + k) * 2 + c] = out;
+        }
+    }
     __syncthreads();
-    const float re = radix_stage2(sy, c, idx, M, tw, true).x;  // i = idx
-    const float inv = 1.0f / (float)(M * M);
-    noise[(((size_t)bq * M + j) * M + idx) * 2 + c] = (c ? s1 : s0) * (re * inv);
+    {  // rows: Hermitian extension, inverse transform, real part over M^2, times s_c
+        const int g = t / (2 * M), lt = t - g * 2 * M, idx = lt >> 1, c = lt & 1;
+        float2* x = sa + g * 2 * M;
+        float2* y = sy + g * 2 * M;
+        const float inv = 1.0f / (float)(M * M);
+        for (int j0 = 0; j0 < M; j0 += G) {
+            const int j = j0 + g;
+            const int kk = idx <= M / 2 ? idx : M - idx;
+            const float2 z = S[(j * H + kk) * 2 + c];
+            x[lt] = idx <= M / 2 ? z : make_float2(z.x, -z.y);
+            __syncthreads();
+            y[lt] = radix_stage1<false>(x, c, idx, M, tw, true);
+            __syncthreads();
+            const float re = radix_stage2(y, c, idx, M, tw, true).x;  // i = idx
+            noise[(((size_t)bq * M + j) * M + idx) * 2 + c] = (c ? s1 : s0) * (re * inv);
+        }
+    }
 }
 
 // ---- field statistics ------------------------------------------------------------
@@ -1687,13 +1694,11 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
         if (band_fits(n)) {
             // the whole network per step as one kernel, which also adds the
             // noise; the noise of up to S steps is drawn ahead in one pass.
-            // Buffers free during a rollout: spectra [S][B][M][M][2] complex in
-            // dz[0], noise [S][B][M][M][2] in dz[1], DFT(h) in dzb[0], the
-            // second input buffer (the kernel reads one, writes the other) in
-            // dzb[1]
+            // Buffers free during a rollout: noise [S][B][M][M][2] in dz[1],
+            // DFT(h) in dzb[0], the second input buffer (the kernel reads one,
+            // writes the other) in dzb[1]
             const int cmax = std::max(n.p.width, 4);
             const int S = std::max(1, std::min(std::min(kNoiseAhead, cmax / 4), 65535 / B));
-            float2* Aw = at<float2>(nn, n.o_dz[0]);
             float* noise = at<float>(nn, n.o_dz[1]);
             float2* Hh = at<float2>(nn, n.o_dzb[0]);
             unsigned short* X1 = at<unsigned short>(nn, n.o_dzb[1]);
@@ -1708,16 +1713,10 @@ int dpd_nn_rollout(dpd_nn* nn, const float* u0, const float* cond, int32_t B, in
                 const int q = (s - 1) % S;
                 if (q == 0) {
                     const int ns = std::min(S, steps - s + 1);
-                    if (noise_filter) {  // M is 32 or 64: two-stage transforms
-                        hipLaunchKernelGGL(k_colour_rows_r, dim3(n.p.M, B * ns), dim3(2 * n.p.M), 0, nn->stream,
-                                           n.p.M, B, (uint32_t)s, k0, k1, Aw);
-                        const int G = kColGroupThreads / (2 * n.p.M);
-                        hipLaunchKernelGGL(k_colour_cols_r, dim3((n.p.M / 2 + G) / G, B * ns),
-                                           dim3(kColGroupThreads), 0, nn->stream, n.p.M,
-                                           (const float2*)Hh, Aw);
-                        hipLaunchKernelGGL(k_colour_noise_r, dim3(n.p.M, B * ns), dim3(2 * n.p.M), 0,
-                                           nn->stream, n.p.M, (const float2*)Aw, noise_std[0], noise_std[1],
-                                           noise);
+                    if (noise_filter) {  // M is 32 or 64: two-stage transforms, one block per field-step
+                        hipLaunchKernelGGL(k_colour_fused_r, dim3(B * ns), dim3(kColGroupThreads), 0,
+                                           nn->stream, n.p.M, B, (uint32_t)s, k0, k1, (const float2*)Hh,
+                                           noise_std[0], noise_std[1], noise);
                     } else {
                         hipLaunchKernelGGL(k_noise_steps, dim3(blocks((long long)nf * ns)), dim3(kThreads), 0,
                                            nn->stream, nf, ns, (uint32_t)s, k0, k1, noise_std[0],
