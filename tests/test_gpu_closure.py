@@ -255,13 +255,14 @@ def test_rollout_band_kernel_adds_the_noise(cl, filtered):
     zero.close()
 
 
-@pytest.mark.parametrize("M,width,layers", [(20, 16, 1), (64, 16, 1), (64, 32, 2)])
+@pytest.mark.parametrize("M,width,layers", [(20, 16, 1), (64, 16, 1), (64, 32, 2), (32, 32, 3)])
 def test_coloured_noise_is_the_periodic_convolution(cl, M, width, layers):
     # one step of the zero network from rest: with unit noise_std the white
     # rollout gives w itself, and the filtered one h * w (periodic, per field
     # and component), here against an FP64 FFT convolution with a random,
     # non-symmetric h; M = 20 is not a power of two; width 32 takes the
-    # one-kernel step with the noise drawn ahead
+    # one-kernel step with the noise drawn ahead (at M = 32 a block of the
+    # noise kernel takes 16 rows or columns at a time, at M = 64 eight)
     B = 2
     net = cl.Closure(M, c_in=4, width=width, layers=layers, max_batch=B, device=DEV)
     rng = np.random.default_rng(15)
