@@ -287,7 +287,8 @@ int derive(const dpd_params* p, int n_rep, Derived* d, std::string* err) {
     }
     if (d->skin) ta = d->tiles;  // the skin keeps the tiling it was created with
     d->tiles_alloc = ta;
-    d->n_scan_blocks = (int)((d->cells + kScanTile - 1) / kScanTile);
+    const long long scan_tile = (long long)kScanThreads * 4 * scan_rows(d->cells);
+    d->n_scan_blocks = (int)((d->cells + scan_tile - 1) / scan_tile);
     d->bin_M_max = bin_M_max;
 
     const size_t N = (size_t)d->N, C = (size_t)d->cells, T = (size_t)d->tiles_alloc;
@@ -450,7 +451,8 @@ int bin_from_counts(dpd_handle* h, int* count, bool clear, const int* rebuild, i
                     const int* id_of_input, const int* ids_in) {
     const int G = h->d.n_scan_blocks;
     const int C = (int)h->d.cells, N = (int)h->d.N;
-    hipLaunchKernelGGL(k_scan, dim3(G), dim3(kScanThreads), 0, h->stream, count, C, clear ? 1 : 0,
+    auto scan = scan_rows(C) == 1 ? k_scan<1> : k_scan<4>;
+    hipLaunchKernelGGL(scan, dim3(G), dim3(kScanThreads), 0, h->stream, count, C, clear ? 1 : 0,
                        h->cs, h->scan_desc,
                        h->scan_desc + G, h->status, h->ovf, rebuild, moved_clear, h->flags + 2);
     hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(N), 4096)), dim3(kBlock), 0, h->stream,

@@ -1121,7 +1121,7 @@ __global__ void k_key_rank(DevParams P, const float2* __restrict__ x, int* key, 
 }
 
 // Exclusive scan of the per-cell counts -> cell_start in one pass over chunks
-// of kScanTile cells (decoupled look-back: Merrill & Garland, "Single-pass
+// of ROWS 4 kScanThreads cells (decoupled look-back: Merrill & Garland, "Single-pass
 // parallel prefix scan with decoupled look-back", NVIDIA tech. report 2016).
 // Each block draws a ticket from a counter, so the chunks are taken in order
 // and a block only ever waits for chunks taken before its own, whose blocks are
@@ -1133,14 +1133,15 @@ __global__ void k_key_rank(DevParams P, const float2* __restrict__ x, int* key, 
 // zeroes its counts for the next binning (the stepping path leaves that to the
 // pair kernel, tile by tile).
 //
-// A chunk is kScanRows rows of kScanThreads groups of 4 cells in row-major
-// order, thread t holding group t of every row: each load and store of a
-// wavefront covers 1 KB of consecutive cells.  The chunks are large (a few
-// hundred for millions of cells, about one per compute unit) and one
-// wavefront reads kScanWindow descriptors per round of the look-back: the
-// blocks run side by side and publish their sums at about the same time, so a
-// round that reaches back over every earlier chunk at once keeps the look-back
-// to one round trip.
+// A chunk is ROWS rows of kScanThreads groups of 4 cells in row-major order,
+// thread t holding group t of every row: each load and store of a wavefront
+// covers 1 KB of consecutive cells.  The chunks are large (ROWS = 4: a few
+// hundred for millions of cells, about one per compute unit; ROWS = 1 below
+// kScanSmallCells cells, so that a small grid still spreads over tens of
+// blocks) and one wavefront reads kScanWindow descriptors per round of the
+// look-back: the blocks run side by side and publish their sums at about the
+// same time, so a round that reaches back over every earlier chunk at once
+// keeps the look-back to one round trip.
 //
 // A descriptor is one 64-bit word, written and read whole: bits 0-31 the
 // value, bit 32 set when the value is the inclusive prefix (clear: the chunk's
@@ -1157,16 +1158,19 @@ __global__ void k_key_rank(DevParams P, const float2* __restrict__ x, int* key, 
 // (`moved_clear`) and counts the rebuilds; the scan itself runs only on
 // rebuild steps (`rebuild` null: always).
 constexpr int kScanThreads = 1024;
-constexpr int kScanRows = 4;
-constexpr int kScanTile = kScanThreads * 4 * kScanRows;  // cells per chunk
-constexpr int kScanLook = 4;                             // descriptors per lane and round
-constexpr int kScanWindow = kWave * kScanLook;           // chunks per round of the look-back
+constexpr int kScanLook = 4;                    // descriptors per lane and round
+constexpr int kScanWindow = kWave * kScanLook;  // chunks per round of the look-back
+// grids up to this many cells scan in chunks of one row (at most kScanWindow
+// chunks, so one look-back round still reaches the first)
+constexpr long long kScanSmallCells = (long long)kScanWindow * kScanThreads * 4;
+__host__ __device__ constexpr int scan_rows(long long cells) { return cells <= kScanSmallCells ? 1 : 4; }
 constexpr int kScanSpin = 1 << 20;
 
 __device__ __forceinline__ uint64_t scan_desc(uint32_t epoch, bool inclusive, uint32_t v) {
     return ((uint64_t)(epoch & 0x7FFFFFFFu) << 33) | ((uint64_t)inclusive << 32) | v;
 }
 
+template <int ROWS>
 __global__ __launch_bounds__(kScanThreads) void k_scan(int* count, int n, int clear, int* cs,
                                                        unsigned long long* desc,
                                                        unsigned long long* ticket,
@@ -1174,7 +1178,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* count, int n, int cl
                                                        const int* rebuild, int* moved_clear,
                                                        int* rebuilds) {
     constexpr int kWaves = kScanThreads / kWave;
-    __shared__ int s_wave[kScanRows][kWaves];
+    constexpr int kTile = kScanThreads * 4 * ROWS;  // cells per chunk
+    __shared__ int s_wave[ROWS][kWaves];
     __shared__ uint32_t s_ticket[2];
     __shared__ int s_prefix;
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
@@ -1200,10 +1205,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* count, int n, int cl
                            __HIP_MEMORY_SCOPE_AGENT);
 
     // group t of every row: 4 consecutive cells
-    const int base = chunk * kScanTile;
-    int4 v[kScanRows];
+    const int base = chunk * kTile;
+    int4 v[ROWS];
 #pragma unroll
-    for (int k = 0; k < kScanRows; ++k) {
+    for (int k = 0; k < ROWS; ++k) {
         const int c = base + (k * kScanThreads + t) * 4;
         if (c + 4 <= n) {
             v[k] = *reinterpret_cast<const int4*>(count + c);
@@ -1213,9 +1218,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* count, int n, int cl
         }
     }
     // exclusive prefix of every group within the chunk
-    int ex[kScanRows];
+    int ex[ROWS];
 #pragma unroll
-    for (int k = 0; k < kScanRows; ++k) {
+    for (int k = 0; k < ROWS; ++k) {
         const int g = (v[k].x + v[k].y) + (v[k].z + v[k].w);
         int incl = g;
 #pragma unroll
@@ -1229,7 +1234,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* count, int n, int cl
     __syncthreads();
     int agg = 0;
 #pragma unroll
-    for (int k = 0; k < kScanRows; ++k) {
+    for (int k = 0; k < ROWS; ++k) {
         int wofs = 0, row = 0;
 #pragma unroll
         for (int q = 0; q < kWaves; ++q) {
@@ -1309,7 +1314,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int* count, int n, int cl
     __syncthreads();
     const int pre = s_prefix;
 #pragma unroll
-    for (int k = 0; k < kScanRows; ++k) {
+    for (int k = 0; k < ROWS; ++k) {
         const int c = base + (k * kScanThreads + t) * 4;
         const int o = pre + ex[k];
         const int4 r = make_int4(o, o + v[k].x, o + v[k].x + v[k].y, o + v[k].x + v[k].y + v[k].z);

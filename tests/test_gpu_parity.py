@@ -85,9 +85,9 @@ BIN_CASES = [
     ("nc5", dict(C1, L=5.0, n_agents=12, seed=9), "random"),
     ("clustered", dict(C1, L=40.0, n_agents=1200, seed=10), "clustered"),
     ("one-agent", dict(C1, L=10.0, n_agents=1, seed=11), "random"),
-    # the cell scan works in chunks of 16384 cells: exactly one chunk; a last
-    # chunk of 257 cells (not a whole group of 4); 270 chunks, more than one
-    # look-back window of 256 chunks
+    # the cell scan works in chunks of 4096 cells up to 2^20 cells, of 16384
+    # above: a whole number of chunks; a last chunk of 257 cells (not a whole
+    # group of 4); 270 large chunks, more than one look-back window of 256
     ("chunk-exact", dict(C1, L=128.0, n_agents=8000, seed=12), "random"),
     ("chunk-ragged", dict(C1, L=129.0, n_agents=8000, seed=13), "random"),
     ("chunks-270", dict(C1, L=2100.0, n_agents=100000, seed=14), "random"),
