@@ -600,8 +600,8 @@ def run_paper(args):
         keep = [tuple(float(t) for t in part.split(",")) for part in args.paper_subset.split(";")]
         reps = [r for r in reps if (r[1], r[2]) in keep]
     t0 = time.perf_counter()
-    res, r_grid = paper_runs.run(dev, args.paper_warm, args.paper_steps, args.paper_every, replicas=reps,
-                                 log=log)
+    res, r_grid, schedule = paper_runs.run(dev, args.paper_warm, args.paper_steps, args.paper_every,
+                                           replicas=reps, log=log)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_particles = sum(2 * int(round(4.0e4 * r[0])) for r in reps)
@@ -622,6 +622,7 @@ def run_paper(args):
                         f"a snapshot every {args.paper_every} steps after {args.paper_warm} steps of "
                         "relaxation",
             "parallelism": "single-gpu (one batch)",
+            "schedule": schedule,
         },
         "replicas": [{k: v for k, v in r.items() if k not in ("E_over_E1", "g_v")} for r in res],
         "checks": paper_runs.checks(res) if reps == paper_runs.REPLICAS else None,

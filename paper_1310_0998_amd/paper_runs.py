@@ -9,7 +9,10 @@ panels of the paper's spectra, correlation lengths and slopes: phi in
 Gamma in {1, 4, 8} with Gamma_s = 0 (pair friction only).
 
 Protocol (Sec. 5): a relaxation from the random start, then snapshots every
-2 x 10^4 steps.  Per snapshot and replica:
+2 x 10^4 steps.  After the first 2 x 10^4 relaxation steps the tile schedule
+is tuned on the state reached (clusters have formed by then, and the tiles of
+the dense replicas overflow the default capacities); the trajectories are
+bitwise independent of the schedule, so only the run time changes.  Per snapshot and replica:
   - u_M on a 128 x 128 grid with overlapping windows of width
     eps = L sqrt(N_f / N), N_f = 10 agents per window on average (Eq. 5.10),
     particle velocities, binned once per replica with its own eps;
@@ -56,7 +59,7 @@ def slope_fit(E: np.ndarray, n: int = 10):
     return float(coef[1]), float(math.exp(coef[0]))
 
 
-def run(device, warm: int, steps: int, every: int, replicas=None, log=print):
+def run(device, warm: int, steps: int, every: int, replicas=None, log=print, tune: bool = True):
     reps = REPLICAS if replicas is None else replicas
     cfgs = [replica_cfg(*r, seed=701 + i) for i, r in enumerate(reps)]
     states = [inputs.initial_state(c) for c in cfgs]
@@ -66,10 +69,17 @@ def run(device, warm: int, steps: int, every: int, replicas=None, log=print):
     sim.set_state(torch.from_numpy(x).to(device), torch.from_numpy(v).to(device), 0)
     sim.set_graph_chunk(100)
     t0 = time.perf_counter()
+    schedule = None
     for w0 in range(0, warm, 20000):
         sim.step(min(20000, warm - w0))
         sim.sync()
         log(f"relaxation: {min(w0 + 20000, warm)} of {warm} steps, {time.perf_counter() - t0:.1f} s")
+        if tune and w0 == 0:
+            tx, ty, order, ms = sim.autotune(50)
+            schedule = dict(replica0_tile=[tx, ty], order=order, trial_ms_per_step=ms,
+                            after_steps=min(20000, warm))
+            log(f"schedule tuned on the relaxed state: replica 0 tile {tx} x {ty}, order {order}, "
+                f"{ms:.4f} ms/step in the trials")
     R = len(cfgs)
     eps = [c["L"] * math.sqrt(N_F / c["n_agents"]) for c in cfgs]
     base = np.concatenate([[0], np.cumsum([2 * c["n_agents"] for c in cfgs])])
@@ -106,7 +116,7 @@ def run(device, warm: int, steps: int, every: int, replicas=None, log=print):
                         L_gv=L_gv, E_over_E1=En.tolist(), g_v=g.tolist()))
         log(f"phi {phi} Gamma {gm} Gamma_s {gs}: alpha {alpha:+.3f}, peak at k = {k_peak}, "
             f"high-k slope {ah:+.2f}, L_gv {L_gv:.3f}")
-    return out, r.tolist()
+    return out, r.tolist(), schedule
 
 
 def checks(res):
