@@ -1121,8 +1121,9 @@ __global__ void k_key_rank(DevParams P, const float2* __restrict__ x, int* key, 
 }
 
 // Exclusive scan of the per-cell counts -> cell_start in one pass over chunks
-// of ROWS 4 kScanThreads cells (decoupled look-back: Merrill & Garland, "Single-pass
-// parallel prefix scan with decoupled look-back", NVIDIA tech. report 2016).
+// of 4 ROWS kScanThreads cells (decoupled look-back: Merrill & Garland,
+// "Single-pass parallel prefix scan with decoupled look-back", NVIDIA tech.
+// report 2016).
 // Each block draws a ticket from a counter, so the chunks are taken in order
 // and a block only ever waits for chunks taken before its own, whose blocks are
 // already running.  A block publishes its chunk's sum at once, then its
