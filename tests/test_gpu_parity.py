@@ -91,6 +91,10 @@ BIN_CASES = [
     ("chunk-exact", dict(C1, L=128.0, n_agents=8000, seed=12), "random"),
     ("chunk-ragged", dict(C1, L=129.0, n_agents=8000, seed=13), "random"),
     ("chunks-270", dict(C1, L=2100.0, n_agents=100000, seed=14), "random"),
+    # 2^20 cells: 256 small chunks, one full look-back window; one cell row
+    # more: large chunks
+    ("small-chunks-256", dict(C1, L=1024.0, n_agents=30000, seed=15), "random"),
+    ("large-chunks-65", dict(C1, L=1025.0, n_agents=30000, seed=16), "random"),
 ]
 
 
