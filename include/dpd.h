@@ -245,7 +245,11 @@ int dpd_get_schedule(dpd_handle* h, int32_t* tile_x, int32_t* tile_y, int32_t* t
  * (every replica's default tile scaled by 1, 0.85, 0.7 and 0.55; the same
  * 8 x 7, 8 x 8, 6 x 6 and 4 x 4 tiles for all; both tile orders), keep the
  * fastest and restore the state exactly as it was (state, step, no prepared
- * step).  The choice holds for states like the one timed: cell occupancy
+ * step).  In a batch, replicas that still have more than 2 % of their tiles
+ * over the tile kernel's LDS capacities (dense clusters) then move, round by
+ * round while the step gets faster, to finer tiles (down to the default tile
+ * scaled by 0.3), so replicas can end with tiles of different scales; the
+ * batch workspace holds those tilings.  The choice holds for states like the one timed: cell occupancy
  * changes along a run (a random start relaxes within a few hundred steps, and
  * propelled agents cluster), so tune on a state of the kind the run will see.
  * Outputs (host, any may be NULL): the chosen schedule and its time per step

@@ -107,6 +107,10 @@ const Sched kCandidates[] = {
     {8, 7, 0.0, 0}, {8, 8, 0.0, 0}, {6, 6, 0.0, 0}, {4, 4, 0.0, 0},
 };
 
+// Finer tilings the tuner may give single replicas of a batch whose tiles
+// still overflow under the candidates above (dense clusters).
+const Sched kRefine[] = {{0, 0, 0.4, 0}, {0, 0, 0.3, 0}};
+
 // Default tile of a system, scaled by f.  Without a skin the sides shrink as
 // 1 / (particles per cell): a tile then keeps about as many pairs as 8 x 7
 // cells at one particle per cell (the kept pairs of a tile grow as its
@@ -283,6 +287,8 @@ int derive(const dpd_params* p, int n_rep, Derived* d, std::string* err) {
     for (const Rep& r : d->reps) {
         long long t = (long long)r.P.ntx * r.P.nty;
         for (const Sched& c : kCandidates) t = std::max(t, tiles_with(r, c));
+        if (d->reps.size() > 1)
+            for (const Sched& c : kRefine) t = std::max(t, tiles_with(r, c));
         ta += t;
     }
     if (d->skin) ta = d->tiles;  // the skin keeps the tiling it was created with
@@ -1446,6 +1452,47 @@ int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* t
         double best = 1e300;
         Derived best_d = h->d;
         int best_order = h->tile_order;
+        // one trial: the state as saved, stepped under tiling nd; its time in
+        // ms and, if asked, each replica's tiles that overflowed an LDS capacity
+        // in the last step
+        auto trial = [&](const Derived& nd, int order, float* ms, std::vector<int>* ovf_rep) -> int {
+            drop_graphs(h);
+            h->d = nd;
+            h->tile_order = order;
+            int r2 = upload_tables(h);
+            if (!r2) r2 = copy_state(h, false);
+            if (r2) return r2;
+            h->step = step0;
+            h->prepared = false;
+            r2 = kick_drift(h);
+            int64_t rec = 0;
+            if (!r2) r2 = run_steps(h, 2, 0, nullptr, 0, &rec);  // untimed
+            if (!r2 && hipEventRecord(e0, h->stream) != hipSuccess) r2 = fail(h, DPD_EHIP, "hipEventRecord failed");
+            if (!r2) r2 = run_steps(h, trial_steps, 0, nullptr, 0, &rec);
+            if (!r2 && hipEventRecord(e1, h->stream) != hipSuccess) r2 = fail(h, DPD_EHIP, "hipEventRecord failed");
+            if (!r2 && hipEventSynchronize(e1) != hipSuccess) r2 = fail(h, DPD_EHIP, "hipEventSynchronize failed");
+            if (!r2 && hipEventElapsedTime(ms, e0, e1) != hipSuccess) r2 = fail(h, DPD_EHIP, "hipEventElapsedTime failed");
+            if (!r2 && ovf_rep) {
+                // the last pair launch's list of overflowing tiles (cleared by
+                // the next step's scan only)
+                int n = 0;
+                HIPCHK(h, hipMemcpy(&n, h->ovf, sizeof n, hipMemcpyDeviceToHost));
+                n = std::max(0, std::min<int>(n, (int)nd.tiles));
+                std::vector<int> list((size_t)n);
+                if (n) HIPCHK(h, hipMemcpy(list.data(), h->ovf + 1, (size_t)n * 4, hipMemcpyDeviceToHost));
+                ovf_rep->assign(nd.reps.size(), 0);
+                for (int t : list)
+                    for (size_t r = 0; r < nd.reps.size(); ++r) {
+                        const long long t0 = nd.reps[r].P.tbase;
+                        if (t >= t0 && t < t0 + (long long)nd.reps[r].P.ntx * nd.reps[r].P.nty) {
+                            ++(*ovf_rep)[r];
+                            break;
+                        }
+                    }
+            }
+            if (!r2) r2 = unprepare(h);
+            return r2;
+        };
         std::vector<std::vector<int>> seen;
         for (const Sched& c0 : kCandidates) {
             for (int order = 0; order < 2 && !rc; ++order) {
@@ -1459,29 +1506,79 @@ int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* t
                 for (const Rep& r : nd.reps) sig.push_back(r.P.tile_x * 16 + r.P.tile_y);
                 if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
                 seen.push_back(sig);
-                rc = apply_schedule(h, c);
-                if (!rc) rc = copy_state(h, false);
-                if (rc) break;
-                h->step = step0;
-                h->prepared = false;
-                rc = kick_drift(h);
-                int64_t rec = 0;
-                if (!rc) rc = run_steps(h, 2, 0, nullptr, 0, &rec);  // untimed
-                if (!rc && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventRecord failed");
-                if (!rc) rc = run_steps(h, trial_steps, 0, nullptr, 0, &rec);
-                if (!rc && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventRecord failed");
-                if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventSynchronize failed");
                 float ms = 0.f;
-                if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(h, DPD_EHIP, "hipEventElapsedTime failed");
-                if (rc) break;
-                rc = unprepare(h);
+                rc = trial(nd, order, &ms, nullptr);
                 if (!rc && ms < best) {
                     best = ms;
-                    best_d = h->d;
+                    best_d = nd;
                     best_order = order;
                 }
             }
             if (rc) break;
+        }
+        // A batch's replicas can differ in how their tiles fill (clusters form
+        // in some and not in others): starting from the best schedule, every
+        // replica with more than 2 % of its tiles overflowing in the last trial
+        // step moves to the tiling with the next larger number of tiles among
+        // the candidates and the finer ones, as long as the step gets faster
+        // (at most eight rounds).  Every replica's tiling is then one of those
+        // the per-tile arrays were sized for.
+        if (!rc && h->R > 1) {
+            const size_t R = best_d.reps.size();
+            std::vector<std::vector<Sched>> ladder(R);
+            std::vector<size_t> pos(R, 0);
+            for (size_t r = 0; r < R; ++r) {
+                std::vector<std::pair<long long, Sched>> opts;
+                std::vector<Sched> all(std::begin(kCandidates), std::end(kCandidates));
+                all.insert(all.end(), std::begin(kRefine), std::end(kRefine));
+                for (const Sched& c0 : all) {
+                    Rep rep = best_d.reps[r];
+                    apply_tiling(rep, c0);
+                    const long long nt = (long long)rep.P.ntx * rep.P.nty;
+                    bool dup = false;
+                    for (auto& o : opts) {
+                        Rep q = best_d.reps[r];
+                        apply_tiling(q, o.second);
+                        dup |= q.P.tile_x == rep.P.tile_x && q.P.tile_y == rep.P.tile_y;
+                    }
+                    if (!dup) opts.push_back({nt, c0});
+                }
+                std::stable_sort(opts.begin(), opts.end(),
+                                 [](const auto& x, const auto& y) { return x.first < y.first; });
+                for (auto& o : opts) ladder[r].push_back(o.second);
+                for (size_t k = 0; k < ladder[r].size(); ++k) {
+                    Rep q = best_d.reps[r];
+                    apply_tiling(q, ladder[r][k]);
+                    if (q.P.tile_x == best_d.reps[r].P.tile_x && q.P.tile_y == best_d.reps[r].P.tile_y) pos[r] = k;
+                }
+            }
+            float ms = 0.f;
+            std::vector<int> ovf;
+            rc = trial(best_d, best_order, &ms, &ovf);
+            for (int round = 0; round < 8 && !rc; ++round) {
+                Derived nd = best_d;
+                bool changed = false;
+                for (size_t r = 0; r < R; ++r) {
+                    const long long nt = (long long)best_d.reps[r].P.ntx * best_d.reps[r].P.nty;
+                    if ((long long)ovf[r] * 50 > nt && pos[r] + 1 < ladder[r].size()) {
+                        apply_tiling(nd.reps[r], ladder[r][pos[r] + 1]);
+                        changed = true;
+                    }
+                }
+                if (!changed) break;
+                assign_offsets(&nd);
+                if (nd.tiles > h->d.tiles_alloc) break;
+                std::vector<int> ovf2;
+                rc = trial(nd, best_order, &ms, &ovf2);
+                if (rc || !(ms < best)) break;
+                best = ms;
+                for (size_t r = 0; r < R; ++r)
+                    if (nd.reps[r].P.tile_x != best_d.reps[r].P.tile_x ||
+                        nd.reps[r].P.tile_y != best_d.reps[r].P.tile_y)
+                        ++pos[r];
+                best_d = nd;
+                ovf = ovf2;
+            }
         }
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);

@@ -255,7 +255,7 @@ def test_batch_error_paths(dpd):
     with pytest.raises(dpd.DPDError):
         b.set_schedule(9, 4, 0)
     with pytest.raises(dpd.DPDError):
-        b.set_schedule(2, 2, 0)  # more tiles than the workspace holds
+        b.set_schedule(1, 1, 0)  # more tiles than the workspace holds
     with pytest.raises(dpd.DPDError):
         b.autotune(4)  # no state yet
     b.close()
