@@ -11,8 +11,9 @@ Gamma in {1, 4, 8} with Gamma_s = 0 (pair friction only).
 Protocol (Sec. 5): a relaxation from the random start, then snapshots every
 2 x 10^4 steps.  After the first 2 x 10^4 relaxation steps the tile schedule
 is tuned on the state reached (clusters have formed by then, and the tiles of
-the dense replicas overflow the default capacities); the trajectories are
-bitwise independent of the schedule, so only the run time changes.  Per snapshot and replica:
+the dense replicas overflow the default capacities), and tuned again every
+2 x 10^5 relaxation steps as the clusters grow; the trajectories are bitwise
+independent of the schedule, so only the run time changes.  Per snapshot and replica:
   - u_M on a 128 x 128 grid with overlapping windows of width
     eps = L sqrt(N_f / N), N_f = 10 agents per window on average (Eq. 5.10),
     particle velocities, binned once per replica with its own eps;
@@ -69,16 +70,17 @@ def run(device, warm: int, steps: int, every: int, replicas=None, log=print, tun
     sim.set_state(torch.from_numpy(x).to(device), torch.from_numpy(v).to(device), 0)
     sim.set_graph_chunk(100)
     t0 = time.perf_counter()
-    schedule = None
+    schedule = []
     for w0 in range(0, warm, 20000):
-        sim.step(min(20000, warm - w0))
+        done = min(w0 + 20000, warm)
+        sim.step(done - w0)
         sim.sync()
-        log(f"relaxation: {min(w0 + 20000, warm)} of {warm} steps, {time.perf_counter() - t0:.1f} s")
-        if tune and w0 == 0:
+        log(f"relaxation: {done} of {warm} steps, {time.perf_counter() - t0:.1f} s")
+        if tune and (w0 == 0 or done % 200000 == 0):
             tx, ty, order, ms = sim.autotune(50)
-            schedule = dict(replica0_tile=[tx, ty], order=order, trial_ms_per_step=ms,
-                            after_steps=min(20000, warm))
-            log(f"schedule tuned on the relaxed state: replica 0 tile {tx} x {ty}, order {order}, "
+            schedule.append(dict(replica0_tile=[tx, ty], order=order, trial_ms_per_step=ms,
+                                 after_steps=done))
+            log(f"schedule tuned after {done} steps: replica 0 tile {tx} x {ty}, order {order}, "
                 f"{ms:.4f} ms/step in the trials")
     R = len(cfgs)
     eps = [c["L"] * math.sqrt(N_F / c["n_agents"]) for c in cfgs]

@@ -228,6 +228,40 @@ def test_autotune_keeps_state(dpd, batch):
     t.close()
 
 
+def test_autotune_clustered_replica_keeps_state(dpd):
+    # a batch whose first replica is one dense cluster (most of its tiles go to
+    # the overflow kernel, so the tuner's per-replica refinement has replicas
+    # to move) next to a uniform one: whatever tiles the tuner gives each
+    # replica, the state comes back exactly and later steps match an untuned
+    # run bit for bit
+    cfgs = [dict(C1, n_agents=1200, L=40.0, seed=41), dict(C1, n_agents=800, L=40.0, seed=42)]
+    states = [inputs.initial_state(cfgs[0], kind="clustered", thermal=True),
+              inputs.initial_state(cfgs[1], thermal=True)]
+    x, v = concat(states)
+    ref = dpd.Sim(cfgs, device=DEV)
+    ref.set_state(dev(x), dev(v), 0)
+    ref.step(6)
+    t = dpd.Sim(cfgs, device=DEV)
+    t.set_state(dev(x), dev(v), 0)
+    t.step(6)
+    tx, ty, order, ms = t.autotune(6)
+    print(f"autotune (clustered replica 0): tile {tx} x {ty}, order {order}, {ms:.4f} ms/step")
+    assert 1 <= tx <= 8 and 1 <= ty <= 8 and ms > 0
+    a, b2 = ref.get_state(), t.get_state()
+    assert a[3] == b2[3] == 6
+    for k in range(3):
+        assert (host(a[k]) == host(b2[k])).all()
+    for u, w in zip(ref.cells(), t.cells()):
+        assert (host(u) == host(w)).all()
+    ref.step(14)
+    t.step(14)
+    a, b2 = ref.get_state(), t.get_state()
+    for k in range(3):
+        assert (host(a[k]) == host(b2[k])).all()
+    ref.close()
+    t.close()
+
+
 def test_sweep_workload_runs(dpd):
     # the 64-replica sweep, briefly: every replica stays finite and keeps the
     # momentum balance of its own friction (Stokes decay only: no propulsion)
