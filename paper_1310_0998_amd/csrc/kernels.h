@@ -1353,12 +1353,17 @@ __global__ void k_pos_of_id(int N, const int* __restrict__ id, const DevParams* 
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
         int base = 0;
         if (reps) {
+            // a wavefront's lanes hold consecutive indices: bisect once for the
+            // first active lane (uniform, so in scalar registers), then each
+            // lane steps on past replicas that end before its own index
+            const int i0 = __builtin_amdgcn_readfirstlane(i);
             int lo = 0, hi = R - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (reps[mid].pbase <= i) lo = mid;
+                if (reps[mid].pbase <= i0) lo = mid;
                 else hi = mid - 1;
             }
+            while (lo + 1 < R && reps[lo + 1].pbase <= i) ++lo;
             base = reps[lo].pbase;
         }
         pos[base + id[i]] = i;

@@ -522,10 +522,13 @@ def test_far_bond_partner_by_id(dpd):
     # the paper's geometry: the bond (l = 1) reaches beyond the 3 x 3 stencil
     # of r_c-wide cells (r_c = 0.5), so the partner is read by id.  Forces match
     # the oracle for a random state (fast kernel) and for a dense cluster (the
-    # overflow kernel's paths), and a batch of both steps bitwise like two
-    # single handles
+    # overflow kernel's paths), and a batch of them steps bitwise like single
+    # handles.  The replicas' sizes (1606, 22 and 2400 particles) put replica
+    # boundaries inside wavefronts, two of them inside one, for the map from
+    # input index to replica that the partner lookup is built with
     base = dict(C1, r_c=0.5, bond_l=1.0, A=1.5, kT=0.05, dt=0.003, L=40.0)
-    cases = [(dict(base, n_agents=800, seed=31), "random"), (dict(base, n_agents=1200, seed=32), "clustered")]
+    cases = [(dict(base, n_agents=803, seed=31), "random"), (dict(base, n_agents=11, seed=33), "random"),
+             (dict(base, n_agents=1200, seed=32), "clustered")]
     singles = []
     for cfg, kind in cases:
         x, v = inputs.initial_state(cfg, kind=kind, thermal=True)
@@ -542,10 +545,12 @@ def test_far_bond_partner_by_id(dpd):
     b.set_state(dev(np.concatenate([s_[0] for s_ in states])), dev(np.concatenate([s_[1] for s_ in states])), 4)
     b.step(40)
     got = [host(t) for t in b.get_state()[:3]]
-    n0 = 2 * cases[0][0]["n_agents"]
-    for q, sl in enumerate((slice(0, n0), slice(n0, None))):
+    o = 0
+    for q, (c, _) in enumerate(cases):
+        n = 2 * c["n_agents"]
         for u, w in zip(got, singles[q]):
-            assert (u[sl] == w).all()
+            assert (u[o:o + n] == w).all(), q
+        o += n
     b.close()
 
 
