@@ -43,7 +43,7 @@ struct Layout {
     size_t off_count2, off_xref, off_rec, off_flags;  // second counter array; Verlet skin
     size_t off_reps, off_tile_rep, off_stepb;         // batch tables, graph step
     size_t off_Tx, off_Tv, off_TF, off_Tid;           // state saved by the tuner
-    size_t off_posid;                                 // input index by id (far bonds)
+    size_t off_posid, off_posid2;                     // input index by id (far bonds), per buffer
     size_t total;
 };
 
@@ -339,6 +339,7 @@ int derive(const dpd_params* p, int n_rep, Derived* d, std::string* err) {
         L.off_Tid = take(N * 4);
     }
     L.off_posid = d->far_bond ? take(N * 4) : 0;
+    L.off_posid2 = d->far_bond ? take(N * 4) : 0;
     L.total = o;
     return DPD_OK;
 }
@@ -377,7 +378,9 @@ struct dpd_handle {
     DevParams* reps_dev;  // parameters of every replica (batch)
     int* tile_rep;        // replica of every tile (batch)
     unsigned* stepb;      // step before a replayed chunk
-    int* posid;           // input index by id (far bonds), or null
+    int* posid;           // input index by id (far bonds), or null: for buffers A and the
+                          // inputs of the calls that bin S
+    int* posid2;          // the same for buffers B
     int tile_order;       // 0: bands of tiles per XCD; 1: launch order
     int64_t step;
     bool have_state;
@@ -454,7 +457,7 @@ int upload_tables(dpd_handle* h) {
 // id here (only for the state loaded with a given force, which no pair kernel
 // passes through before it is stored).
 int bin_from_counts(dpd_handle* h, int* count, bool clear, const int* rebuild, int* moved_clear,
-                    const int* id_of_input, const int* ids_in) {
+                    const int* id_of_input, const int* ids_in, int* pos) {
     const int G = h->d.n_scan_blocks;
     const int C = (int)h->d.cells, N = (int)h->d.N;
     auto scan = scan_rows(C) == 1 ? k_scan<1> : k_scan<4>;
@@ -467,10 +470,10 @@ int bin_from_counts(dpd_handle* h, int* count, bool clear, const int* rebuild, i
     if (id_of_input)
         hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(C)), dim3(kBlock), 0, h->stream, C,
                            (const int*)h->cs, h->src, id_of_input);
-    if (h->posid)  // bonds beyond the stencil: where every id sits in the input
+    if (pos)  // bonds beyond the stencil: where every id sits in the input
         hipLaunchKernelGGL(k_pos_of_id, dim3(std::min(grid_for(N), 4096)), dim3(kBlock), 0, h->stream,
                            N, ids_in, h->R > 1 ? (const DevParams*)h->reps_dev : nullptr, h->R,
-                           h->posid, rebuild);
+                           pos, rebuild);
     LAUNCHCHK(h);
     return DPD_OK;
 }
@@ -489,6 +492,14 @@ int* counter_of(dpd_handle* h, int64_t s) {
 // Whenever no step is prepared both arrays are zero.
 int* counter_of_buffer(dpd_handle* h, const float2* x) {
     return x == h->Ax ? h->count : h->count2;
+}
+
+// Far bonds: the id -> index map of stepping buffers A or B (null without far
+// bonds).  Whatever writes one of these buffers on the stepping path
+// (k_kick_drift, the pair kernels) writes its map too, so the stepping
+// binnings build none.
+int* pos_of_buffer(dpd_handle* h, const float2* x) {
+    return x == h->Ax ? h->posid : h->posid2;
 }
 
 template <int MODE, bool SKIN, bool BATCH>
@@ -533,7 +544,7 @@ int launch_pair(dpd_handle* h, int mode, const PairArgs& a, bool reduce) {
     b.tile_rep = h->tile_rep;
     b.nt_total = (int)h->d.tiles;
     b.tile_order = h->tile_order;
-    b.pos_of_id = h->posid;
+    if (!b.pos_of_id) b.pos_of_id = h->posid;
     const int red = reduce ? 1 : 0;
     const bool batch = h->R > 1;
     // the Verlet-skin variant of the kernel only where a skin is set (a force
@@ -642,7 +653,8 @@ int kick_drift(dpd_handle* h) {
         hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(P.N)), dim3(kBlock), 0, h->stream, P,
                            (const float2*)(h->Sx + pb), (const float2*)(h->Sv + pb),
                            (const float2*)(h->SF + pb), (const int*)(h->Sid + pb), h->Ax + pb,
-                           h->Au + pb, h->Aid + pb, h->key + pb, h->rank + pb, count, h->status);
+                           h->Au + pb, h->Aid + pb, h->key + pb, h->rank + pb, count, h->status,
+                           h->posid);
     }
     if (h->d.skin)
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, h->stream, h->flags + (h->step & 1),
@@ -682,6 +694,8 @@ PairArgs step_args(dpd_handle* h, int64_t k, bool last, float2* inx, float2* inu
     } else {
         a.count = counter_of_buffer(h, outx);
         a.count_clear = counter_of_buffer(h, inx);
+        a.pos_of_id = pos_of_buffer(h, inx);
+        a.pos_out = pos_of_buffer(h, outx);
     }
     if (last) {
         a.xout = h->Sx;
@@ -716,7 +730,7 @@ int run_steps(dpd_handle* h, int64_t n, int reduce_every, double* pk_out, int64_
         const int* rebuild = h->d.skin ? h->flags + ((s - 1) & 1) : nullptr;
         int* moved = h->d.skin ? h->flags + (s & 1) : nullptr;
         int* counts = h->d.skin ? counter_of(h, s - 1) : counter_of_buffer(h, inx);
-        int rc = bin_from_counts(h, counts, h->d.skin, rebuild, moved, nullptr, inid);
+        int rc = bin_from_counts(h, counts, h->d.skin, rebuild, moved, nullptr, inid, nullptr);
         if (rc) return rc;
         const bool last = (k == n);
         const bool red = pk_out && reduce_every > 0 && ((k0 + k) % reduce_every == 0);
@@ -758,7 +772,7 @@ int capture_chunk(dpd_handle* h, int K, bool reduce_last, hipGraphExec_t* out) {
     float2 *inx = h->Ax, *inu = h->Au, *outx = h->Bx, *outu = h->Bu;
     int *inid = h->Aid, *outid = h->Bid;
     for (int k = 1; k <= K && rc == DPD_OK; ++k) {
-        rc = bin_from_counts(h, counter_of_buffer(h, inx), false, nullptr, nullptr, nullptr, inid);
+        rc = bin_from_counts(h, counter_of_buffer(h, inx), false, nullptr, nullptr, nullptr, inid, nullptr);
         if (rc) break;
         const bool last = (k == K);
         PairArgs a = step_args(h, k, last, inx, inu, inid, outx, outu, outid);
@@ -811,7 +825,7 @@ int rebin_stored(dpd_handle* h) {
                            (const float2*)h->Sx + pb, h->key + pb, h->rank + pb, h->count);
     }
     LAUNCHCHK(h);
-    return bin_from_counts(h, h->count, true, nullptr, nullptr, nullptr, h->Sid);
+    return bin_from_counts(h, h->count, true, nullptr, nullptr, nullptr, h->Sid, h->posid);
 }
 
 // The handle's replicas under schedule s (tile sides clamped per replica).
@@ -948,6 +962,7 @@ int dpd_create_batch(const dpd_params* p, int32_t n_rep, void* workspace, size_t
         h->TF = d.skin ? nullptr : (float2*)(w + L.off_TF);
         h->Tid = d.skin ? nullptr : (int*)(w + L.off_Tid);
         h->posid = d.far_bond ? (int*)(w + L.off_posid) : nullptr;
+        h->posid2 = d.far_bond ? (int*)(w + L.off_posid2) : nullptr;
         h->tile_order = 0;
         h->step = 0;
         h->have_state = false;
@@ -1029,7 +1044,7 @@ int dpd_set_state(dpd_handle* h, const float* x, const float* v, int64_t step, c
                                h->Aid + pb, h->key + pb, h->rank + pb, h->count, h->status);
         }
         LAUNCHCHK(h);
-        int rc = bin_from_counts(h, h->count, true, nullptr, nullptr, F ? h->Aid : nullptr, h->Aid);
+        int rc = bin_from_counts(h, h->count, true, nullptr, nullptr, F ? h->Aid : nullptr, h->Aid, h->posid);
         if (rc) return rc;
         if (F) {
             for (const Rep& r : h->d.reps) {
@@ -1140,7 +1155,7 @@ int dpd_forces(dpd_handle* h, float* F_out) {
                                (const float2*)h->Sx + pb, h->key + pb, h->rank + pb, h->count);
         }
         LAUNCHCHK(h);
-        int rc = bin_from_counts(h, h->count, true, nullptr, nullptr, nullptr, h->Sid);
+        int rc = bin_from_counts(h, h->count, true, nullptr, nullptr, nullptr, h->Sid, h->posid);
         if (rc) return rc;
         PairArgs a = {};
         a.cs = h->cs;

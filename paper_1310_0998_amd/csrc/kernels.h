@@ -90,6 +90,9 @@ struct PairArgs {
     // bonds longer than the cell stencil reaches (far_bond): index in the input
     // buffers of the particle with id i of the replica at pbase, at pos_of_id[pbase + i]
     const int* pos_of_id;
+    // STEP, and FINAL with pxout: the same map for the buffers this launch
+    // writes (the next step's input), or null
+    int* pos_out;
 };
 
 // ---- small helpers ----------------------------------------------------------
@@ -313,6 +316,7 @@ __device__ __forceinline__ void finish_particle(const DevParams& P, const PairAr
             a.pidout[g] = idi;
             a.keyout[g] = key;
             a.rankout[g] = atomicAdd(&a.count[key], 1);
+            if (a.pos_out && (unsigned)idi < (unsigned)P.N) a.pos_out[P.pbase + idi] = g;
             bad |= !finite2(xn) || !finite2(un);
             if (SKIN && a.moved && moved_too_far(P, a, g, xi, xn, rebuilt)) atomicOr(a.moved, 1);
         }
@@ -328,6 +332,7 @@ __device__ __forceinline__ void finish_particle(const DevParams& P, const PairAr
     a.idout[g] = idi;
     a.keyout[g] = key;
     a.rankout[g] = rank;
+    if (a.pos_out && (unsigned)idi < (unsigned)P.N) a.pos_out[P.pbase + idi] = g;
     if (!finite2(xn) || !finite2(un)) atomicOr(a.status, kStatusNonFinite);
     if (SKIN && a.moved && moved_too_far(P, a, g, xi, xn, rebuilt)) atomicOr(a.moved, 1);
 }
@@ -1439,16 +1444,20 @@ __global__ void k_gather_state(int N, const int* __restrict__ src, const float2*
 __global__ void k_kick_drift(DevParams P, const float2* __restrict__ x, const float2* __restrict__ v,
                              const float2* __restrict__ F, const int* __restrict__ id, float2* xo,
                              float2* uo, int* ido, int* key, int* rank, int* count,
-                             unsigned* status) {
+                             unsigned* status, int* pos) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= P.N) return;
     const float2 f = F[g], vv = v[g], xx = x[g];
     const float2 u = make_float2(fmaf(P.h, f.x, vv.x), fmaf(P.h, f.y, vv.y));
     const float2 xn = make_float2(drift_wrap(xx.x, u.x, P), drift_wrap(xx.y, u.y, P));
     const int k = cell_key(xn, P) + P.cbase;
+    const int idg = id[g];
     xo[g] = xn;
     uo[g] = u;
-    ido[g] = id[g];
+    ido[g] = idg;
+    // far bonds: the id -> index map of the buffers written (indices of the
+    // whole batch)
+    if (pos && (unsigned)idg < (unsigned)P.N) pos[P.pbase + idg] = P.pbase + g;
     key[g] = k;
     rank[g] = atomicAdd(&count[k], 1);
     if (!finite2(xn) || !finite2(u)) atomicOr(status, kStatusNonFinite);
