@@ -933,6 +933,8 @@ __global__ __launch_bounds__(kWave) void k_pair(DevParams P, PairArgs a, int red
 // some lanes down the wrong side of the test.  The velocity sums are always
 // accumulated (the caller decides whether to store them).
 constexpr int kOvfWindow = 2048;
+// Candidates (and cell members) the global path loads at a time per lane.
+constexpr int kGlobBatch = 4;
 template <int MODE, bool REBUILT>
 __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int cy0, int tw,
                             int th, double rv[3]) {
@@ -978,10 +980,18 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
             }
             const int idi = a.idin[p];
             int r = 0;  // members of the cell with a smaller id (ids are distinct)
-            for (int g1 = b; g1 < e; ++g1) {
-                int p1 = REBUILT ? a.src[g1] : g1;
-                if ((unsigned)(p1 - P.pbase) >= (unsigned)P.N) p1 = P.pbase;
-                r += (a.idin[p1] < idi) ? 1 : 0;
+            for (int g1 = b; g1 < e; g1 += kGlobBatch) {
+                // a batch of members at a time: their loads are independent
+                int pv[kGlobBatch];
+#pragma unroll
+                for (int k = 0; k < kGlobBatch; ++k) {
+                    int p1 = g1 + k < e ? (REBUILT ? a.src[g1 + k] : g1 + k) : P.pbase;
+                    if ((unsigned)(p1 - P.pbase) >= (unsigned)P.N) p1 = P.pbase;
+                    pv[k] = p1;
+                }
+#pragma unroll
+                for (int k = 0; k < kGlobBatch; ++k)
+                    r += (g1 + k < e && a.idin[pv[k]] < idi) ? 1 : 0;
             }
             const int tc = s_pre[lo] + r;
             if (tc >= w0 && tc < w1) s_slot[tc - w0] = g;
@@ -1006,27 +1016,45 @@ __device__ void tile_global(const DevParams& P, const PairArgs& a, int cx0, int 
                 for (int ox = -1; ox <= 1; ++ox) {
                     const int c2 = wrap_cell(gy + oy, nc) * nc + wrap_cell(gx + ox, nc);
                     const int b2 = a.cs[c2], e2 = a.cs[c2 + 1];
-                    for (int g2 = b2; g2 < e2; ++g2) {
-                        if (g2 == g) continue;
-                        int q = REBUILT ? a.src[g2] : g2;
-                        if ((unsigned)(q - P.pbase) >= (unsigned)P.N) q = P.pbase;
-                        const int idj = a.idin[q];
-                        const float2 xj = a.xin[q];
-                        if (idj == pid) {
-                            found = true;
-                            xpart = xj;
-                            continue;
+                    for (int g2 = b2; g2 < e2; g2 += kGlobBatch) {
+                        // a batch of candidates at a time, in slot order: the
+                        // loads of a batch are independent and overlap (the
+                        // fixed-point sums do not depend on the order anyway)
+                        int qv[kGlobBatch], idv[kGlobBatch];
+                        float2 xv[kGlobBatch], uv[kGlobBatch];
+#pragma unroll
+                        for (int k = 0; k < kGlobBatch; ++k) {
+                            int q = g2 + k < e2 ? (REBUILT ? a.src[g2 + k] : g2 + k) : P.pbase;
+                            if ((unsigned)(q - P.pbase) >= (unsigned)P.N) q = P.pbase;
+                            qv[k] = q;
                         }
-                        const float dx = minimg_sub(xi.x, xj.x, P);
-                        const float dy = minimg_sub(xi.y, xj.y, P);
-                        const float gap = cutoff_gap(P, dx, dy);
-                        const float r2 = fmaf(dx, dx, dy * dy);
-                        if (interacts(gap, r2)) {
-                            float fx = 0.f, fy = 0.f;
-                            add_pair_force(P, dx, dy, gap, r2, ui, a.uin[q], idi, idj, a.step, fx, fy);
-                            bad |= !(__builtin_isfinite(fx) && __builtin_isfinite(fy));
-                            qx += to_fixed(fx);
-                            qy += to_fixed(fy);
+#pragma unroll
+                        for (int k = 0; k < kGlobBatch; ++k) {
+                            idv[k] = a.idin[qv[k]];
+                            xv[k] = a.xin[qv[k]];
+                            uv[k] = a.uin[qv[k]];
+                        }
+#pragma unroll
+                        for (int k = 0; k < kGlobBatch; ++k) {
+                            if (g2 + k >= e2 || g2 + k == g) continue;
+                            const int idj = idv[k];
+                            const float2 xj = xv[k];
+                            if (idj == pid) {
+                                found = true;
+                                xpart = xj;
+                                continue;
+                            }
+                            const float dx = minimg_sub(xi.x, xj.x, P);
+                            const float dy = minimg_sub(xi.y, xj.y, P);
+                            const float gap = cutoff_gap(P, dx, dy);
+                            const float r2 = fmaf(dx, dx, dy * dy);
+                            if (interacts(gap, r2)) {
+                                float fx = 0.f, fy = 0.f;
+                                add_pair_force(P, dx, dy, gap, r2, ui, uv[k], idi, idj, a.step, fx, fy);
+                                bad |= !(__builtin_isfinite(fx) && __builtin_isfinite(fy));
+                                qx += to_fixed(fx);
+                                qy += to_fixed(fy);
+                            }
                         }
                     }
                 }
