@@ -455,7 +455,10 @@ int upload_tables(dpd_handle* h) {
 // cell the slots are in arrival order; the pair kernel places each cell's
 // members by id itself.  With id_of_input != NULL every cell is also ordered by
 // id here (only for the state loaded with a given force, which no pair kernel
-// passes through before it is stored).
+// passes through before it is stored).  With pos != NULL (far bonds) the map
+// from id to input index of the binned buffers is written there; the stepping
+// path passes NULL, since its buffers carry maps written by the kernels that
+// wrote them (pos_of_buffer).
 int bin_from_counts(dpd_handle* h, int* count, bool clear, const int* rebuild, int* moved_clear,
                     const int* id_of_input, const int* ids_in, int* pos) {
     const int G = h->d.n_scan_blocks;
