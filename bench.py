@@ -409,11 +409,11 @@ def _finite(o):
 def run_closure(args):
     """The learned closure: DPD-generated training pairs (independent replicas
     of every condition), training on the GPU, noise calibrated against the
-    judged condition's training fields, then an ensemble of closure rollouts
+    evaluated condition's training fields, then an ensemble of closure rollouts
     against an independent ensemble of DPD runs, timed, with the
     energy-spectrum, correlation-length and mode-autocorrelation errors.  The
     zero network (persistence, u(t + 50) = u(t)) goes through the same
-    calibration and judge as the control of what the network adds."""
+    calibration and evaluation as the control of what the network adds."""
     import torch
 
     from paper_1310_0998_amd import closure, closure_train as ct, inputs
@@ -439,13 +439,13 @@ def run_closure(args):
     _, _, res = ct.evaluate(net, runs, train_idx, dev)
     log(f"held-out one-step MSE: network {mse_net:.5e}, persistence {mse_per:.5e}; "
         f"training residual rms {res[0]:.4f} {res[1]:.4f}")
-    r_judge = 4  # zeta = 0.5, F_p = 1
-    idx_r = [q for q in train_idx if runs[q[0]]["run"] == r_judge]
-    cond = torch.tensor(ct.runs_cond(r_judge), dtype=torch.float32, device=dev)
-    # calibration: rollouts from the judged condition's training fields, against
+    r_eval = 4  # zeta = 0.5, F_p = 1
+    idx_r = [q for q in train_idx if runs[q[0]]["run"] == r_eval]
+    cond = torch.tensor(ct.runs_cond(r_eval), dtype=torch.float32, device=dev)
+    # calibration: rollouts from the evaluated condition's training fields, against
     # the spectrum of those fields (no DPD beyond the training data)
-    target = ct.condition_fields(runs, r_judge)
-    cstart = ct.training_starts(runs, r_judge, E)
+    target = ct.condition_fields(runs, r_eval)
+    cstart = ct.training_starts(runs, r_eval, E)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     filters = {}
@@ -455,13 +455,13 @@ def run_closure(args):
         filters[name] = (h0, h, cal)
     torch.cuda.synchronize()
     t_cal = time.perf_counter() - t0
-    jstart, jfields, t_dpd = ct.ensemble(r_judge, E, args.closure_warm, T, 2000, dev, log=log)
+    jstart, jfields, t_dpd = ct.ensemble(r_eval, E, args.closure_warm, T, 2000, dev, log=log)
     models = {"calibrated": (net, (1.0, 1.0), filters["network"][1]),
               "residual": (net, (1.0, 1.0), filters["network"][0]),
               "white": (net, (float(res[0]), float(res[1])), None),
               "zero_calibrated": (zero, (1.0, 1.0), filters["zero"][1]),
               "zero_no_noise": (zero, (0.0, 0.0), None)}
-    j = ct.judge(models, r_judge, jstart, jfields, t_dpd, dev, log=log)
+    j = ct.evaluate(models, r_eval, jstart, jfields, t_dpd, dev, log=log)
     del jfields
     jm = j["models"]["calibrated"]
     jz = j["models"]["zero_calibrated"]
@@ -486,11 +486,11 @@ def run_closure(args):
             "workload": "closure: 200k particles (100k dimers, L=447), gamma=4.5, zeta {0,0.5} x F_p "
                         f"{{0.5,1,2}}, {ct.REPLICAS} independent replicas per condition; 64x64 binned "
                         "velocity every 10 steps; pairs 50 steps apart; 4 conv layers, 32 channels, 3x3 "
-                        f"periodic; judged at zeta=0.5, F_p=1: {E} independent DPD replicas (one batch, "
+                        f"periodic; evaluated at zeta=0.5, F_p=1: {E} independent DPD replicas (one batch, "
                         f"own seeds) x {T * ct.INTERVAL} steps against {E} batched closure rollouts x {T} "
                         "steps from the same fields; rollout noise filtered to the training residual's "
                         "spectrum, scaled per shell until a rollout reproduces the spectrum of the "
-                        "judged condition's training fields",
+                        "evaluated condition's training fields",
             "pairs_train": len(train_idx),
             "pairs_test": len(test_idx),
             "epochs": args.closure_epochs,
@@ -660,11 +660,11 @@ def main():
                     help="skip the one-after-another runs (workload sweep64)")
     ap.add_argument("--closure-epochs", type=int, default=40)
     ap.add_argument("--closure-ensemble", type=int, default=32,
-                    help="independent replicas of the judged run (and of its calibration ensemble)")
+                    help="independent replicas of the evaluated run (and of its calibration ensemble)")
     ap.add_argument("--closure-warm", type=int, default=4000,
                     help="DPD warm-up steps of each ensemble before its fields are taken")
     ap.add_argument("--closure-steps", type=int, default=2000,
-                    help="closure steps of the judged rollout (x50 DPD steps)")
+                    help="closure steps of the evaluated rollout (x50 DPD steps)")
     ap.add_argument("--closure-cal-steps", type=int, default=1000,
                     help="closure steps of each calibration rollout")
     ap.add_argument("--rollout-steps", type=int, default=200,
