@@ -461,7 +461,7 @@ def run_closure(args):
               "white": (net, (float(res[0]), float(res[1])), None),
               "zero_calibrated": (zero, (1.0, 1.0), filters["zero"][1]),
               "zero_no_noise": (zero, (0.0, 0.0), None)}
-    j = ct.evaluate(models, r_eval, jstart, jfields, t_dpd, dev, log=log)
+    j = ct.evaluate_rollouts(models, r_eval, jstart, jfields, t_dpd, dev, log=log)
     del jfields
     jm = j["models"]["calibrated"]
     jz = j["models"]["zero_calibrated"]
