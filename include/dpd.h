@@ -249,12 +249,14 @@ int dpd_get_schedule(dpd_handle* h, int32_t* tile_x, int32_t* tile_y, int32_t* t
  * over the tile kernel's LDS capacities (dense clusters) then move, round by
  * round while the step gets faster, to finer tiles (down to the default tile
  * scaled by 0.3), so replicas can end with tiles of different scales; the
- * batch workspace holds those tilings.  The choice holds for states like the one timed: cell occupancy
- * changes along a run (a random start relaxes within a few hundred steps, and
- * propelled agents cluster), so tune on a state of the kind the run will see.
- * Outputs (host, any may be NULL): the chosen schedule and its time per step
- * in ms.  Synchronises the stream.  Not with a Verlet skin.
- * Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP, device flags. */
+ * batch workspace holds those tilings.  The choice holds for states like the
+ * one timed: cell occupancy changes along a run (a random start relaxes within
+ * a few hundred steps, and propelled agents cluster), so tune on a state of
+ * the kind the run will see, and again as it changes.
+ * Outputs (host, any may be NULL): replica 0's tile and the tile order of the
+ * chosen schedule, and its time per step in ms.  Synchronises the stream.
+ * Not with a Verlet skin.  Errors: DPD_ESTATE, DPD_EINVAL, DPD_EHIP, device
+ * flags; after DPD_EHIP the state and schedule are those of the failed trial. */
 int dpd_autotune(dpd_handle* h, int32_t trial_steps, int32_t* tile_x, int32_t* tile_y,
                  int32_t* tile_order, double* best_ms);
 
